@@ -1,0 +1,32 @@
+"""Plain FP64 CPU oracle for the HGKS time stage of Pan & Xu,
+"High-order gas-kinetic scheme with three-dimensional WENO reconstruction for
+the Euler and Navier-Stokes solutions" (arXiv:1909.01580).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this package: only the tests, the smoke check and the CPU-baseline leg of
+the benchmark use it.  It shares no code with the HIP library; the two meet
+only through arrays produced by the seeded input generators.
+
+The oracle follows the paper step by step, in NumPy FP64, vectorised over
+cells and face Gauss points:
+
+* ``geometry``  trilinear cells, 2x2x2 Gauss moments, bilinear faces
+                (Sec. 2 last part; Sec. 3, Eqs. (10)-(11)).
+* ``weno``      WENO-AO reconstruction: big stencil, 24 sub-stencils,
+                least squares, smoothness indicators, nonlinear weights,
+                positivity fallback (Sec. 2, Eqs. (1)-(5); Sec. 4 limiter).
+* ``gks``       BGK gas-kinetic flux at one Gauss point, generic moment
+                algebra and 5x5 solves (Sec. 3, Eqs. (7)-(8), (13)-(16)).
+* ``scheme``    finite-volume operator, two-stage fourth-order stepping,
+                moving-mesh update, time step and totals
+                (Sec. 3, Eq. (9) and Remark 2).
+
+Array convention inside the oracle: spatial axes are ordered (i, j, k) =
+(x, y, z).  The public helpers in ``scheme`` accept and return states in the
+library layout ``[5][nz][ny][nx]`` and transpose at the edge.
+"""
+
+from .scheme import (  # noqa: F401
+    Params, Problem, uniform_problem, vertex_problem, residual, step,
+    s2o4, max_dt, totals, gp_states, face_fluxes,
+)

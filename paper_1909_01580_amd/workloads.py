@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs shaped like the paper's 3D tests.
+
+This module holds input generation only: initial cell averages, vertex
+positions of the deforming meshes, and the batch of random smooth problems.
+It contains none of the scheme's arithmetic and is the only code that the
+library harness and the test oracle both use.
+
+Cell averages of smooth initial data use a 3x3x3 Gauss-Legendre rule on
+each cell (through the trilinear cell map on deformed grids); the
+discontinuous explosion is sampled at cell centres.  The advection data
+use the exact cell average of the sine wave on cubes.
+"""
+
+import numpy as np
+
+GAMMA = 1.4
+
+_GL3_X = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)]) / 2.0   # nodes on [-1/2, 1/2]
+_GL3_W = np.array([5.0, 8.0, 5.0]) / 18.0
+
+
+def conservative(rho, u, v, w, p, gamma=GAMMA):
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+def _centres(n, origin, length):
+    return [origin[d] + (np.arange(n[d]) + 0.5) * (length[d] / n[d]) for d in range(3)]
+
+
+def _box_average(n, origin, length, point_fn):
+    """3x3x3 Gauss average over each box cell of point_fn(x, y, z) -> (5, ...).
+    Returns the library layout [5][nz][ny][nx]."""
+    h = [length[d] / n[d] for d in range(3)]
+    cx, cy, cz = _centres(n, origin, length)
+    acc = 0.0
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                x = cx + _GL3_X[a] * h[0]
+                y = cy + _GL3_X[b] * h[1]
+                z = cz + _GL3_X[c] * h[2]
+                Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+                acc = acc + _GL3_W[a] * _GL3_W[b] * _GL3_W[c] * point_fn(X, Y, Z)
+    return np.ascontiguousarray(acc)
+
+
+# ------------------------------------------------------------ advection
+def advection_exact(n, t=0.0, length=2.0, gamma=GAMMA):
+    """Density wave carried by the uniform stream u = v = w = 1, p = 1 on
+    [0, length]^3: rho = 1 + 0.2 sin(pi (x+y+z-3t)) (the wave moves with the
+    stream; at t = 2 this is the initial field again).  Exact cell averages
+    on the uniform cubic grid."""
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    h = [length / n[d] for d in range(3)]
+    cx, cy, cz = _centres(n, (0.0, 0.0, 0.0), (length,) * 3)
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    s = 1.0
+    for d in range(3):
+        arg = np.pi * h[d] / 2.0
+        s *= np.sin(arg) / arg
+    rho = 1.0 + 0.2 * s * np.sin(np.pi * (X + Y + Z - 3.0 * t))
+    one = np.ones_like(rho)
+    return np.ascontiguousarray(conservative(rho, one, one, one, one, gamma))
+
+
+# ------------------------------------------------------------ Taylor-Green
+def tgv_point(X, Y, Z, mach=0.1, gamma=GAMMA):
+    """Taylor-Green vortex with rho0 = V0 = L = 1 and uniform temperature."""
+    p0 = 1.0 / (gamma * mach * mach)
+    u = np.sin(X) * np.cos(Y) * np.cos(Z)
+    v = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    w = np.zeros_like(X)
+    p = p0 + (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0) / 16.0
+    rho = p / p0
+    return conservative(rho, u, v, w, p, gamma)
+
+
+def tgv_state(n, mach=0.1, gamma=GAMMA):
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    L = 2.0 * np.pi
+    return _box_average(n, (-np.pi,) * 3, (L,) * 3,
+                        lambda X, Y, Z: tgv_point(X, Y, Z, mach, gamma))
+
+
+TGV_MU = 1.0 / 1600.0
+
+
+# ------------------------------------------------------------ explosion
+def explosion_state(n, radius=0.4, centre=(0.5, 0.5, 0.5), gamma=GAMMA):
+    """Spherical Sod-type explosion on [0,1]^3, sampled at cell centres:
+    inside rho = 1, p = 1; outside rho = 0.125, p = 0.1; at rest."""
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    cx, cy, cz = _centres(n, (0.0,) * 3, (1.0,) * 3)
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    r = np.sqrt((X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2)
+    inside = r < radius
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    zero = np.zeros_like(rho)
+    return np.ascontiguousarray(conservative(rho, zero, zero, zero, p, gamma))
+
+
+# ------------------------------------------------------------ deformed grids
+def sine_mesh_vertices(n, t, amp=0.1, omega=np.pi, length=2.0, static=False):
+    """Vertices x = xi + amp sin(pi xi) sin(pi eta) sin(pi zeta) s(t) (all
+    three components), s(t) = sin(omega t), or 1 for the static non-coplanar
+    mesh.  Periodic grid on [0, length]^3 with n vertices per axis.
+    Library layout [3][nz][ny][nx]."""
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    xi = [np.arange(n[d]) * (length / n[d]) for d in range(3)]
+    Z, Y, X = np.meshgrid(xi[2], xi[1], xi[0], indexing="ij")
+    s = 1.0 if static else np.sin(omega * t)
+    disp = amp * np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z) * s
+    return np.ascontiguousarray(np.stack([X + disp, Y + disp, Z + disp]))
+
+
+def _trilinear_points(verts, period, node):
+    """Physical points and |J| at parametric offsets ``node`` (3,) in every
+    cell of a periodic vertex grid (library layout)."""
+    v = np.transpose(verts, (0, 3, 2, 1))  # (3, i, j, k)
+    n = v.shape[1:]
+    corners = {}
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                arr = np.roll(v, shift=(-a, -b, -c), axis=(1, 2, 3)).copy()
+                for d, bit in enumerate((a, b, c)):
+                    if bit:
+                        last = [slice(None)] * 3
+                        last[d] = n[d] - 1
+                        arr[(d,) + tuple(last)] += period[d]
+                corners[(a, b, c)] = arr
+    xi, eta, zeta = node
+    X = 0.0
+    dX = [0.0, 0.0, 0.0]
+    for (a, b, c), xm in corners.items():
+        sa, sb, sc = (2 * a - 1), (2 * b - 1), (2 * c - 1)
+        fa, fb, fc = 1 + 2 * sa * xi, 1 + 2 * sb * eta, 1 + 2 * sc * zeta
+        X = X + fa * fb * fc / 8.0 * xm
+        dX[0] = dX[0] + 2 * sa * fb * fc / 8.0 * xm
+        dX[1] = dX[1] + 2 * sb * fa * fc / 8.0 * xm
+        dX[2] = dX[2] + 2 * sc * fa * fb / 8.0 * xm
+    J = np.einsum("i...,i...->...", dX[0], np.cross(dX[1], dX[2], axis=0))
+    return X, np.abs(J)
+
+
+def hex_average(verts, period, point_fn):
+    """3x3x3 Gauss cell averages on a periodic hexahedral grid.
+    Returns the library layout [5][nz][ny][nx]."""
+    acc = 0.0
+    vol = 0.0
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                X, J = _trilinear_points(verts, period, (_GL3_X[a], _GL3_X[b], _GL3_X[c]))
+                w = _GL3_W[a] * _GL3_W[b] * _GL3_W[c] * J
+                acc = acc + w * point_fn(X[0], X[1], X[2])
+                vol = vol + w
+    out = acc / vol
+    return np.ascontiguousarray(np.transpose(out, (0, 3, 2, 1)))
+
+
+def advection_point(X, Y, Z, t=0.0, gamma=GAMMA):
+    rho = 1.0 + 0.2 * np.sin(np.pi * (X + Y + Z - 3.0 * t))
+    one = np.ones_like(rho)
+    return conservative(rho, one, one, one, one, gamma)
+
+
+def pulse_point(X, Y, Z, gamma=GAMMA):
+    """Uniform stream (1, 0.5, 0.25), p = 1, with a smooth density pulse
+    centred at (1, 1, 1)."""
+    r2 = (X - 1.0) ** 2 + (Y - 1.0) ** 2 + (Z - 1.0) ** 2
+    rho = 1.0 + 0.2 * np.exp(-r2 / 0.04)
+    one = np.ones_like(rho)
+    return conservative(rho, one, 0.5 * one, 0.25 * one, one, gamma)
+
+
+def uniform_point(X, Y, Z, gamma=GAMMA):
+    one = np.ones_like(X)
+    return conservative(one, one, one, one, one, gamma)
+
+
+# ------------------------------------------------------------ batch
+def batch_problems(seed=190901580, count=48, sizes=(32, 48, 64, 96), h=2 * np.pi / 64,
+                   gamma=GAMMA):
+    """Independent periodic problems of uneven box sizes with random smooth
+    data: four Fourier modes per field with integer wave vectors in
+    {-2..2}^3 (fitted to each box) and random phases; rho = 1 + 0.1 phi_rho,
+    p = (1 + 0.1 phi_p)/gamma, velocity = Ma phi_u with Ma in [0.1, 0.5];
+    even problems inviscid, odd ones viscous with mu = 1/1600.
+    Returns a list of dicts (n, length, mu, state)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(count):
+        n = tuple(int(s) for s in rng.choice(sizes, size=3))
+        length = tuple(n[d] * h for d in range(3))
+        mach = rng.uniform(0.1, 0.5)
+        fields = {}
+        for name in ("rho", "p", "u", "v", "w"):
+            kv = []
+            while len(kv) < 4:
+                k = tuple(int(x) for x in rng.integers(-2, 3, size=3))
+                if k != (0, 0, 0):
+                    kv.append(k)
+            ph = rng.uniform(0.0, 2 * np.pi, size=4)
+            fields[name] = (kv, ph)
+
+        def point(X, Y, Z, fields=fields, length=length, mach=mach):
+            vals = {}
+            for name, (kv, ph) in fields.items():
+                s = 0.0
+                for k, phase in zip(kv, ph):
+                    s = s + np.sin(2 * np.pi * (k[0] * X / length[0] + k[1] * Y / length[1]
+                                                + k[2] * Z / length[2]) + phase)
+                vals[name] = s / 4.0
+            rho = 1.0 + 0.1 * vals["rho"]
+            p = (1.0 + 0.1 * vals["p"]) / gamma
+            return conservative(rho, mach * vals["u"], mach * vals["v"], mach * vals["w"], p, gamma)
+
+        state = _box_average(n, (0.0,) * 3, length, point)
+        out.append({"n": n, "length": length, "mu": 0.0 if g % 2 == 0 else 1.0 / 1600.0,
+                    "mach": mach, "state": state})
+    return out
