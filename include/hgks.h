@@ -1,0 +1,156 @@
+/*
+ * hgks.h - C ABI of the MI355X (gfx950) HGKS time-stage library.
+ *
+ * The library advances cell averages of the five conservative variables
+ * (rho, rho U, rho V, rho W, rho E) of the compressible Euler / Navier-Stokes
+ * equations on a structured hexahedral grid with the high-order gas-kinetic
+ * scheme of Pan & Xu, "High-order gas-kinetic scheme with three-dimensional
+ * WENO reconstruction for the Euler and Navier-Stokes solutions"
+ * (arXiv:1909.01580):
+ *   - third-order WENO-AO reconstruction in every cell (Sec. 2, Eqs. (1)-(5));
+ *   - the BGK gas-kinetic flux at the 2x2 Gauss points of every face
+ *     (Sec. 3, Eqs. (7)-(16)), with the collision time of Sec. 4;
+ *   - the two-stage fourth-order update (Sec. 3, after Eq. (9)), with the
+ *     grid velocity on moving meshes (Sec. 3, Remark 2).
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only; every call returns an hgks_status; no call throws.
+ *   - Pointers named *_dev are device pointers (HIP device memory of the
+ *     current device); pointers named *_host are host pointers.
+ *   - The caller owns every buffer it passes, including the workspace.  The
+ *     library never frees caller memory and allocates no device memory.
+ *   - Device work is enqueued on the stream given in the configuration
+ *     (NULL = the default stream) and is asynchronous, except for calls
+ *     with *_host outputs, which synchronise that stream before returning.
+ *   - State arrays are structure-of-arrays [5][nz][ny][nx] of double, x
+ *     fastest, in every precision mode.
+ *   - The first HIP error seen by a context is sticky: later calls on that
+ *     context return HGKS_EDEVICE.  hgks_last_error() returns a message for
+ *     the last failing call of the calling thread.
+ */
+#ifndef HGKS_H
+#define HGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hgks_ctx_s* hgks_ctx;
+typedef struct hgks_batch_s* hgks_batch;
+
+typedef enum {
+  HGKS_OK = 0,
+  HGKS_EINVAL = 1,        /* bad argument, size or configuration            */
+  HGKS_ENOMEM = 2,        /* workspace smaller than hgks_workspace_size     */
+  HGKS_EDEVICE = 3,       /* a HIP call failed (sticky per context)         */
+  HGKS_ESTATE = 4,        /* call order: e.g. step before set_state         */
+  HGKS_ENONPHYS = 5,      /* rho <= 0 or p <= 0 found by a check            */
+  HGKS_EUNSUPPORTED = 6   /* valid request this build does not provide      */
+} hgks_status;
+
+typedef enum { HGKS_BC_PERIODIC = 0, HGKS_BC_OUTFLOW = 1 } hgks_bc;
+
+typedef enum {
+  HGKS_FP64 = 0,  /* every step of the stage in double                        */
+  HGKS_MIXED = 1  /* reconstruction and gas-kinetic flux in float; stencil
+                     differences, face sums, stage accumulation, geometry and
+                     totals in double                                         */
+} hgks_prec;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 2                        */
+  int32_t bc[3];          /* hgks_bc per axis (x, y, z)                       */
+  double gamma;           /* ratio of specific heats, 1 < gamma < 5/3 (1.4)   */
+  double mu;              /* dynamic viscosity; 0 selects the inviscid
+                             collision time (Sec. 4)                          */
+  double weno_Gamma;      /* linear weight of each sub-stencil, 0 < G < 1/24
+                             (Sec. 2 suggests 0.0025)                         */
+  double weno_eps;        /* epsilon of the nonlinear weights, Eq. (3)       */
+  double tau_eps, tau_C;  /* collision time tau = tau_eps dt + tau_C
+                             |p_l - p_r|/(p_l + p_r) dt (inviscid) or
+                             mu/p + tau_C |...| dt (viscous), Sec. 4; the
+                             paper uses 0.01 and 1                            */
+  int32_t precision;      /* hgks_prec                                        */
+  int32_t moving;         /* 1: hexahedral vertex grid given by
+                             hgks_set_vertices (all axes periodic); 0: uniform
+                             box grid from hgks_set_uniform_grid              */
+  void* stream;           /* hipStream_t, NULL for the default stream         */
+} hgks_config;
+
+/* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,
+ * tau_eps 0.01, tau_C 1, FP64, periodic, inviscid) for an n^3 grid. */
+hgks_status hgks_default_config(hgks_config* cfg, int32_t nx, int32_t ny, int32_t nz);
+
+/* Device bytes of the workspace a context with this configuration needs. */
+hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes);
+
+/* Creates a context bound to the caller's workspace (device memory of at
+ * least hgks_workspace_size bytes, 256-byte aligned).  The configuration
+ * is copied.  HGKS_ENOMEM if bytes is too small. */
+hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t bytes,
+                        hgks_ctx* out);
+hgks_status hgks_destroy(hgks_ctx ctx);
+
+/* Uniform box grid: cell (i,j,k) = origin + [i,i+1]x[j,j+1]x[k,k+1] * h with
+ * h = length / n per axis.  Only for contexts with moving = 0. */
+hgks_status hgks_set_uniform_grid(hgks_ctx ctx, const double origin_host[3],
+                                  const double length_host[3]);
+
+/* Hexahedral grid (Sec. 2, trilinear cells; Sec. 3, bilinear faces): vertex
+ * positions [3][nz][ny][nx] (one vertex per cell and axis; all axes
+ * periodic, vertex n along an axis is vertex 0 shifted by the period).
+ * The vertices are copied into the workspace.  Only for moving = 1. */
+hgks_status hgks_set_vertices(hgks_ctx ctx, const double* xyz_dev, const double period_host[3]);
+
+/* Vertex positions at t_{n+1} for the next hgks_step (moving meshes,
+ * Sec. 3 Remark 2): the grid velocity is (next - current)/dt over the step,
+ * the stage geometry is at t_n and t_n + dt/2, and after the step the next
+ * vertices become the current ones.  Without a call the grid is static. */
+hgks_status hgks_set_next_vertices(hgks_ctx ctx, const double* xyz_dev);
+
+/* Copies cell averages [5][nz][ny][nx] (device) into / out of the context. */
+hgks_status hgks_set_state(hgks_ctx ctx, const double* q_dev);
+hgks_status hgks_get_state(hgks_ctx ctx, double* q_dev_out);
+
+/* dt = cfl * min over cells of h_cell / (|U| + c), h_cell the smallest
+ * distance between centres of opposite faces (the paper fixes only
+ * CFL = 0.35, Sec. 4).  Synchronises the stream. */
+hgks_status hgks_max_dt(hgks_ctx ctx, double cfl, double* dt_host);
+
+/* One time step of size dt: n_stages = 2 is the two-stage fourth-order
+ * scheme of Sec. 3; n_stages = 1 the one-stage update Q + dt L + dt^2/2 dL.
+ * Asynchronous. */
+hgks_status hgks_step(hgks_ctx ctx, double dt, int32_t n_stages);
+
+/* out[v] = sum over cells of |Omega| Q_v (deterministic order, double).
+ * Synchronises the stream. */
+hgks_status hgks_totals(hgks_ctx ctx, double out_host[5]);
+
+/* Number of cells whose density or pressure is not positive, and the
+ * number of (cell, Gauss point) pairs where the last stage used the
+ * first-order fallback of Sec. 4.  Synchronises the stream. */
+hgks_status hgks_check(hgks_ctx ctx, int64_t* nonphysical_host, int64_t* fallback_host);
+
+/* Parity hooks.  Both run one stage-1 reconstruction (and flux) of the
+ * current state with time step dt, without changing the state.
+ * gp states: [nz][ny][nx][24][5][4] = (value, d/dx, d/dy, d/dz) of each
+ *   variable at Gauss point 4*face + g, faces (-x,+x,-y,+y,-z,+z), g =
+ *   2*[a>0] + [b>0] in the face's cyclic parameters, after the fallback.
+ * face flux: [3][nz][ny][nx][2][5] = (F_p, dF_p/dt) summed over the lower
+ *   face of each cell along x, y, z (Eq. (11) with its time derivative). */
+hgks_status hgks_debug_gp_states(hgks_ctx ctx, double dt, double* dev_out);
+hgks_status hgks_debug_face_flux(hgks_ctx ctx, double dt, double* dev_out);
+
+/* Waits for the context's stream. */
+hgks_status hgks_sync(hgks_ctx ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hgks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HGKS_H */

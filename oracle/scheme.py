@@ -401,6 +401,26 @@ def gp_states(prob, Q_lib, dt, alpha=0.0):
     return np.ascontiguousarray(np.transpose(out, (2, 1, 0, 3, 4, 5)))
 
 
+def fallback_mask(prob, Q_lib, dt, alpha=0.0):
+    """Per real cell, bit 4*face + g set where that Gauss point used the
+    first-order fallback; layout [nz][ny][nx], same numbering as gp_states."""
+    Q = _to_ijk(np.asarray(Q_lib, float))
+    r = residual(prob, Q, dt, alpha, keep_faces=True)
+    n = prob.n
+    mask = np.zeros(n, dtype=np.uint32)
+    for d in range(3):
+        fd = r["faces"][d]
+        lo = [slice(None)] * 3
+        lo[d] = slice(0, n[d])
+        hi_idx = (np.arange(n[d]) + 1) % n[d] if prob.bc[d] == "periodic" else np.arange(n[d]) + 1
+        minus = fd["trigR"][(slice(None),) + tuple(lo)]          # (4gp, i, j, k)
+        plus = np.take(fd["trigL"], hi_idx, axis=1 + d)
+        for face, arr in ((2 * d, minus), (2 * d + 1, plus)):
+            for g in range(4):
+                mask |= arr[g].astype(np.uint32) << np.uint32(4 * face + g)
+    return np.ascontiguousarray(np.transpose(mask, (2, 1, 0)))
+
+
 def face_fluxes(prob, Q_lib, dt, alpha=0.0):
     """Face sums on the lower face of every real cell along each axis:
     layout [3][nz][ny][nx][2][5] holding (F_p, dF_p)."""

@@ -1,0 +1,485 @@
+// Kernels of the HGKS stage on a uniform box grid (Pan & Xu, Sec. 2-4).
+//
+// Layout in HBM (structure of arrays, x fastest):
+//   state     q[5][nz][ny][nx]                         double
+//   coef      c[5 vars][10][NRz][NRy][NRx]               TC (double/float)
+//             per variable: the cell mean and the nine coefficients of the
+//             reconstructed quadratic in the unit-cube coordinate xi;
+//             NR = n + 2 on outflow axes (one ghost layer), n on periodic.
+//   mask      m[NRz][NRy][NRx]                           uint32, bit 4 f + g
+//             set where Gauss point g of face f uses the first-order
+//             fallback (Sec. 4 limiting procedure)
+//   faces     F_d[10][fz][fy][fx] per direction d         TF
+//             (F_p, dF_p/dt) of the face on the lower side of cell (i,j,k)
+//             along d, summed over its 2x2 Gauss points with weight
+//             Delta_a Delta_b / 4 (Eq. (11)); f_d = n_d (periodic) or
+//             n_d + 1 (outflow), the other two extents n.
+#pragma once
+
+#include "common.h"
+#include "gks_flux.h"
+#include "weno_box.h"
+
+namespace hgks {
+
+constexpr int kBlock = 256;
+constexpr uint32_t kNeedsCheck = 0x80000000u;
+constexpr double kGaussNode = 0.28867513459481288225457439025097873;  // 1/(2 sqrt 3)
+
+struct BoxGrid {
+  int n[3];
+  int g[3];     // ghost layer of the reconstruction box
+  int nr[3];    // reconstruction box
+  int per[3];   // periodic axis
+  int nf[3][3]; // face grid per direction
+  double inv_dx[3];
+  double vol;
+};
+
+__device__ __forceinline__ int bc_index(const BoxGrid& G, int ax, int i) {
+  // Real index after the boundary rule: periodic wrap or zero-gradient clamp.
+  const int n = G.n[ax];
+  if (G.per[ax]) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ int rec_index(const BoxGrid& G, int ax, int i) {
+  // Reconstruction-box index of real cell i (i in [-1, n]).
+  const int n = G.n[ax];
+  if (G.per[ax]) return i < 0 ? i + n : (i >= n ? i - n : i);
+  return i + 1;
+}
+
+// ---------------------------------------------------------------- recon
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__ q, TC* __restrict__ coef,
+                                                      uint32_t* __restrict__ mask, BoxGrid G,
+                                                      WenoParams<TC> P, TC margin, TC gm1, size_t NR,
+                                                      unsigned nblk) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk) return;
+  const size_t idx = (size_t)b * kBlock + threadIdx.x;
+  if (idx >= NR) return;
+  const int ri = (int)(idx % G.nr[0]);
+  const int rj = (int)((idx / G.nr[0]) % G.nr[1]);
+  const int rk = (int)(idx / ((size_t)G.nr[0] * G.nr[1]));
+  const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
+  int ix[3], iy[3], iz[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    ix[o] = bc_index(G, 0, i + o - 1);
+    iy[o] = bc_index(G, 1, j + o - 1);
+    iz[o] = bc_index(G, 2, k + o - 1);
+  }
+  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
+  TC qc[5], bnd[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double* qv = q + v * N;
+    const double c = qv[iz[1] * nxy + iy[1] * nx + ix[1]];
+    TC d[27];
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+          if (nz == 0 || nz == 3) {
+            d[sidx(ox, oy, oz)] = TC(0);
+          } else {
+            d[sidx(ox, oy, oz)] = TC(qv[iz[oz + 1] * nxy + iy[oy + 1] * nx + ix[ox + 1]] - c);
+          }
+        }
+    BoxRecon<TC> r;
+    weno_box(d, P, r);
+    TC* cv = coef + (size_t)v * 10 * NR + idx;
+    cv[0] = TC(c);
+#pragma unroll
+    for (int m = 0; m < 9; ++m) cv[(size_t)(m + 1) * NR] = r.c[m];
+    qc[v] = TC(c);
+    bnd[v] = r.bound;
+  }
+  // Sufficient test that no polynomial can give rho <= 0 or p < 0 at a
+  // Gauss point: bounds of every variable over all 25 polynomials and 24
+  // points; the exact test runs only where this one fails.
+  const TC rmin = qc[0] - bnd[0];
+  bool safe = rmin > margin * qc[0];
+  if (safe) {
+    TC msq = TC(0);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+      const TC mm = d_abs(qc[1 + dd]) + bnd[1 + dd];
+      msq += mm * mm;
+    }
+    const TC emin = qc[4] - bnd[4];
+    safe = gm1 * (emin - TC(0.5) * msq / rmin) > margin * gm1 * (d_abs(qc[4]) + bnd[4]);
+  }
+  mask[idx] = safe ? 0u : kNeedsCheck;
+}
+
+// Exact fallback test (Sec. 4): for every Gauss point of the cell, any of
+// the 25 polynomials with rho <= 0 or p < 0 marks the point.
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __restrict__ q, uint32_t* __restrict__ mask,
+                                                            BoxGrid G, TC gm1, size_t NR) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= NR) return;
+  if (mask[idx] != kNeedsCheck) return;
+  const int ri = (int)(idx % G.nr[0]);
+  const int rj = (int)((idx / G.nr[0]) % G.nr[1]);
+  const int rk = (int)(idx / ((size_t)G.nr[0] * G.nr[1]));
+  const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
+  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
+  auto at = [&](int v, int ox, int oy, int oz) -> double {
+    const int a = bc_index(G, 0, i + ox), bb = bc_index(G, 1, j + oy), c = bc_index(G, 2, k + oz);
+    return q[v * N + c * nxy + bb * nx + a];
+  };
+  uint32_t bits = 0;
+  for (int m = 0; m < 25; ++m) {
+    TC qc[5], cf[5][9];
+    for (int v = 0; v < 5; ++v) {
+      const double c = at(v, 0, 0, 0);
+      qc[v] = TC(c);
+      for (int t = 0; t < 9; ++t) cf[v][t] = TC(0);
+      if (m == 0) {
+        TC d[27];
+        for (int oz = -1; oz <= 1; ++oz)
+          for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox) {
+              const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+              d[sidx(ox, oy, oz)] = (nz == 0 || nz == 3) ? TC(0) : TC(at(v, ox, oy, oz) - c);
+            }
+        big_quadratic(d, cf[v]);
+      } else {
+        const int mm = m - 1, t = mm / 8, r = mm % 8;
+        const int ic = r / 4, ib = (r / 2) % 2, ia = r % 2;
+        const int ea = t, eb = (t + 1) % 3, ec = (t + 2) % 3;
+        const int sa = ia ? -1 : 1, sb = ib ? -1 : 1, sc = ic ? -1 : 1;
+        int oa[3] = {0, 0, 0}, ob[3] = {0, 0, 0}, oc[3] = {0, 0, 0};
+        oa[ea] = sa; ob[eb] = sb; oc[ec] = sc;
+        const TC da = TC(at(v, oa[0], oa[1], oa[2]) - c);
+        const TC db = TC(at(v, ob[0], ob[1], ob[2]) - c);
+        const TC dab = TC(at(v, oa[0] + ob[0], oa[1] + ob[1], oa[2] + ob[2]) - c);
+        const TC dc = TC(at(v, oc[0], oc[1], oc[2]) - c);
+        cf[v][ec] = TC(sc) * dc;
+        cf[v][ea] = TC(sa) * (TC(2) * da - db + dab) * TC(1.0 / 3.0);
+        cf[v][eb] = TC(sb) * (TC(2) * db - da + dab) * TC(1.0 / 3.0);
+      }
+    }
+    for (int bit = 0; bit < 24; ++bit) {
+      const int f = bit >> 2, gp = bit & 3, d = f >> 1;
+      TC xi[3];
+      xi[d] = (f & 1) ? TC(0.5) : TC(-0.5);
+      xi[(d + 1) % 3] = (gp >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
+      xi[(d + 2) % 3] = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
+      TC val[5];
+      for (int v = 0; v < 5; ++v) {
+        TC gx, gy, gz;
+        quad_eval(qc[v], cf[v], xi[0], xi[1], xi[2], val[v], gx, gy, gz);
+      }
+      bool bad = !(val[0] > TC(0));
+      if (!bad) {
+        const TC p = gm1 * (val[4] - TC(0.5) * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]);
+        bad = p < TC(0);
+      }
+      if (bad) bits |= 1u << bit;
+    }
+  }
+  mask[idx] = bits;
+}
+
+// ---------------------------------------------------------------- flux
+// Value and gradient of the five variables of reconstructed cell `cell` at
+// unit-cube point xi, in the local frame of a face normal to axis D:
+// W = (rho, M_D, M_A, M_B, E), dW[j] = derivative along axis (D, A, B)[j].
+template <int D, typename TC>
+__device__ __forceinline__ void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, TC xD, TC xA,
+                                            TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
+                                            TC (&dW)[3][5]) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+  constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
+  TC xi[3];
+  xi[D] = xD;
+  xi[A] = xA;
+  xi[B] = xB;
+#pragma unroll
+  for (int kk = 0; kk < 5; ++kk) {
+    const TC* cv = coef + (size_t)lv[kk] * 10 * NR + cell;
+    const TC q0 = cv[0];
+    TC c[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) c[m] = cv[(size_t)(m + 1) * NR];
+    TC val, g[3];
+    quad_eval(q0, c, xi[0], xi[1], xi[2], val, g[0], g[1], g[2]);
+    if (fallback) {
+      val = q0;
+      g[0] = g[1] = g[2] = TC(0);
+    }
+    W[kk] = val;
+    dW[0][kk] = g[D] * invd[D];
+    dW[1][kk] = g[A] * invd[A];
+    dW[2][kk] = g[B] * invd[B];
+  }
+}
+
+template <int D, typename TC>
+__global__ void __launch_bounds__(kBlock) k_flux_box(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
+                                                     TC* __restrict__ face, BoxGrid G, GasParams<TC> gp, TC dt,
+                                                     size_t NR, size_t NF, unsigned nblk) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk) return;
+  const size_t tid = (size_t)b * kBlock + threadIdx.x;
+  const int gpi = (int)(tid & 3);
+  size_t f = tid >> 2;
+  const bool live = f < NF;
+  if (!live) f = NF - 1;  // keep the lane in the 4-lane sum; its result is not written
+  const int f0 = (int)(f % G.nf[D][0]);
+  const int f1 = (int)((f / G.nf[D][0]) % G.nf[D][1]);
+  const int f2 = (int)(f / ((size_t)G.nf[D][0] * G.nf[D][1]));
+  int cR[3] = {f0, f1, f2};
+  int cL[3] = {f0, f1, f2};
+  cL[D] -= 1;
+  size_t iL = 0, iR = 0;
+  {
+    const size_t s1 = G.nr[0], s2 = (size_t)G.nr[0] * G.nr[1];
+    iL = rec_index(G, 2, cL[2]) * s2 + rec_index(G, 1, cL[1]) * s1 + rec_index(G, 0, cL[0]);
+    iR = rec_index(G, 2, cR[2]) * s2 + rec_index(G, 1, cR[1]) * s1 + rec_index(G, 0, cR[0]);
+  }
+  const TC xa = (gpi >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
+  const TC xb = (gpi & 1) ? TC(kGaussNode) : TC(-kGaussNode);
+  const TC invd[3] = {TC(G.inv_dx[0]), TC(G.inv_dx[1]), TC(G.inv_dx[2])};
+  const bool fbL = (mask[iL] >> (4 * (2 * D + 1) + gpi)) & 1u;
+  const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
+
+  FluxAcc<TC> acc;
+  acc_zero(acc);
+  {
+    TC W[5], dW[3][5];
+    eval_box_gp<D>(coef, NR, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
+    side_terms<+1>(W, dW, gp, acc);
+  }
+  {
+    TC W[5], dW[3][5];
+    eval_box_gp<D>(coef, NR, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
+    side_terms<-1>(W, dW, gp, acc);
+  }
+  TC F[5], dF[5];
+  finish_flux(acc, gp, dt, F, dF);
+  // Face weight of Eq. (11): Gauss weight 1/4 times the area element.
+  const TC w = TC(0.25 / (G.inv_dx[A] * G.inv_dx[B]));
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    F[i] *= w;
+    dF[i] *= w;
+    F[i] += __shfl_xor(F[i], 1);
+    dF[i] += __shfl_xor(dF[i], 1);
+    F[i] += __shfl_xor(F[i], 2);
+    dF[i] += __shfl_xor(dF[i], 2);
+  }
+  if (live && gpi == 0) {
+    constexpr int gv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      face[(size_t)gv[i] * NF + f] = F[i];
+      face[(size_t)(5 + gv[i]) * NF + f] = dF[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- update
+// mode 0: one-stage update q = q + dt L + dt^2/2 dL
+// mode 1: first stage: qs = q + dt/2 L + dt^2/8 dL, acc = q + dt L + dt^2/6 dL
+// mode 2: second stage: q = acc + dt^2/3 dL(q*)
+template <typename TF>
+__global__ void __launch_bounds__(kBlock) k_update_box(double* __restrict__ q, double* __restrict__ qs,
+                                                       double* __restrict__ acc, const TF* __restrict__ fx,
+                                                       const TF* __restrict__ fy, const TF* __restrict__ fz,
+                                                       BoxGrid G, double dt, int mode, size_t N) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int c[3] = {(int)(idx % G.n[0]), (int)((idx / G.n[0]) % G.n[1]), (int)(idx / ((size_t)G.n[0] * G.n[1]))};
+  const TF* fs[3] = {fx, fy, fz};
+  double R[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) R[k] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int* nf = G.nf[d];
+    const size_t NF = (size_t)nf[0] * nf[1] * nf[2];
+    int hi[3] = {c[0], c[1], c[2]};
+    hi[d] += 1;
+    if (G.per[d] && hi[d] == G.n[d]) hi[d] = 0;
+    const size_t lo_i = ((size_t)c[2] * nf[1] + c[1]) * nf[0] + c[0];
+    const size_t hi_i = ((size_t)hi[2] * nf[1] + hi[1]) * nf[0] + hi[0];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) R[k] -= (double)fs[d][k * NF + hi_i] - (double)fs[d][k * NF + lo_i];
+  }
+  const double iv = 1.0 / G.vol;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double L = R[v] * iv, dL = R[5 + v] * iv;
+    const size_t o = (size_t)v * N + idx;
+    if (mode == 0) {
+      q[o] = q[o] + dt * L + 0.5 * dt * dt * dL;
+    } else if (mode == 1) {
+      const double q0 = q[o];
+      qs[o] = q0 + 0.5 * dt * L + 0.125 * dt * dt * dL;
+      acc[o] = q0 + dt * L + dt * dt / 6.0 * dL;
+    } else {
+      q[o] = acc[o] + dt * dt / 3.0 * dL;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+template <typename T, typename Op>
+__device__ __forceinline__ T block_reduce(T v, T* sh, Op op) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = op(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+struct MinOp {
+  __device__ double operator()(double a, double b) const { return a < b ? a : b; }
+};
+struct SumOp {
+  template <typename T>
+  __device__ T operator()(T a, T b) const { return a + b; }
+};
+
+// Time-step bound h / (|U| + c) per cell, minimum per block.
+__global__ void __launch_bounds__(kBlock) k_dt_box(const double* __restrict__ q, BoxGrid G, double gamma,
+                                                   double* __restrict__ part, size_t N) {
+  __shared__ double sh[kBlock];
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double v = 1e300;
+  if (idx < N) {
+    const double rho = q[idx];
+    const double u = q[N + idx] / rho, w1 = q[2 * N + idx] / rho, w2 = q[3 * N + idx] / rho;
+    const double p = (gamma - 1.0) * (q[4 * N + idx] - 0.5 * rho * (u * u + w1 * w1 + w2 * w2));
+    const double c = sqrt(gamma * p / rho);
+    double h = 1.0 / G.inv_dx[0];
+    h = fmin(h, 1.0 / G.inv_dx[1]);
+    h = fmin(h, 1.0 / G.inv_dx[2]);
+    v = h / (sqrt(u * u + w1 * w1 + w2 * w2) + c);
+    if (!(v > 0.0)) v = -1.0;  // non-physical state: reported as a negative bound
+  }
+  const double r = block_reduce(v, sh, MinOp());
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_min_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  double v = 1e300;
+  for (int i = threadIdx.x; i < n; i += kBlock) v = fmin(v, part[i]);
+  const double r = block_reduce(v, sh, MinOp());
+  if (threadIdx.x == 0) out[0] = r;
+}
+
+// sum |Omega| Q_v: fixed-order block sums, then a fixed-order final sum.
+__global__ void __launch_bounds__(kBlock) k_totals_box(const double* __restrict__ q, double vol,
+                                                       double* __restrict__ part, size_t N, int nblk) {
+  __shared__ double sh[kBlock];
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  for (int v = 0; v < 5; ++v) {
+    const double x = idx < N ? q[(size_t)v * N + idx] * vol : 0.0;
+    const double r = block_reduce(x, sh, SumOp());
+    if (threadIdx.x == 0) part[(size_t)v * nblk + blockIdx.x] = r;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_final(const double* __restrict__ part, int n, int nvec,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  for (int v = 0; v < nvec; ++v) {
+    double x = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) x += part[(size_t)v * n + i];
+    const double r = block_reduce(x, sh, SumOp());
+    if (threadIdx.x == 0) out[v] = r;
+    __syncthreads();
+  }
+}
+
+// Counts of non-physical cells and of fallback Gauss points of real cells.
+__global__ void __launch_bounds__(kBlock) k_check_box(const double* __restrict__ q, const uint32_t* __restrict__ mask,
+                                                      BoxGrid G, double gamma, double* __restrict__ part,
+                                                      size_t N, int nblk) {
+  __shared__ double sh[kBlock];
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double bad = 0.0, fb = 0.0;
+  if (idx < N) {
+    const double rho = q[idx];
+    const double e = q[4 * N + idx];
+    const double m2 = q[N + idx] * q[N + idx] + q[2 * N + idx] * q[2 * N + idx] + q[3 * N + idx] * q[3 * N + idx];
+    const double p = (gamma - 1.0) * (e - 0.5 * m2 / rho);
+    bad = (rho > 0.0 && p > 0.0) ? 0.0 : 1.0;
+    const int c0 = (int)(idx % G.n[0]), c1 = (int)((idx / G.n[0]) % G.n[1]);
+    const int c2 = (int)(idx / ((size_t)G.n[0] * G.n[1]));
+    const size_t r = ((size_t)(c2 + G.g[2]) * G.nr[1] + (c1 + G.g[1])) * G.nr[0] + (c0 + G.g[0]);
+    fb = (double)__popc(mask[r] & 0x00FFFFFFu);
+  }
+  double r1 = block_reduce(bad, sh, SumOp());
+  if (threadIdx.x == 0) part[blockIdx.x] = r1;
+  __syncthreads();
+  double r2 = block_reduce(fb, sh, SumOp());
+  if (threadIdx.x == 0) part[(size_t)nblk + blockIdx.x] = r2;
+}
+
+// ---------------------------------------------------------------- debug
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_debug_gp_box(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
+                                                         BoxGrid G, size_t NR, size_t N, double* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int c0 = (int)(idx % G.n[0]), c1 = (int)((idx / G.n[0]) % G.n[1]);
+  const int c2 = (int)(idx / ((size_t)G.n[0] * G.n[1]));
+  const size_t r = ((size_t)(c2 + G.g[2]) * G.nr[1] + (c1 + G.g[1])) * G.nr[0] + (c0 + G.g[0]);
+  const uint32_t mk = mask[r];
+  for (int bit = 0; bit < 24; ++bit) {
+    const int f = bit >> 2, gp = bit & 3, d = f >> 1;
+    TC xi[3];
+    xi[d] = (f & 1) ? TC(0.5) : TC(-0.5);
+    xi[(d + 1) % 3] = (gp >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
+    xi[(d + 2) % 3] = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
+    const bool fb = (mk >> bit) & 1u;
+    for (int v = 0; v < 5; ++v) {
+      const TC* cv = coef + (size_t)v * 10 * NR + r;
+      TC c[9];
+      for (int m = 0; m < 9; ++m) c[m] = cv[(size_t)(m + 1) * NR];
+      TC val, g[3];
+      quad_eval(cv[0], c, xi[0], xi[1], xi[2], val, g[0], g[1], g[2]);
+      if (fb) {
+        val = cv[0];
+        g[0] = g[1] = g[2] = TC(0);
+      }
+      double* o = out + ((idx * 24 + bit) * 5 + v) * 4;
+      o[0] = (double)val;
+      o[1] = (double)g[0] * G.inv_dx[0];
+      o[2] = (double)g[1] * G.inv_dx[1];
+      o[3] = (double)g[2] * G.inv_dx[2];
+    }
+  }
+}
+
+template <typename TF>
+__global__ void __launch_bounds__(kBlock) k_debug_face_box(const TF* __restrict__ face, BoxGrid G, int d, size_t N,
+                                                           double* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int c0 = (int)(idx % G.n[0]), c1 = (int)((idx / G.n[0]) % G.n[1]);
+  const int c2 = (int)(idx / ((size_t)G.n[0] * G.n[1]));
+  const int* nf = G.nf[d];
+  const size_t NF = (size_t)nf[0] * nf[1] * nf[2];
+  const size_t fi = ((size_t)c2 * nf[1] + c1) * nf[0] + c0;
+  for (int k = 0; k < 10; ++k) out[((size_t)d * N + idx) * 10 + k] = (double)face[(size_t)k * NF + fi];
+}
+
+}  // namespace hgks

@@ -1,0 +1,488 @@
+// Host side of the HGKS library: context, workspace carving, validation and
+// the launch sequence of one time stage (Pan & Xu, Sec. 3, two-stage
+// fourth-order scheme).  The C ABI is declared in include/hgks.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/hgks.h"
+#include "box_kernels.h"
+#include "hex_kernels.h"
+
+using namespace hgks;
+
+namespace {
+
+thread_local std::string g_err;
+
+hgks_status fail(hgks_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+unsigned pad8(unsigned nb) { return (nb + 7u) & ~7u; }
+
+struct Layout {
+  size_t q, qs, acc, coef, mask, face[3], red, geo, verts, vnext, vol, vacc, total;
+};
+
+struct Dims {
+  int n[3], g[3], nr[3], per[3], nf[3][3];
+  size_t N, NR, NF[3];
+  size_t nred;  // doubles of reduction scratch
+};
+
+bool valid_config(const hgks_config* c) {
+  if (!c) return false;
+  if (c->nx < 2 || c->ny < 2 || c->nz < 2) return false;
+  for (int d = 0; d < 3; ++d)
+    if (c->bc[d] != HGKS_BC_PERIODIC && c->bc[d] != HGKS_BC_OUTFLOW) return false;
+  if (!(c->gamma > 1.0 && c->gamma < 5.0 / 3.0)) return false;
+  if (!(c->mu >= 0.0) || !(c->weno_Gamma > 0.0 && c->weno_Gamma < 1.0 / 24.0)) return false;
+  if (!(c->weno_eps > 0.0) || !(c->tau_eps >= 0.0) || !(c->tau_C >= 0.0)) return false;
+  if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED) return false;
+  if (c->moving != 0 && c->moving != 1) return false;
+  if (c->moving)
+    for (int d = 0; d < 3; ++d)
+      if (c->bc[d] != HGKS_BC_PERIODIC) return false;
+  return true;
+}
+
+Dims make_dims(const hgks_config* c) {
+  Dims D;
+  const int n[3] = {c->nx, c->ny, c->nz};
+  D.N = 1;
+  D.NR = 1;
+  for (int d = 0; d < 3; ++d) {
+    D.n[d] = n[d];
+    D.per[d] = c->bc[d] == HGKS_BC_PERIODIC;
+    D.g[d] = D.per[d] ? 0 : 1;
+    D.nr[d] = n[d] + 2 * D.g[d];
+    D.N *= (size_t)n[d];
+    D.NR *= (size_t)D.nr[d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    for (int e = 0; e < 3; ++e) D.nf[d][e] = n[e];
+    if (!D.per[d]) D.nf[d][d] += 1;
+    D.NF[d] = (size_t)D.nf[d][0] * D.nf[d][1] * D.nf[d][2];
+  }
+  D.nred = 8 * (size_t)blocks_for(D.N) + 64;
+  return D;
+}
+
+Layout make_layout(const hgks_config* c, const Dims& D) {
+  Layout L;
+  const size_t tc = c->precision == HGKS_MIXED ? sizeof(float) : sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.q = take(5 * D.N * sizeof(double));
+  L.qs = take(5 * D.N * sizeof(double));
+  L.acc = take(5 * D.N * sizeof(double));
+  L.coef = take(50 * D.NR * tc);
+  L.mask = take(D.NR * sizeof(uint32_t));
+  const size_t nface = c->moving ? 12 : 10;
+  for (int d = 0; d < 3; ++d) L.face[d] = take(nface * D.NF[d] * tc);
+  L.red = take(D.nred * sizeof(double));
+  if (c->moving) {
+    L.geo = take((size_t)kHexGeo * D.N * sizeof(double));
+    L.verts = take(3 * D.N * sizeof(double));
+    L.vnext = take(3 * D.N * sizeof(double));
+    L.vol = take(D.N * sizeof(double));
+    L.vacc = take(2 * D.N * sizeof(double));
+  } else {
+    L.geo = L.verts = L.vnext = L.vol = L.vacc = 0;
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct hgks_ctx_s {
+  hgks_config cfg;
+  hipStream_t stream;
+  Dims D;
+  Layout L;
+  BoxGrid G;
+  HexGrid H;
+  char* ws;
+  bool grid_set = false, state_set = false, next_set = false;
+  hgks_status sticky = HGKS_OK;
+  double period[3];
+
+  double* q() { return (double*)(ws + L.q); }
+  double* qs() { return (double*)(ws + L.qs); }
+  double* acc() { return (double*)(ws + L.acc); }
+  void* coef() { return ws + L.coef; }
+  uint32_t* mask() { return (uint32_t*)(ws + L.mask); }
+  void* face(int d) { return ws + L.face[d]; }
+  double* red() { return (double*)(ws + L.red); }
+  double* geo() { return (double*)(ws + L.geo); }
+  double* verts() { return (double*)(ws + L.verts); }
+  double* vnext() { return (double*)(ws + L.vnext); }
+  double* vol() { return (double*)(ws + L.vol); }
+  double* vacc() { return (double*)(ws + L.vacc); }
+  bool mixed() const { return cfg.precision == HGKS_MIXED; }
+};
+
+namespace {
+
+hgks_status check_hip(hgks_ctx c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return HGKS_OK;
+  c->sticky = HGKS_EDEVICE;
+  return fail(HGKS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+hgks_status launched(hgks_ctx c, const char* what) { return check_hip(c, hipGetLastError(), what); }
+
+hgks_status usable(hgks_ctx c) {
+  if (!c) return fail(HGKS_EINVAL, "null context");
+  if (c->sticky != HGKS_OK) return fail(c->sticky, "context has a previous device error");
+  return HGKS_OK;
+}
+
+template <typename T>
+WenoParams<T> weno_params(const hgks_config& cfg, const double dx[3]) {
+  WenoParams<T> P;
+  P.gamma0 = T(1.0 - 24.0 * cfg.weno_Gamma);
+  P.Gamma = T(cfg.weno_Gamma);
+  P.eps = T(cfg.weno_eps);
+  const double h = std::cbrt(dx[0] * dx[1] * dx[2]);
+  double s[3];
+  for (int d = 0; d < 3; ++d) s[d] = (h / dx[d]) * (h / dx[d]);
+  for (int d = 0; d < 3; ++d) {
+    P.kl[d] = T(s[d]);
+    P.kq[d] = T(s[d] / 3.0 + 4.0 * s[d] * s[d]);
+  }
+  const int pd[3] = {0, 1, 0}, pe[3] = {1, 2, 2};
+  for (int k = 0; k < 3; ++k) P.km[k] = T(s[pd[k]] * s[pe[k]] + (s[pd[k]] + s[pe[k]]) / 12.0);
+  return P;
+}
+
+template <typename T>
+GasParams<T> gas_params(const hgks_config& cfg) {
+  GasParams<T> g;
+  const double K = (5.0 - 3.0 * cfg.gamma) / (cfg.gamma - 1.0);
+  g.gm1 = T(cfg.gamma - 1.0);
+  g.K = T(K);
+  g.K3 = T(K + 3.0);
+  g.KK2 = T(K * (K + 2.0));
+  g.mu = T(cfg.mu);
+  g.tau_eps = T(cfg.tau_eps);
+  g.tau_C = T(cfg.tau_C);
+  g.viscous = cfg.mu > 0.0;
+  return g;
+}
+
+// Reconstruction (with the fallback mask) and face fluxes of the state qin.
+template <typename TC>
+hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
+  const Dims& D = c->D;
+  const double dx[3] = {1.0 / c->G.inv_dx[0], 1.0 / c->G.inv_dx[1], 1.0 / c->G.inv_dx[2]};
+  const WenoParams<TC> P = weno_params<TC>(c->cfg, dx);
+  const GasParams<TC> gp = gas_params<TC>(c->cfg);
+  const TC margin = sizeof(TC) == 8 ? TC(1e-10) : TC(1e-5);
+  TC* coef = (TC*)c->coef();
+  {
+    const unsigned nb = blocks_for(D.NR);
+    hipLaunchKernelGGL((k_recon_box<TC>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(), c->G, P,
+                       margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
+    if (hgks_status s = launched(c, "recon")) return s;
+    hipLaunchKernelGGL((k_posit_exact_box<TC>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+                       TC(c->cfg.gamma - 1.0), D.NR);
+    if (hgks_status s = launched(c, "positivity")) return s;
+  }
+  const unsigned nbx = blocks_for(4 * D.NF[0]), nby = blocks_for(4 * D.NF[1]), nbz = blocks_for(4 * D.NF[2]);
+  hipLaunchKernelGGL((k_flux_box<0, TC>), dim3(pad8(nbx)), dim3(kBlock), 0, c->stream, coef, c->mask(),
+                     (TC*)c->face(0), c->G, gp, TC(dt), D.NR, D.NF[0], nbx);
+  hipLaunchKernelGGL((k_flux_box<1, TC>), dim3(pad8(nby)), dim3(kBlock), 0, c->stream, coef, c->mask(),
+                     (TC*)c->face(1), c->G, gp, TC(dt), D.NR, D.NF[1], nby);
+  hipLaunchKernelGGL((k_flux_box<2, TC>), dim3(pad8(nbz)), dim3(kBlock), 0, c->stream, coef, c->mask(),
+                     (TC*)c->face(2), c->G, gp, TC(dt), D.NR, D.NF[2], nbz);
+  return launched(c, "flux");
+}
+
+template <typename TF>
+hgks_status box_update(hgks_ctx c, double dt, int mode) {
+  hipLaunchKernelGGL((k_update_box<TF>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, c->q(), c->qs(),
+                     c->acc(), (const TF*)c->face(0), (const TF*)c->face(1), (const TF*)c->face(2), c->G, dt, mode,
+                     c->D.N);
+  return launched(c, "update");
+}
+
+template <typename T>
+hgks_status box_step(hgks_ctx c, double dt, int n_stages) {
+  if (hgks_status s = box_stage<T>(c, c->q(), dt)) return s;
+  if (n_stages == 1) return box_update<T>(c, dt, 0);
+  if (hgks_status s = box_update<T>(c, dt, 1)) return s;
+  if (hgks_status s = box_stage<T>(c, c->qs(), dt)) return s;
+  return box_update<T>(c, dt, 2);
+}
+
+template <typename T>
+hgks_status hex_step(hgks_ctx, double, int) {
+  return fail(HGKS_EUNSUPPORTED, "hexahedral grids are not built yet");
+}
+hgks_status hex_dt(hgks_ctx, double*, unsigned) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
+hgks_status hex_totals(hgks_ctx, double*, unsigned) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
+hgks_status hex_debug_gp(hgks_ctx, double, double*) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
+hgks_status hex_debug_face(hgks_ctx, double, double*) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
+
+hgks_status sync_copy(hgks_ctx c, void* dst, const void* src, size_t bytes) {
+  if (hgks_status s = check_hip(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream), "copy"))
+    return s;
+  return check_hip(c, hipStreamSynchronize(c->stream), "synchronise");
+}
+
+}  // namespace
+
+extern "C" {
+
+hgks_status hgks_default_config(hgks_config* cfg, int32_t nx, int32_t ny, int32_t nz) {
+  if (!cfg) return fail(HGKS_EINVAL, "null config");
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->nx = nx;
+  cfg->ny = ny;
+  cfg->nz = nz;
+  cfg->gamma = 1.4;
+  cfg->mu = 0.0;
+  cfg->weno_Gamma = 0.0025;
+  cfg->weno_eps = 1e-8;
+  cfg->tau_eps = 0.01;
+  cfg->tau_C = 1.0;
+  cfg->precision = HGKS_FP64;
+  return HGKS_OK;
+}
+
+hgks_status hgks_workspace_size(const hgks_config* cfg, size_t* bytes) {
+  if (!valid_config(cfg) || !bytes) return fail(HGKS_EINVAL, "invalid configuration");
+  const Dims D = make_dims(cfg);
+  *bytes = make_layout(cfg, D).total;
+  return HGKS_OK;
+}
+
+hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t bytes, hgks_ctx* out) {
+  if (!out) return fail(HGKS_EINVAL, "null output");
+  *out = nullptr;
+  if (!valid_config(cfg)) return fail(HGKS_EINVAL, "invalid configuration");
+  if (!workspace_dev || ((uintptr_t)workspace_dev & 255u)) return fail(HGKS_EINVAL, "workspace must be 256-byte aligned");
+  hgks_ctx c = new (std::nothrow) hgks_ctx_s;
+  if (!c) return fail(HGKS_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)cfg->stream;
+  c->D = make_dims(cfg);
+  c->L = make_layout(cfg, c->D);
+  if (bytes < c->L.total) {
+    delete c;
+    return fail(HGKS_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, c->L.total);
+  }
+  c->ws = (char*)workspace_dev;
+  std::memset(&c->G, 0, sizeof c->G);
+  for (int d = 0; d < 3; ++d) {
+    c->G.n[d] = c->D.n[d];
+    c->G.g[d] = c->D.g[d];
+    c->G.nr[d] = c->D.nr[d];
+    c->G.per[d] = c->D.per[d];
+    for (int e = 0; e < 3; ++e) c->G.nf[d][e] = c->D.nf[d][e];
+  }
+  std::memset(&c->H, 0, sizeof c->H);
+  *out = c;
+  return HGKS_OK;
+}
+
+hgks_status hgks_destroy(hgks_ctx ctx) {
+  delete ctx;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_uniform_grid(hgks_ctx c, const double origin[3], const double length[3]) {
+  if (hgks_status s = usable(c)) return s;
+  if (c->cfg.moving) return fail(HGKS_EINVAL, "context expects vertices (moving = 1)");
+  if (!origin || !length) return fail(HGKS_EINVAL, "null origin or length");
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    if (!(length[d] > 0.0) || !std::isfinite(origin[d])) return fail(HGKS_EINVAL, "bad box");
+    const double h = length[d] / c->D.n[d];
+    c->G.inv_dx[d] = 1.0 / h;
+    vol *= h;
+  }
+  c->G.vol = vol;
+  c->grid_set = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_vertices(hgks_ctx c, const double* xyz_dev, const double period[3]) {
+  if (hgks_status s = usable(c)) return s;
+  if (!c->cfg.moving) return fail(HGKS_EINVAL, "context expects a uniform grid (moving = 0)");
+  if (!xyz_dev || !period) return fail(HGKS_EINVAL, "null vertices or period");
+  for (int d = 0; d < 3; ++d)
+    if (!(period[d] > 0.0)) return fail(HGKS_EINVAL, "bad period");
+  if (hgks_status s = check_hip(c, hipMemcpyAsync(c->verts(), xyz_dev, 3 * c->D.N * sizeof(double),
+                                                  hipMemcpyDeviceToDevice, c->stream),
+                                "copy vertices"))
+    return s;
+  for (int d = 0; d < 3; ++d) c->period[d] = period[d];
+  hex_setup(c->H, c->D.n, period);
+  c->grid_set = true;
+  c->next_set = false;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_next_vertices(hgks_ctx c, const double* xyz_dev) {
+  if (hgks_status s = usable(c)) return s;
+  if (!c->cfg.moving || !c->grid_set) return fail(HGKS_ESTATE, "set_vertices first");
+  if (!xyz_dev) return fail(HGKS_EINVAL, "null vertices");
+  if (hgks_status s = check_hip(c, hipMemcpyAsync(c->vnext(), xyz_dev, 3 * c->D.N * sizeof(double),
+                                                  hipMemcpyDeviceToDevice, c->stream),
+                                "copy next vertices"))
+    return s;
+  c->next_set = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_set_state(hgks_ctx c, const double* q_dev) {
+  if (hgks_status s = usable(c)) return s;
+  if (!q_dev) return fail(HGKS_EINVAL, "null state");
+  if (hgks_status s = check_hip(c, hipMemcpyAsync(c->q(), q_dev, 5 * c->D.N * sizeof(double),
+                                                  hipMemcpyDeviceToDevice, c->stream),
+                                "copy state"))
+    return s;
+  c->state_set = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_get_state(hgks_ctx c, double* q_dev_out) {
+  if (hgks_status s = usable(c)) return s;
+  if (!c->state_set) return fail(HGKS_ESTATE, "no state");
+  if (!q_dev_out) return fail(HGKS_EINVAL, "null output");
+  return check_hip(c, hipMemcpyAsync(q_dev_out, c->q(), 5 * c->D.N * sizeof(double), hipMemcpyDeviceToDevice,
+                                     c->stream),
+                   "copy state out");
+}
+
+static hgks_status ready(hgks_ctx c) {
+  if (hgks_status s = usable(c)) return s;
+  if (!c->grid_set) return fail(HGKS_ESTATE, "grid not set");
+  if (!c->state_set) return fail(HGKS_ESTATE, "state not set");
+  return HGKS_OK;
+}
+
+hgks_status hgks_step(hgks_ctx c, double dt, int32_t n_stages) {
+  if (hgks_status s = ready(c)) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HGKS_EINVAL, "dt must be positive");
+  if (n_stages != 1 && n_stages != 2) return fail(HGKS_EINVAL, "n_stages must be 1 or 2");
+  hgks_status s;
+  if (c->cfg.moving)
+    s = c->mixed() ? hex_step<float>(c, dt, n_stages) : hex_step<double>(c, dt, n_stages);
+  else
+    s = c->mixed() ? box_step<float>(c, dt, n_stages) : box_step<double>(c, dt, n_stages);
+  return s;
+}
+
+hgks_status hgks_max_dt(hgks_ctx c, double cfl, double* dt_host) {
+  if (hgks_status s = ready(c)) return s;
+  if (!(cfl > 0.0) || !dt_host) return fail(HGKS_EINVAL, "bad cfl or output");
+  const unsigned nb = blocks_for(c->D.N);
+  double* part = c->red();
+  if (c->cfg.moving) {
+    if (hgks_status s = hex_dt(c, part, nb)) return s;
+  } else {
+    hipLaunchKernelGGL(k_dt_box, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), c->G, c->cfg.gamma, part, c->D.N);
+  }
+  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, c->stream, part, (int)nb, part + c->D.nred - 8);
+  if (hgks_status s = launched(c, "max_dt")) return s;
+  double m = 0.0;
+  if (hgks_status s = sync_copy(c, &m, part + c->D.nred - 8, sizeof(double))) return s;
+  if (!(m > 0.0)) return fail(HGKS_ENONPHYS, "non-physical state in max_dt");
+  *dt_host = cfl * m;
+  return HGKS_OK;
+}
+
+hgks_status hgks_totals(hgks_ctx c, double out[5]) {
+  if (hgks_status s = ready(c)) return s;
+  if (!out) return fail(HGKS_EINVAL, "null output");
+  const unsigned nb = blocks_for(c->D.N);
+  double* part = c->red();
+  if (c->cfg.moving) {
+    if (hgks_status s = hex_totals(c, part, nb)) return s;
+  } else {
+    hipLaunchKernelGGL(k_totals_box, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), c->G.vol, part, c->D.N, (int)nb);
+  }
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, c->stream, part, (int)nb, 5, part + c->D.nred - 8);
+  if (hgks_status s = launched(c, "totals")) return s;
+  return sync_copy(c, out, part + c->D.nred - 8, 5 * sizeof(double));
+}
+
+hgks_status hgks_check(hgks_ctx c, int64_t* nonphys, int64_t* fallback) {
+  if (hgks_status s = ready(c)) return s;
+  if (!nonphys || !fallback) return fail(HGKS_EINVAL, "null output");
+  const unsigned nb = blocks_for(c->D.N);
+  double* part = c->red();
+  hipLaunchKernelGGL(k_check_box, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), c->mask(), c->G, c->cfg.gamma, part,
+                     c->D.N, (int)nb);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, c->stream, part, (int)nb, 2, part + c->D.nred - 8);
+  if (hgks_status s = launched(c, "check")) return s;
+  double r[2];
+  if (hgks_status s = sync_copy(c, r, part + c->D.nred - 8, 2 * sizeof(double))) return s;
+  *nonphys = (int64_t)r[0];
+  *fallback = (int64_t)r[1];
+  return HGKS_OK;
+}
+
+hgks_status hgks_debug_gp_states(hgks_ctx c, double dt, double* out) {
+  if (hgks_status s = ready(c)) return s;
+  if (!out || !(dt > 0.0)) return fail(HGKS_EINVAL, "bad arguments");
+  if (c->cfg.moving) return hex_debug_gp(c, dt, out);
+  hgks_status s = c->mixed() ? box_stage<float>(c, c->q(), dt) : box_stage<double>(c, c->q(), dt);
+  if (s) return s;
+  if (c->mixed())
+    hipLaunchKernelGGL((k_debug_gp_box<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
+                       (const float*)c->coef(), c->mask(), c->G, c->D.NR, c->D.N, out);
+  else
+    hipLaunchKernelGGL((k_debug_gp_box<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
+                       (const double*)c->coef(), c->mask(), c->G, c->D.NR, c->D.N, out);
+  return launched(c, "debug gp");
+}
+
+hgks_status hgks_debug_face_flux(hgks_ctx c, double dt, double* out) {
+  if (hgks_status s = ready(c)) return s;
+  if (!out || !(dt > 0.0)) return fail(HGKS_EINVAL, "bad arguments");
+  if (c->cfg.moving) return hex_debug_face(c, dt, out);
+  hgks_status s = c->mixed() ? box_stage<float>(c, c->q(), dt) : box_stage<double>(c, c->q(), dt);
+  if (s) return s;
+  for (int d = 0; d < 3; ++d) {
+    if (c->mixed())
+      hipLaunchKernelGGL((k_debug_face_box<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
+                         (const float*)c->face(d), c->G, d, c->D.N, out);
+    else
+      hipLaunchKernelGGL((k_debug_face_box<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
+                         (const double*)c->face(d), c->G, d, c->D.N, out);
+  }
+  return launched(c, "debug face");
+}
+
+hgks_status hgks_sync(hgks_ctx c) {
+  if (hgks_status s = usable(c)) return s;
+  return check_hip(c, hipStreamSynchronize(c->stream), "synchronise");
+}
+
+const char* hgks_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""ctypes binding of the HGKS C ABI (include/hgks.h).
+
+Argument marshalling only: every step of the time stage runs in the HIP
+library.  PyTorch provides device memory and the stream.  Loading fails
+loudly when libhgks.so has not been built.
+
+Module-level functions carry the C names (``hgks_step(ctx, dt, n)`` ...);
+``Context`` wraps a context handle with methods of the same names without
+the prefix.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgks.so")
+
+HGKS_OK, HGKS_EINVAL, HGKS_ENOMEM, HGKS_EDEVICE, HGKS_ESTATE, HGKS_ENONPHYS, HGKS_EUNSUPPORTED = range(7)
+BC = {"periodic": 0, "outflow": 1}
+PREC = {"fp64": 0, "mixed": 1}
+
+EXPORTS = [
+    "hgks_default_config", "hgks_workspace_size", "hgks_create", "hgks_destroy",
+    "hgks_set_uniform_grid", "hgks_set_vertices", "hgks_set_next_vertices",
+    "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_totals",
+    "hgks_check", "hgks_debug_gp_states", "hgks_debug_face_flux", "hgks_sync",
+    "hgks_last_error",
+]
+
+
+class hgks_config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 3),
+        ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+        ("weno_Gamma", ctypes.c_double), ("weno_eps", ctypes.c_double),
+        ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("moving", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class HGKSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hgks status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libhgks.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, D, I32, SZ = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_size_t
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "hgks_default_config": [ctypes.POINTER(hgks_config), I32, I32, I32],
+        "hgks_workspace_size": [ctypes.POINTER(hgks_config), ctypes.POINTER(SZ)],
+        "hgks_create": [ctypes.POINTER(hgks_config), P, SZ, ctypes.POINTER(P)],
+        "hgks_destroy": [P],
+        "hgks_set_uniform_grid": [P, DP, DP],
+        "hgks_set_vertices": [P, P, DP],
+        "hgks_set_next_vertices": [P, P],
+        "hgks_set_state": [P, P],
+        "hgks_get_state": [P, P],
+        "hgks_max_dt": [P, D, DP],
+        "hgks_step": [P, D, I32],
+        "hgks_totals": [P, DP],
+        "hgks_check": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+        "hgks_debug_gp_states": [P, D, P],
+        "hgks_debug_face_flux": [P, D, P],
+        "hgks_sync": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.hgks_last_error.argtypes = []
+    L.hgks_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != HGKS_OK:
+        raise HGKSError(status, load().hgks_last_error().decode())
+
+
+def _dptr(t, shape=None, dtype=torch.float64):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor of dtype %s" % dtype)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _arr3(x):
+    return (ctypes.c_double * 3)(*[float(v) for v in x])
+
+
+# ------------------------------------------------------------ C-named calls
+def hgks_default_config(nx, ny, nz):
+    cfg = hgks_config()
+    _check(load().hgks_default_config(ctypes.byref(cfg), nx, ny, nz))
+    return cfg
+
+
+def hgks_workspace_size(cfg):
+    n = ctypes.c_size_t()
+    _check(load().hgks_workspace_size(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def hgks_create(cfg, workspace):
+    h = ctypes.c_void_p()
+    _check(load().hgks_create(ctypes.byref(cfg), ctypes.c_void_p(workspace.data_ptr()),
+                              workspace.numel() * workspace.element_size(), ctypes.byref(h)))
+    return h
+
+
+def hgks_destroy(h):
+    _check(load().hgks_destroy(h))
+
+
+def hgks_set_uniform_grid(h, origin, length):
+    _check(load().hgks_set_uniform_grid(h, _arr3(origin), _arr3(length)))
+
+
+def hgks_set_vertices(h, xyz, period):
+    _check(load().hgks_set_vertices(h, _dptr(xyz), _arr3(period)))
+
+
+def hgks_set_next_vertices(h, xyz):
+    _check(load().hgks_set_next_vertices(h, _dptr(xyz)))
+
+
+def hgks_set_state(h, q):
+    _check(load().hgks_set_state(h, _dptr(q)))
+
+
+def hgks_get_state(h, out):
+    _check(load().hgks_get_state(h, _dptr(out)))
+
+
+def hgks_max_dt(h, cfl):
+    dt = ctypes.c_double()
+    _check(load().hgks_max_dt(h, cfl, ctypes.byref(dt)))
+    return dt.value
+
+
+def hgks_step(h, dt, n_stages=2):
+    _check(load().hgks_step(h, dt, n_stages))
+
+
+def hgks_totals(h):
+    out = (ctypes.c_double * 5)()
+    _check(load().hgks_totals(h, out))
+    return list(out)
+
+
+def hgks_check(h):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().hgks_check(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def hgks_debug_gp_states(h, dt, out):
+    _check(load().hgks_debug_gp_states(h, dt, _dptr(out)))
+
+
+def hgks_debug_face_flux(h, dt, out):
+    _check(load().hgks_debug_face_flux(h, dt, _dptr(out)))
+
+
+def hgks_sync(h):
+    _check(load().hgks_sync(h))
+
+
+# ------------------------------------------------------------ wrapper
+class Context:
+    """One HGKS context with its workspace held as a torch tensor."""
+
+    def __init__(self, n, bc=("periodic",) * 3, gamma=1.4, mu=0.0, weno_Gamma=0.0025,
+                 weno_eps=1e-8, tau_eps=0.01, tau_C=1.0, precision="fp64", moving=False,
+                 device="cuda:0", stream=None):
+        self.n = tuple(int(x) for x in n)
+        self.device = torch.device(device)
+        cfg = hgks_default_config(*self.n)
+        for d in range(3):
+            cfg.bc[d] = BC[bc[d]]
+        cfg.gamma, cfg.mu = gamma, mu
+        cfg.weno_Gamma, cfg.weno_eps = weno_Gamma, weno_eps
+        cfg.tau_eps, cfg.tau_C = tau_eps, tau_C
+        cfg.precision = PREC[precision]
+        cfg.moving = 1 if moving else 0
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        cfg.stream = ctypes.c_void_p(stream.cuda_stream)
+        self.cfg = cfg
+        nbytes = hgks_workspace_size(cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.h = hgks_create(cfg, self._ws)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.hgks_destroy(h)
+            self.h = None
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (5, nz, ny, nx)
+
+    def set_uniform_grid(self, origin, length):
+        hgks_set_uniform_grid(self.h, origin, length)
+
+    def set_vertices(self, xyz, period):
+        hgks_set_vertices(self.h, xyz, period)
+
+    def set_next_vertices(self, xyz):
+        hgks_set_next_vertices(self.h, xyz)
+
+    def set_state(self, q):
+        hgks_set_state(self.h, q)
+
+    def get_state(self, out=None):
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        hgks_get_state(self.h, out)
+        return out
+
+    def max_dt(self, cfl):
+        return hgks_max_dt(self.h, cfl)
+
+    def step(self, dt, n_stages=2):
+        hgks_step(self.h, dt, n_stages)
+
+    def totals(self):
+        return hgks_totals(self.h)
+
+    def check(self):
+        return hgks_check(self.h)
+
+    def debug_gp_states(self, dt):
+        nx, ny, nz = self.n
+        out = torch.empty((nz, ny, nx, 24, 5, 4), dtype=torch.float64, device=self.device)
+        hgks_debug_gp_states(self.h, dt, out)
+        return out
+
+    def debug_face_flux(self, dt):
+        nx, ny, nz = self.n
+        out = torch.empty((3, nz, ny, nx, 2, 5), dtype=torch.float64, device=self.device)
+        hgks_debug_face_flux(self.h, dt, out)
+        return out
+
+    def sync(self):
+        hgks_sync(self.h)

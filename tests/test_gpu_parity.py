@@ -1,0 +1,115 @@
+"""GPU FP64 path against the FP64 oracle, element by element, through the
+C ABI: Gauss-point states after the fallback, face fluxes, whole steps,
+time-step bound and conservation.  Bar: normalised max-norm error <= 1e-12
+per variable (momentum components share one denominator), fallback masks
+identical.  Grids are ragged (no extent a multiple of the 64-lane wave or of
+the 256-thread block) and mix periodic and outflow axes."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import scheme
+from tests.helpers import blast_state, nerr, smooth_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+CASES = {
+    "periodic_inviscid": dict(n=(12, 10, 9), L=(1.2, 1.0, 0.9), bc=("periodic",) * 3, mu=0.0,
+                              state=lambda n, L: smooth_state(n, L, 1)),
+    "periodic_viscous": dict(n=(11, 9, 10), L=(1.1, 0.9, 1.0), bc=("periodic",) * 3, mu=2e-3,
+                             state=lambda n, L: smooth_state(n, L, 2, mach=0.6)),
+    "outflow_blast": dict(n=(14, 12, 10), L=(1.0, 1.0, 1.0), bc=("outflow",) * 3, mu=0.0,
+                          state=lambda n, L: blast_state(n, L)),
+    "mixed_bc_rect": dict(n=(10, 13, 9), L=(1.0, 1.6, 0.7), bc=("periodic", "outflow", "periodic"),
+                          mu=5e-4, state=lambda n, L: smooth_state(n, L, 3)),
+}
+
+
+@pytest.fixture(scope="module")
+def hg():
+    from paper_1909_01580_amd import hgks
+    hgks.load()
+    assert torch.cuda.is_available()
+    return hgks
+
+
+def setup(hg, case, precision="fp64"):
+    c = CASES[case]
+    Q = c["state"](c["n"], c["L"])
+    prob = oracle.uniform_problem(c["n"], (0.0, 0.0, 0.0), c["L"], bc=c["bc"],
+                                  params=oracle.Params(mu=c["mu"]))
+    ctx = hg.Context(c["n"], bc=c["bc"], mu=c["mu"], precision=precision)
+    ctx.set_uniform_grid((0.0, 0.0, 0.0), c["L"])
+    ctx.set_state(torch.tensor(Q, device="cuda:0"))
+    return Q, prob, ctx
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_max_dt(hg, case):
+    Q, prob, ctx = setup(hg, case)
+    assert abs(ctx.max_dt(0.35) - oracle.max_dt(prob, Q, 0.35)) < 1e-15 * oracle.max_dt(prob, Q, 0.35) * 10
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_gp_states(hg, case):
+    Q, prob, ctx = setup(hg, case)
+    dt = oracle.max_dt(prob, Q, 0.35)
+    gpu = ctx.debug_gp_states(dt).cpu().numpy()          # [nz][ny][nx][24][5][4]
+    ref = scheme.gp_states(prob, Q, dt)
+    for k in range(4):
+        e = nerr(gpu[..., k], ref[..., k], axis_var=4)
+        assert e.max() < TOL * (1 if k == 0 else 10), (k, e)
+    # Fallback decisions: same number of (cell, Gauss point) pairs; the
+    # discontinuous case exercises them.
+    mask = scheme.fallback_mask(prob, Q, dt)
+    count = int(sum(bin(int(m)).count("1") for m in mask.ravel()))
+    _, gpu_count = ctx.check()
+    assert gpu_count == count
+    if case == "outflow_blast":
+        assert count > 100
+        zero_g = np.all(ref[..., 1:] == 0.0, axis=(-1, -2))
+        assert np.array_equal(np.all(gpu[..., 1:] == 0.0, axis=(-1, -2)), zero_g)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_face_flux(hg, case):
+    Q, prob, ctx = setup(hg, case)
+    dt = oracle.max_dt(prob, Q, 0.35)
+    gpu = ctx.debug_face_flux(dt).cpu().numpy()          # [3][nz][ny][nx][2][5]
+    ref = scheme.face_fluxes(prob, Q, dt)
+    for k in range(2):
+        scale = np.abs(ref[..., k, :]).max()
+        err = np.abs(gpu[..., k, :] - ref[..., k, :]).max() / scale
+        assert err < TOL * (1 if k == 0 else 100), (k, err)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("n_stages", [1, 2])
+def test_step(hg, case, n_stages):
+    Q, prob, ctx = setup(hg, case)
+    ref = Q
+    steps = 2 if n_stages == 2 else 1
+    for _ in range(steps):
+        dt = oracle.max_dt(prob, ref, 0.35)
+        ref = oracle.step(prob, ref, dt, n_stages=n_stages)
+        ctx.step(dt, n_stages)
+    e = nerr(ctx.get_state().cpu().numpy(), ref)
+    assert e.max() < TOL, e
+
+
+def test_conservation_many_steps(hg):
+    case = CASES["periodic_viscous"]
+    Q, prob, ctx = setup(hg, "periodic_viscous")
+    t0 = np.array(ctx.totals())
+    assert np.allclose(t0, oracle.totals(prob, Q), rtol=1e-14, atol=1e-14)
+    for _ in range(50):
+        ctx.step(ctx.max_dt(0.35), 2)
+    t1 = np.array(ctx.totals())
+    assert np.abs(t1 - t0).max() < 1e-13 * np.abs(t0).max()
+    nonphys, _ = ctx.check()
+    assert nonphys == 0
+    del case

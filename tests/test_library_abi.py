@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/hgks.h declares, and its host-only logic
+(defaults, configuration validation, workspace sizing) behaves."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgks.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hgks_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1909_01580_amd import hgks
+    if not os.path.exists(hgks.LIB_PATH):
+        pytest.skip("libhgks.so not built")
+    return hgks.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1909_01580_amd import hgks
+    assert sorted(hgks.EXPORTS) == names
+
+
+def test_defaults_and_workspace(lib):
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(16, 16, 16)
+    assert cfg.gamma == 1.4 and cfg.weno_Gamma == 0.0025 and cfg.tau_eps == 0.01 and cfg.tau_C == 1.0
+    n = hgks.hgks_workspace_size(cfg)
+    # state x3, coefficients, masks, faces, reductions
+    N = 16 ** 3
+    assert n >= (15 + 50 + 30) * 8 * N
+    cfg.precision = hgks.PREC["mixed"]
+    assert hgks.hgks_workspace_size(cfg) < n
+    cfg.bc[0] = hgks.BC["outflow"]
+    n2 = hgks.hgks_workspace_size(cfg)
+    assert n2 > 0
+
+
+@pytest.mark.parametrize("field,value", [("nx", 1), ("gamma", 1.0), ("weno_Gamma", 0.05),
+                                         ("weno_eps", 0.0), ("precision", 7), ("moving", 2)])
+def test_invalid_configurations_rejected(lib, field, value):
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(8, 8, 8)
+    setattr(cfg, field, value)
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.hgks_workspace_size(cfg)
+    assert e.value.status == hgks.HGKS_EINVAL
+
+
+def test_moving_requires_periodic(lib):
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(8, 8, 8)
+    cfg.moving = 1
+    cfg.bc[2] = hgks.BC["outflow"]
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_workspace_size(cfg)
+
+
+def test_null_and_small_workspace(lib):
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(8, 8, 8)
+    h = ctypes.c_void_p()
+    st = lib.hgks_create(ctypes.byref(cfg), None, 0, ctypes.byref(h))
+    assert st == hgks.HGKS_EINVAL
+    st = lib.hgks_create(ctypes.byref(cfg), ctypes.c_void_p(256), 16, ctypes.byref(h))
+    assert st == hgks.HGKS_ENOMEM
+    assert b"workspace" in lib.hgks_last_error()
