@@ -1,0 +1,230 @@
+"""Throughput of the HGKS time step on the 128^3 Taylor-Green vortex.
+
+One step = one two-stage fourth-order time step of the whole hot path
+(WENO-AO reconstruction, gas-kinetic face flux, stage update) over the
+128^3 periodic grid on [-pi, pi]^3 (Re 1600, Ma 0.1), including the
+per-step time-step reduction.  The FP64 path gives ``value``; the mixed
+path (FP32 reconstruction and flux, FP64 accumulation) is reported beside
+it with its error against the FP64 result.
+
+Prints one JSON line.  Inputs are synthetic (the analytic initial field);
+they are resident in device memory before the timed region starts.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3}      # TFLOP/s, MI355X vector
+HBM_PEAK = 8000.0                         # GB/s
+BYTES_PER_CELL_STAGE = 120.0              # algorithmic HBM bytes (FP64 state)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flux_box_tgv128_traffic.json")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1909_01580_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")) and name != "opcount.hip":
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def op_counts():
+    with open(os.path.join(ROOT, "paper_1909_01580_amd", "opcount.json")) as f:
+        return json.load(f)
+
+
+def measured_traffic(precision):
+    """HBM bytes per flux launch from the committed rocprofv3 counter runs,
+    or None when they were taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(precision)
+    if not entry or t.get("source_hash") != source_hash():
+        return None
+    return entry["bytes_per_launch"]
+
+
+def run_gpu(n, steps, warmup, precision, cfl=0.35, record_first=False):
+    import torch
+    from paper_1909_01580_amd import hgks
+    from paper_1909_01580_amd import workloads as wl
+
+    q0 = torch.tensor(wl.tgv_state(n), device="cuda:0")
+    ctx = hgks.Context((n, n, n), mu=wl.TGV_MU, precision=precision)
+    ctx.set_uniform_grid((-np.pi,) * 3, (2 * np.pi,) * 3)
+    ctx.set_state(q0)
+    first = None
+    for i in range(warmup):
+        dt = ctx.max_dt(cfl)
+        ctx.step(dt, 2)
+        if i == 0 and record_first:
+            first = (dt, ctx.get_state().cpu().numpy())
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        dt = ctx.max_dt(cfl)
+        ctx.step(dt, 2)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_end()
+    ms = ev0.elapsed_time(ev1)
+    state = ctx.get_state().cpu().numpy()
+    totals = ctx.totals()
+    return {"ms": ms, "wall": wall, "prof": prof, "state": state, "totals": totals,
+            "first": first, "q0": q0.cpu().numpy()}
+
+
+def sampled_oracle_error(q0, first, n):
+    """Error of the first GPU FP64 step against the oracle at sampled cells:
+    the oracle advances a 13^3 periodic patch around each sampled cell (the
+    two-stage step at a cell depends on cells within 4 of it)."""
+    import oracle
+    from paper_1909_01580_amd import workloads as wl
+    dt, gpu = first
+    h = 2 * np.pi / n
+    worst = np.zeros(5)
+    samples = [(0, 0, 0), (n - 1, 5, 77), (64, 64, 64), (17, n - 1, 3)]
+    for (i, j, k) in samples:
+        idx = [np.arange(c - 6, c + 7) % n for c in (i, j, k)]
+        patch = q0[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+        prob = oracle.uniform_problem((13, 13, 13), (0, 0, 0), (13 * h,) * 3, bc=("outflow",) * 3,
+                                      params=oracle.Params(mu=wl.TGV_MU))
+        ref = oracle.step(prob, patch, dt)[:, 6, 6, 6]
+        got = gpu[:, k, j, i]
+        scale = np.array([1.0, 1.0, 1.0, 1.0, np.abs(q0[4]).max()])
+        worst = np.maximum(worst, np.abs(got - ref) / scale)
+    return float(worst.max()), len(samples)
+
+
+def cpu_baseline(q0, n, budget_cells=20):
+    """The oracle on a bounded sample of the same workload: one two-stage
+    step of a 20^3 block of the 128^3 Taylor-Green state (outflow at the
+    block faces), single-threaded."""
+    import oracle
+    from paper_1909_01580_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except ImportError:  # pragma: no cover
+        limiter = None
+    m = budget_cells
+    h = 2 * np.pi / n
+    block = np.ascontiguousarray(q0[:, :m, :m, :m])
+    prob = oracle.uniform_problem((m, m, m), (0, 0, 0), (m * h,) * 3, bc=("outflow",) * 3,
+                                  params=oracle.Params(mu=wl.TGV_MU))
+    dt = oracle.max_dt(prob, block, 0.35)
+    t0 = time.perf_counter()
+    oracle.step(prob, block, dt)
+    el = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister()
+    return {"value": m ** 3 * 2 / el, "unit": "cell-stage updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one two-stage step of a {m}^3 block of the 128^3 Taylor-Green state, "
+                      f"outflow block faces, NumPy FP64, one thread ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also copy this many MiB once (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, see the documentation)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    n = args.n
+    ops = op_counts()
+    results = {}
+    for prec in (("fp64", "mixed") if args.precision == "both" else (args.precision,)):
+        results[prec] = run_gpu(n, args.steps, max(args.warmup, 1), prec, record_first=(prec == "fp64"))
+    if args.copy_calibration:
+        nb = args.copy_calibration * (1 << 20)
+        a = torch.empty(nb // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    cells = n ** 3
+    head = results.get("fp64") or results["mixed"]
+    head_prec = "fp64" if "fp64" in results else "mixed"
+    ms_step = head["ms"] / args.steps
+    value = cells * 2 * args.steps / (head["ms"] / 1e3)
+    fl_ms, fl_n = head["prof"]["flux"]
+    launch_ms = fl_ms / max(fl_n, 1)
+    flops_per_launch = 12 * cells * ops["flux_gp_ops"]
+    achieved = flops_per_launch / (launch_ms / 1e3) / 1e12
+    peak = PEAK["fp64" if head_prec == "fp64" else "fp32"]
+    out = {
+        "metric": "cell-stage updates/sec (128^3 Taylor-Green, FP64; FP32-mixed beside)",
+        "value": value,
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head_prec == "fp64" else "f32 (f64 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "taylor-green-vortex 128^3 periodic [-pi,pi]^3, Re 1600, Ma 0.1, "
+                               "gamma 1.4, CFL 0.35, two-stage steps with per-step dt reduction",
+                   "cells": cells, "precision": head_prec},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": measured_traffic(head_prec),
+                     "kernel": "k_flux_box", "launch_ms": launch_ms,
+                     "ops_per_launch": flops_per_launch},
+        "hbm": {"algorithmic_GBps": BYTES_PER_CELL_STAGE * value / 1e9,
+                "frac_of_8TBps": BYTES_PER_CELL_STAGE * value / 1e9 / HBM_PEAK},
+        "phases_ms_per_step": {k: v[0] / args.steps for k, v in head["prof"].items()},
+        "conservation_rel_drift": float(np.abs(np.array(head["totals"]) - np.array(
+            [np.sum(head["q0"][v]) * (2 * np.pi / n) ** 3 for v in range(5)])).max()
+            / np.abs(head["totals"]).max()),
+    }
+    if "mixed" in results and "fp64" in results:
+        mx = results["mixed"]
+        r64 = results["fp64"]["state"][0]
+        out["mixed"] = {
+            "value": cells * 2 * args.steps / (mx["ms"] / 1e3),
+            "ms_per_step": mx["ms"] / args.steps,
+            "speedup_vs_fp64": results["fp64"]["ms"] / mx["ms"],
+            "l1_rho_rel_error_vs_fp64": float(np.abs(mx["state"][0] - r64).sum() / np.abs(r64).sum()),
+            "flux_launch_ms": mx["prof"]["flux"][0] / max(mx["prof"]["flux"][1], 1),
+            "roofline_frac_fp32": (flops_per_launch / (mx["prof"]["flux"][0] / max(mx["prof"]["flux"][1], 1) / 1e3)
+                                   / 1e12) / PEAK["fp32"],
+        }
+    if head.get("first") is not None and not args.no_oracle_check:
+        err, ns = sampled_oracle_error(head["q0"], head["first"], n)
+        out["fp64_error_vs_oracle"] = {"max_normalised": err, "sampled_cells": ns, "steps": 1}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(head["q0"], n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -144,6 +144,26 @@ hgks_status hgks_check(hgks_ctx ctx, int64_t* nonphysical_host, int64_t* fallbac
 hgks_status hgks_debug_gp_states(hgks_ctx ctx, double dt, double* dev_out);
 hgks_status hgks_debug_face_flux(hgks_ctx ctx, double dt, double* dev_out);
 
+/* Kernel timing by phase.  Between hgks_profile_begin and hgks_profile_end
+ * the context records a pair of HIP events on its stream around every
+ * launch of a phase (at most 512 launches per phase are timed; later ones
+ * run untimed).  hgks_profile_end synchronises the stream and returns, per
+ * phase, the summed kernel time in milliseconds and the number of timed
+ * launches.  Phases: reconstruction, exact fallback test, face flux (one
+ * launch covers the faces of all three directions), stage update,
+ * reductions (time step, totals, checks). */
+typedef enum {
+  HGKS_PHASE_RECON = 0,
+  HGKS_PHASE_FALLBACK = 1,
+  HGKS_PHASE_FLUX = 2,
+  HGKS_PHASE_UPDATE = 3,
+  HGKS_PHASE_REDUCE = 4,
+  HGKS_NPHASES = 5
+} hgks_phase;
+
+hgks_status hgks_profile_begin(hgks_ctx ctx);
+hgks_status hgks_profile_end(hgks_ctx ctx, double ms_host[5], int64_t launches_host[5]);
+
 /* Waits for the context's stream. */
 hgks_status hgks_sync(hgks_ctx ctx);
 

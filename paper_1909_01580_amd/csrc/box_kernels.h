@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __rest
 // unit-cube point xi, in the local frame of a face normal to axis D:
 // W = (rho, M_D, M_A, M_B, E), dW[j] = derivative along axis (D, A, B)[j].
 template <int D, typename TC>
-__device__ __forceinline__ void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, TC xD, TC xA,
+HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, TC xD, TC xA,
                                             TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
                                             TC (&dW)[3][5]) {
   constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
@@ -223,14 +223,14 @@ __device__ __forceinline__ void eval_box_gp(const TC* __restrict__ coef, size_t 
   }
 }
 
+// One lane = one Gauss point of one face normal to axis D; the four lanes of
+// a face sum their weighted fluxes with lane shuffles.  tid enumerates
+// (face, Gauss point) with the face index x-fastest.
 template <int D, typename TC>
-__global__ void __launch_bounds__(kBlock) k_flux_box(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
-                                                     TC* __restrict__ face, BoxGrid G, GasParams<TC> gp, TC dt,
-                                                     size_t NR, size_t NF, unsigned nblk) {
+__device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
+                                              TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
+                                              TC dt, size_t NR, size_t NF, size_t tid) {
   constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b >= nblk) return;
-  const size_t tid = (size_t)b * kBlock + threadIdx.x;
   const int gpi = (int)(tid & 3);
   size_t f = tid >> 2;
   const bool live = f < NF;
@@ -285,6 +285,24 @@ __global__ void __launch_bounds__(kBlock) k_flux_box(const TC* __restrict__ coef
       face[(size_t)gv[i] * NF + f] = F[i];
       face[(size_t)(5 + gv[i]) * NF + f] = dF[i];
     }
+  }
+}
+
+// All faces of the three directions in one launch: logical blocks
+// [0, nb0) take x-faces, [nb0, nb0+nb1) y-faces, the rest z-faces.
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_flux_box(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
+                                                     TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
+                                                     BoxGrid G, GasParams<TC> gp, TC dt, size_t NR, size_t NF0,
+                                                     size_t NF1, size_t NF2, unsigned nb0, unsigned nb1,
+                                                     unsigned nb2) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b < nb0) {
+    flux_box_face<0>(coef, mask, fx, G, gp, dt, NR, NF0, (size_t)b * kBlock + threadIdx.x);
+  } else if (b < nb0 + nb1) {
+    flux_box_face<1>(coef, mask, fy, G, gp, dt, NR, NF1, (size_t)(b - nb0) * kBlock + threadIdx.x);
+  } else if (b < nb0 + nb1 + nb2) {
+    flux_box_face<2>(coef, mask, fz, G, gp, dt, NR, NF2, (size_t)(b - nb0 - nb1) * kBlock + threadIdx.x);
   }
 }
 

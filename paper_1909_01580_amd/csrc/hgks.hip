@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/hgks.h"
 #include "box_kernels.h"
@@ -126,6 +127,12 @@ struct hgks_ctx_s {
   bool grid_set = false, state_set = false, next_set = false;
   hgks_status sticky = HGKS_OK;
   double period[3];
+  // Phase timing (hgks_profile_begin / hgks_profile_end).
+  static constexpr int kProfCap = 512;
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev[HGKS_NPHASES];
+  int prof_used[HGKS_NPHASES] = {0, 0, 0, 0, 0};
+  bool prof_open[HGKS_NPHASES] = {false, false, false, false, false};
 
   double* q() { return (double*)(ws + L.q); }
   double* qs() { return (double*)(ws + L.qs); }
@@ -151,6 +158,21 @@ hgks_status check_hip(hgks_ctx c, hipError_t e, const char* what) {
 }
 
 hgks_status launched(hgks_ctx c, const char* what) { return check_hip(c, hipGetLastError(), what); }
+
+// Records the start or end event of one timed launch of a phase.
+void prof_mark(hgks_ctx c, int phase, bool start) {
+  if (!c->prof_on) return;
+  int& k = c->prof_used[phase];
+  if (start) {
+    if (k >= hgks_ctx_s::kProfCap) return;
+    hipEventRecord(c->prof_ev[phase][2 * k], c->stream);
+    c->prof_open[phase] = true;
+  } else if (c->prof_open[phase]) {
+    hipEventRecord(c->prof_ev[phase][2 * k + 1], c->stream);
+    c->prof_open[phase] = false;
+    ++k;
+  }
+}
 
 hgks_status usable(hgks_ctx c) {
   if (!c) return fail(HGKS_EINVAL, "null context");
@@ -183,7 +205,7 @@ GasParams<T> gas_params(const hgks_config& cfg) {
   g.gm1 = T(cfg.gamma - 1.0);
   g.K = T(K);
   g.K3 = T(K + 3.0);
-  g.KK2 = T(K * (K + 2.0));
+  g.K2 = T(K + 2.0);
   g.mu = T(cfg.mu);
   g.tau_eps = T(cfg.tau_eps);
   g.tau_C = T(cfg.tau_C);
@@ -202,28 +224,33 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
   TC* coef = (TC*)c->coef();
   {
     const unsigned nb = blocks_for(D.NR);
+    prof_mark(c, HGKS_PHASE_RECON, true);
     hipLaunchKernelGGL((k_recon_box<TC>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(), c->G, P,
                        margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
+    prof_mark(c, HGKS_PHASE_RECON, false);
     if (hgks_status s = launched(c, "recon")) return s;
+    prof_mark(c, HGKS_PHASE_FALLBACK, true);
     hipLaunchKernelGGL((k_posit_exact_box<TC>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
                        TC(c->cfg.gamma - 1.0), D.NR);
+    prof_mark(c, HGKS_PHASE_FALLBACK, false);
     if (hgks_status s = launched(c, "positivity")) return s;
   }
   const unsigned nbx = blocks_for(4 * D.NF[0]), nby = blocks_for(4 * D.NF[1]), nbz = blocks_for(4 * D.NF[2]);
-  hipLaunchKernelGGL((k_flux_box<0, TC>), dim3(pad8(nbx)), dim3(kBlock), 0, c->stream, coef, c->mask(),
-                     (TC*)c->face(0), c->G, gp, TC(dt), D.NR, D.NF[0], nbx);
-  hipLaunchKernelGGL((k_flux_box<1, TC>), dim3(pad8(nby)), dim3(kBlock), 0, c->stream, coef, c->mask(),
-                     (TC*)c->face(1), c->G, gp, TC(dt), D.NR, D.NF[1], nby);
-  hipLaunchKernelGGL((k_flux_box<2, TC>), dim3(pad8(nbz)), dim3(kBlock), 0, c->stream, coef, c->mask(),
-                     (TC*)c->face(2), c->G, gp, TC(dt), D.NR, D.NF[2], nbz);
+  prof_mark(c, HGKS_PHASE_FLUX, true);
+  hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nbx + nby + nbz)), dim3(kBlock), 0, c->stream, coef, c->mask(),
+                     (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), D.NR, D.NF[0], D.NF[1],
+                     D.NF[2], nbx, nby, nbz);
+  prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
 
 template <typename TF>
 hgks_status box_update(hgks_ctx c, double dt, int mode) {
+  prof_mark(c, HGKS_PHASE_UPDATE, true);
   hipLaunchKernelGGL((k_update_box<TF>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, c->q(), c->qs(),
                      c->acc(), (const TF*)c->face(0), (const TF*)c->face(1), (const TF*)c->face(2), c->G, dt, mode,
                      c->D.N);
+  prof_mark(c, HGKS_PHASE_UPDATE, false);
   return launched(c, "update");
 }
 
@@ -308,6 +335,9 @@ hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t byte
 }
 
 hgks_status hgks_destroy(hgks_ctx ctx) {
+  if (ctx)
+    for (int p = 0; p < HGKS_NPHASES; ++p)
+      for (auto& e : ctx->prof_ev[p]) hipEventDestroy(e);
   delete ctx;
   return HGKS_OK;
 }
@@ -401,12 +431,14 @@ hgks_status hgks_max_dt(hgks_ctx c, double cfl, double* dt_host) {
   if (!(cfl > 0.0) || !dt_host) return fail(HGKS_EINVAL, "bad cfl or output");
   const unsigned nb = blocks_for(c->D.N);
   double* part = c->red();
+  prof_mark(c, HGKS_PHASE_REDUCE, true);
   if (c->cfg.moving) {
     if (hgks_status s = hex_dt(c, part, nb)) return s;
   } else {
     hipLaunchKernelGGL(k_dt_box, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), c->G, c->cfg.gamma, part, c->D.N);
   }
   hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, c->stream, part, (int)nb, part + c->D.nred - 8);
+  prof_mark(c, HGKS_PHASE_REDUCE, false);
   if (hgks_status s = launched(c, "max_dt")) return s;
   double m = 0.0;
   if (hgks_status s = sync_copy(c, &m, part + c->D.nred - 8, sizeof(double))) return s;
@@ -481,6 +513,43 @@ hgks_status hgks_debug_face_flux(hgks_ctx c, double dt, double* out) {
 hgks_status hgks_sync(hgks_ctx c) {
   if (hgks_status s = usable(c)) return s;
   return check_hip(c, hipStreamSynchronize(c->stream), "synchronise");
+}
+
+hgks_status hgks_profile_begin(hgks_ctx c) {
+  if (hgks_status s = usable(c)) return s;
+  if (c->prof_on) return fail(HGKS_ESTATE, "profiling already on");
+  for (int p = 0; p < HGKS_NPHASES; ++p) {
+    if (c->prof_ev[p].empty()) {
+      c->prof_ev[p].resize(2 * hgks_ctx_s::kProfCap);
+      for (auto& e : c->prof_ev[p])
+        if (hgks_status s = check_hip(c, hipEventCreate(&e), "event create")) return s;
+    }
+    c->prof_used[p] = 0;
+    c->prof_open[p] = false;
+  }
+  c->prof_on = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_profile_end(hgks_ctx c, double ms[5], int64_t launches[5]) {
+  if (hgks_status s = usable(c)) return s;
+  if (!c->prof_on) return fail(HGKS_ESTATE, "profiling is off");
+  if (!ms || !launches) return fail(HGKS_EINVAL, "null output");
+  c->prof_on = false;
+  if (hgks_status s = check_hip(c, hipStreamSynchronize(c->stream), "synchronise")) return s;
+  for (int p = 0; p < HGKS_NPHASES; ++p) {
+    double tot = 0.0;
+    for (int k = 0; k < c->prof_used[p]; ++k) {
+      float t = 0.f;
+      if (hgks_status s = check_hip(c, hipEventElapsedTime(&t, c->prof_ev[p][2 * k], c->prof_ev[p][2 * k + 1]),
+                                    "event time"))
+        return s;
+      tot += t;
+    }
+    ms[p] = tot;
+    launches[p] = c->prof_used[p];
+  }
+  return HGKS_OK;
 }
 
 const char* hgks_last_error(void) { return g_err.c_str(); }

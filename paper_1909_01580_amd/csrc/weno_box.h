@@ -40,8 +40,8 @@ struct WenoParams {
 };
 
 // Offsets o in {-1,0,1}^3 are stored at index (o_z+1)*9 + (o_y+1)*3 + (o_x+1).
-__host__ __device__ constexpr int sidx(int ox, int oy, int oz) { return (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1); }
-__host__ __device__ constexpr int sidx3(const int (&o)[3]) { return sidx(o[0], o[1], o[2]); }
+HGKS_FN constexpr int sidx(int ox, int oy, int oz) { return (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1); }
+HGKS_FN constexpr int sidx3(const int (&o)[3]) { return sidx(o[0], o[1], o[2]); }
 
 // Coefficient order: x, y, z, xx, yy, zz, xy, yz, xz.
 template <typename T>
@@ -55,13 +55,13 @@ struct BoxRecon {
 // linear coefficients l and (optional) quadratic coefficients: |xi_d| <= 1/2,
 // |xi_d^2 - 1/12| <= 1/6, |xi_d xi_e| <= 1/(4 sqrt 3).
 template <typename T>
-__device__ __forceinline__ T lin_bound(T bx, T by, T bz) {
+HGKS_FN T lin_bound(T bx, T by, T bz) {
   return T(0.5) * (d_abs(bx) + d_abs(by) + d_abs(bz));
 }
 
 // Least-squares quadratic of the big stencil (closed form above).
 template <typename T>
-__device__ __forceinline__ void big_quadratic(const T (&d)[27], T (&a)[9]) {
+HGKS_FN void big_quadratic(const T (&d)[27], T (&a)[9]) {
   {
     T r[3];
 #pragma unroll
@@ -114,7 +114,7 @@ __device__ __forceinline__ void big_quadratic(const T (&d)[27], T (&a)[9]) {
 }
 
 template <typename T>
-__device__ __forceinline__ void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out) {
+HGKS_FN void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out) {
   T a[9];
   big_quadratic(d, a);
   const T beta0 = P.kl[0] * a[0] * a[0] + P.kl[1] * a[1] * a[1] + P.kl[2] * a[2] * a[2] +
@@ -197,7 +197,7 @@ __device__ __forceinline__ void weno_box(const T (&d)[27], const WenoParams<T>& 
 // Value and unit-cube gradient of a quadratic with coefficients c (order x,
 // y, z, xx, yy, zz, xy, yz, xz) about the cell mean q at xi.
 template <typename T>
-__device__ __forceinline__ void quad_eval(T q, const T (&c)[9], T x, T y, T z, T& val, T& gx, T& gy, T& gz) {
+HGKS_FN void quad_eval(T q, const T (&c)[9], T x, T y, T z, T& val, T& gx, T& gy, T& gz) {
   const T t12 = T(1.0 / 12.0);
   val = q + c[0] * x + c[1] * y + c[2] * z + c[3] * (x * x - t12) + c[4] * (y * y - t12) +
         c[5] * (z * z - t12) + c[6] * x * y + c[7] * y * z + c[8] * x * z;

@@ -26,8 +26,9 @@ EXPORTS = [
     "hgks_set_uniform_grid", "hgks_set_vertices", "hgks_set_next_vertices",
     "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_totals",
     "hgks_check", "hgks_debug_gp_states", "hgks_debug_face_flux", "hgks_sync",
-    "hgks_last_error",
+    "hgks_last_error", "hgks_profile_begin", "hgks_profile_end",
 ]
+PHASES = ("recon", "fallback", "flux", "update", "reduce")
 
 
 class hgks_config(ctypes.Structure):
@@ -78,6 +79,8 @@ def load():
         "hgks_debug_gp_states": [P, D, P],
         "hgks_debug_face_flux": [P, D, P],
         "hgks_sync": [P],
+        "hgks_profile_begin": [P],
+        "hgks_profile_end": [P, DP, ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -184,6 +187,18 @@ def hgks_sync(h):
     _check(load().hgks_sync(h))
 
 
+def hgks_profile_begin(h):
+    _check(load().hgks_profile_begin(h))
+
+
+def hgks_profile_end(h):
+    """Returns {phase: (total ms, timed launches)}."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
+    _check(load().hgks_profile_end(h, ms, cnt))
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(PHASES)}
+
+
 # ------------------------------------------------------------ wrapper
 class Context:
     """One HGKS context with its workspace held as a torch tensor."""
@@ -267,3 +282,9 @@ class Context:
 
     def sync(self):
         hgks_sync(self.h)
+
+    def profile_begin(self):
+        hgks_profile_begin(self.h)
+
+    def profile_end(self):
+        return hgks_profile_end(self.h)
