@@ -1,19 +1,52 @@
 // Kernels of the HGKS stage on a periodic hexahedral (vertex) grid, static
-// or moving (Pan & Xu, Sec. 2 final part, Sec. 3 Eqs. (10)-(11), Remark 2).
+// or moving (Pan & Xu, Sec. 2 final part; Sec. 3, Eqs. (10)-(11) and
+// Remark 2).
+//
+// Geometry.  A cell is the trilinear image of [-1/2, 1/2]^3 of its eight
+// vertices (corner 4a + 2b + c = vertex (i+a, j+b, k+c)); cell integrals use
+// the 2x2x2 Gauss rule with |J|.  A face is the bilinear image of its four
+// vertices, parameterised by the two other axes in cyclic order (a, b) =
+// (d+1, d+2), so that X_a x X_b points towards increasing index along d;
+// Gauss point g = 2 [a>0] + [b>0] of the 2x2 rule, weight 1/4.  Vertices
+// move with the constant velocity (x^{n+1} - x^n)/dt; the stage geometry is
+// at t_n (stage 1) and t_n + dt/2 (stage 2).
+//
+// Per-stage geometry record of a cell (doubles, SoA [kHexGeo][N]): volume,
+// centroid (3), central second moments xx, yy, zz, xy, yz, xz (6), all by
+// the 2x2x2 rule.  The average over neighbour cell o of the scaled
+// monomials X^n, X = (x - c_i)/h_i, h_i = |Omega_i|^(1/3), follows from
+// o's record: mean X = (c_o - c_i)/h_i, mean X_a X_b = (M_o,ab + (c_o -
+// c_i)_a (c_o - c_i)_b)/h_i^2; this fills the rows of the least-squares
+// systems of Sec. 2 (big stencil 18 x 9, sub-stencils 4 x 3), solved here by
+// normal equations (Cholesky for 9 x 9, closed-form inverse for 3 x 3).
+//
+// Face flux.  At each face Gauss point the two reconstructions are
+// evaluated, shifted to the frame moving with the grid velocity U^g of the
+// point (M - rho U^g, E - M.U^g + rho |U^g|^2 / 2), rotated into the local
+// frame, passed through the static gas-kinetic flux and transformed back.
+// With a_G = X_a x X_b:
+//   F_p   = sum_G (1/4) |a_G| F_G,
+//   dF_p  = sum_G (1/4) (|a_G| dF_G - Q_0 (U^g . da_G/dt)),
+//   R_V   = sum_G (1/4) U^g . a_G,       dR_V = sum_G (1/4) U^g . da_G/dt,
+// and the stage update acts on |Omega| Q and |Omega| together.
 #pragma once
 
+#include "box_kernels.h"
 #include "common.h"
 #include "gks_flux.h"
 
 namespace hgks {
 
-// Per-cell geometry record (doubles): volume, centroid (3), second central
-// moments xx, yy, zz, xy, yz, xz (6).
 constexpr int kHexGeo = 10;
+constexpr int kHexFace = 12;  // F (5), dF (5), R_V, dR_V
 
 struct HexGrid {
   int n[3];
   double period[3];
+  const double* x0;  // vertices at t_n, [3][N]
+  const double* x1;  // vertices at t_{n+1}, or null for a static grid
+  double alpha;      // stage time (t - t_n) / dt
+  double inv_dt;
 };
 
 inline void hex_setup(HexGrid& H, const int n[3], const double period[3]) {
@@ -21,6 +54,867 @@ inline void hex_setup(HexGrid& H, const int n[3], const double period[3]) {
     H.n[d] = n[d];
     H.period[d] = period[d];
   }
+  H.x0 = H.x1 = nullptr;
+  H.alpha = 0.0;
+  H.inv_dt = 0.0;
+}
+
+__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+
+// Position and velocity of vertex (i, j, k) (indices may leave [0, n): the
+// periodic image is shifted by the period along that axis).
+__device__ __forceinline__ void hex_vertex(const HexGrid& H, int i, int j, int k, double (&x)[3], double (&u)[3]) {
+  int c[3] = {i, j, k};
+  double s[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int w = floordiv(c[d], H.n[d]);
+    c[d] -= w * H.n[d];
+    s[d] = w * H.period[d];
+  }
+  const size_t N = (size_t)H.n[0] * H.n[1] * H.n[2];
+  const size_t idx = ((size_t)c[2] * H.n[1] + c[1]) * H.n[0] + c[0];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const double a = H.x0[e * N + idx] + s[e];
+    if (H.x1) {
+      const double b = H.x1[e * N + idx] + s[e];
+      x[e] = a + H.alpha * (b - a);
+      u[e] = (b - a) * H.inv_dt;
+    } else {
+      x[e] = a;
+      u[e] = 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void cross3(const double (&a)[3], const double (&b)[3], double (&c)[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Bilinear face map (Eq. (10)) at parameters (sa, sb): position, the two
+// parametric derivatives, and the same for the vertex velocities.
+struct FacePoint {
+  double x[3], xa[3], xb[3], u[3], ua[3], ub[3];
+};
+
+__device__ __forceinline__ void face_point(const double (&cx)[4][3], const double (&cu)[4][3], double sa, double sb,
+                                           FacePoint& P) {
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    P.x[e] = P.xa[e] = P.xb[e] = P.u[e] = P.ua[e] = P.ub[e] = 0.0;
+  }
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+      const double ea = ia ? 1.0 : -1.0, eb = ib ? 1.0 : -1.0;
+      const double fa = 1.0 + 2.0 * ea * sa, fb = 1.0 + 2.0 * eb * sb;
+      const int m = 2 * ia + ib;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        P.x[e] += 0.25 * fa * fb * cx[m][e];
+        P.xa[e] += 0.5 * ea * fb * cx[m][e];
+        P.xb[e] += 0.5 * eb * fa * cx[m][e];
+        P.u[e] += 0.25 * fa * fb * cu[m][e];
+        P.ua[e] += 0.5 * ea * fb * cu[m][e];
+        P.ub[e] += 0.5 * eb * fa * cu[m][e];
+      }
+    }
+}
+
+// Corners of the face normal to axis d on vertex plane (i, j, k) (the
+// face's lowest vertex), corner 2*ia + ib along the cyclic axes (a, b).
+__device__ __forceinline__ void face_corners(const HexGrid& H, int d, int i, int j, int k, double (&cx)[4][3],
+                                             double (&cu)[4][3]) {
+  const int a = (d + 1) % 3, b = (d + 2) % 3;
+#pragma unroll
+  for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+      int c[3] = {i, j, k};
+      c[a] += ia;
+      c[b] += ib;
+      hex_vertex(H, c[0], c[1], c[2], cx[2 * ia + ib], cu[2 * ia + ib]);
+    }
+}
+
+// ---------------------------------------------------------------- K1
+// Cell geometry record at the stage time.
+__global__ void __launch_bounds__(kBlock) k_geometry_hex(HexGrid H, double* __restrict__ geo, size_t N) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  double cx[8][3];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    double u[3];
+    hex_vertex(H, i + ((m >> 2) & 1), j + ((m >> 1) & 1), k + (m & 1), cx[m], u);
+  }
+  const double g = kGaussNode;
+  double xq[8][3], wq[8];
+  double V = 0.0, c[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double xi = ((q >> 2) & 1) ? g : -g, et = ((q >> 1) & 1) ? g : -g, ze = (q & 1) ? g : -g;
+    double X[3] = {0, 0, 0}, D0[3] = {0, 0, 0}, D1[3] = {0, 0, 0}, D2[3] = {0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double sa = ((m >> 2) & 1) ? 1.0 : -1.0, sb = ((m >> 1) & 1) ? 1.0 : -1.0, sc = (m & 1) ? 1.0 : -1.0;
+      const double fa = 1.0 + 2.0 * sa * xi, fb = 1.0 + 2.0 * sb * et, fc = 1.0 + 2.0 * sc * ze;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        X[e] += fa * fb * fc * 0.125 * cx[m][e];
+        D0[e] += 2.0 * sa * fb * fc * 0.125 * cx[m][e];
+        D1[e] += 2.0 * sb * fa * fc * 0.125 * cx[m][e];
+        D2[e] += 2.0 * sc * fa * fb * 0.125 * cx[m][e];
+      }
+    }
+    double cr[3];
+    cross3(D1, D2, cr);
+    const double J = D0[0] * cr[0] + D0[1] * cr[1] + D0[2] * cr[2];
+    wq[q] = 0.125 * (J < 0 ? -J : J);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) xq[q][e] = X[e];
+    V += wq[q];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) c[e] += wq[q] * X[e];
+  }
+#pragma unroll
+  for (int e = 0; e < 3; ++e) c[e] /= V;
+  double M[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double dx = xq[q][0] - c[0], dy = xq[q][1] - c[1], dz = xq[q][2] - c[2];
+    M[0] += wq[q] * dx * dx;
+    M[1] += wq[q] * dy * dy;
+    M[2] += wq[q] * dz * dz;
+    M[3] += wq[q] * dx * dy;
+    M[4] += wq[q] * dy * dz;
+    M[5] += wq[q] * dx * dz;
+  }
+  geo[idx] = V;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) geo[(1 + e) * N + idx] = c[e];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) geo[(4 + e) * N + idx] = M[e] / V;
+}
+
+// ---------------------------------------------------------------- K2
+// Neighbour access for the reconstruction of cell (i, j, k).
+struct HexCell {
+  double c[3];   // centroid
+  double h, ih;  // |Omega|^(1/3) and its inverse
+  double m[6];   // central second moments / h^2 (means of X_a X_b)
+};
+
+__device__ __forceinline__ size_t hex_index(const HexGrid& H, int i, int j, int k, double (&shift)[3]) {
+  int c[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int w = floordiv(c[d], H.n[d]);
+    c[d] -= w * H.n[d];
+    shift[d] = w * H.period[d];
+  }
+  return ((size_t)c[2] * H.n[1] + c[1]) * H.n[0] + c[0];
+}
+
+__device__ __forceinline__ void load_cell(const double* __restrict__ geo, size_t N, size_t idx, HexCell& C) {
+  const double V = geo[idx];
+  C.h = cbrt(V);
+  C.ih = 1.0 / C.h;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) C.c[e] = geo[(1 + e) * N + idx];
+  const double ih2 = C.ih * C.ih;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) C.m[e] = geo[(4 + e) * N + idx] * ih2;
+}
+
+// Row of the least-squares system for neighbour cell o in the scaled basis
+// of cell i: mean over o of (X, X_x^2 - m_xx, ..., X_x X_z - m_xz).
+__device__ __forceinline__ void ls_row(const HexCell& Ci, const double* __restrict__ geo, size_t N, size_t io,
+                                       const double (&shift)[3], double (&r)[9]) {
+  double d[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) d[e] = (geo[(1 + e) * N + io] + shift[e] - Ci.c[e]) * Ci.ih;
+  const double ih2 = Ci.ih * Ci.ih;
+  double mo[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) mo[e] = geo[(4 + e) * N + io] * ih2;
+  r[0] = d[0];
+  r[1] = d[1];
+  r[2] = d[2];
+  r[3] = mo[0] + d[0] * d[0] - Ci.m[0];
+  r[4] = mo[1] + d[1] * d[1] - Ci.m[1];
+  r[5] = mo[2] + d[2] * d[2] - Ci.m[2];
+  r[6] = mo[3] + d[0] * d[1] - Ci.m[3];
+  r[7] = mo[4] + d[1] * d[2] - Ci.m[4];
+  r[8] = mo[5] + d[0] * d[2] - Ci.m[5];
+}
+
+// In-place Cholesky factorisation of a symmetric positive definite 9x9
+// matrix stored as its lower triangle L[i*(i+1)/2 + j].
+__device__ __forceinline__ void chol9(double (&L)[45]) {
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    double s = L[j * (j + 1) / 2 + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+    const double djj = sqrt(s);
+    L[j * (j + 1) / 2 + j] = djj;
+    const double inv = 1.0 / djj;
+#pragma unroll
+    for (int i = j + 1; i < 9; ++i) {
+      double t = L[i * (i + 1) / 2 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      L[i * (i + 1) / 2 + j] = t * inv;
+    }
+  }
+}
+
+__device__ __forceinline__ void chol9_solve(const double (&L)[45], double (&x)[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double t = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) t -= L[i * (i + 1) / 2 + k] * x[k];
+    x[i] = t / L[i * (i + 1) / 2 + i];
+  }
+#pragma unroll
+  for (int i = 8; i >= 0; --i) {
+    double t = x[i];
+#pragma unroll
+    for (int k = i + 1; k < 9; ++k) t -= L[k * (k + 1) / 2 + i] * x[k];
+    x[i] = t / L[i * (i + 1) / 2 + i];
+  }
+}
+
+// The 24 sub-stencils (Sec. 2): axis triple t = (a, b; c) in
+// ((x,y;z), (y,z;x), (z,x;y)), signs s_c, s_b, s_a in (+,-): cells
+// s_a e_a, s_b e_b, s_a e_a + s_b e_b, s_c e_c.
+__device__ __forceinline__ void sub_offsets(int m, int (&o)[4][3]) {
+  const int t = m / 8, r = m % 8;
+  const int ea = t, eb = (t + 1) % 3, ec = (t + 2) % 3;
+  const int sa = (r & 1) ? -1 : 1, sb = (r & 2) ? -1 : 1, sc = (r & 4) ? -1 : 1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q][0] = o[q][1] = o[q][2] = 0;
+  o[0][ea] = sa;
+  o[1][eb] = sb;
+  o[2][ea] = sa;
+  o[2][eb] = sb;
+  o[3][ec] = sc;
+}
+
+// Linear least squares of sub-stencil m for all five variables of cell
+// (i,j,k): b[v][3] in the scaled basis.
+__device__ __forceinline__ void sub_fit(const HexGrid& H, const HexCell& Ci, const double* __restrict__ geo,
+                                        const double* __restrict__ q, size_t N, int i, int j, int k,
+                                        const double (&qc)[5], int m, double (&b)[5][3]) {
+  int o[4][3];
+  sub_offsets(m, o);
+  double A[6] = {0, 0, 0, 0, 0, 0};  // xx, yy, zz, xy, yz, xz
+  double r[5][3];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) r[v][0] = r[v][1] = r[v][2] = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double sh[3];
+    const size_t io = hex_index(H, i + o[s][0], j + o[s][1], k + o[s][2], sh);
+    double d[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) d[e] = (geo[(1 + e) * N + io] + sh[e] - Ci.c[e]) * Ci.ih;
+    A[0] += d[0] * d[0];
+    A[1] += d[1] * d[1];
+    A[2] += d[2] * d[2];
+    A[3] += d[0] * d[1];
+    A[4] += d[1] * d[2];
+    A[5] += d[0] * d[2];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double dq = q[v * N + io] - qc[v];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) r[v][e] += d[e] * dq;
+    }
+  }
+  // closed-form inverse of the symmetric 3x3 normal matrix
+  const double c00 = A[1] * A[2] - A[4] * A[4];
+  const double c01 = A[5] * A[4] - A[3] * A[2];
+  const double c02 = A[3] * A[4] - A[1] * A[5];
+  const double c11 = A[0] * A[2] - A[5] * A[5];
+  const double c12 = A[3] * A[5] - A[0] * A[4];
+  const double c22 = A[0] * A[1] - A[3] * A[3];
+  const double idet = 1.0 / (A[0] * c00 + A[3] * c01 + A[5] * c02);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    b[v][0] = idet * (c00 * r[v][0] + c01 * r[v][1] + c02 * r[v][2]);
+    b[v][1] = idet * (c01 * r[v][0] + c11 * r[v][1] + c12 * r[v][2]);
+    b[v][2] = idet * (c02 * r[v][0] + c12 * r[v][1] + c22 * r[v][2]);
+  }
+}
+
+// Quadratic least squares of the big stencil for all five variables.
+__device__ __forceinline__ void big_fit(const HexGrid& H, const HexCell& Ci, const double* __restrict__ geo,
+                                        const double* __restrict__ q, size_t N, int i, int j, int k,
+                                        const double (&qc)[5], double (&a)[5][9]) {
+  double L[45];
+#pragma unroll
+  for (int e = 0; e < 45; ++e) L[e] = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) a[v][e] = 0.0;
+#pragma unroll 1
+  for (int s = 0; s < 27; ++s) {
+    const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = s / 9 - 1;
+    const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+    if (nz == 0 || nz == 3) continue;
+    double sh[3];
+    const size_t io = hex_index(H, i + ox, j + oy, k + oz, sh);
+    double r[9];
+    ls_row(Ci, geo, N, io, sh, r);
+#pragma unroll
+    for (int p = 0; p < 9; ++p)
+#pragma unroll
+      for (int t = 0; t <= p; ++t) L[p * (p + 1) / 2 + t] += r[p] * r[t];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double dq = q[v * N + io] - qc[v];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) a[v][e] += r[e] * dq;
+    }
+  }
+  chol9(L);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) chol9_solve(L, a[v]);
+}
+
+// Scaled coordinates of the 24 face Gauss points of cell (i,j,k), Gauss
+// point 4 f + g with faces (-x, +x, -y, +y, -z, +z).
+__device__ __forceinline__ void cell_gp(const HexGrid& H, const HexCell& Ci, int i, int j, int k, int bit,
+                                        double (&X)[3]) {
+  const int f = bit >> 2, gp = bit & 3, d = f >> 1;
+  int c[3] = {i, j, k};
+  c[d] += (f & 1);
+  double cx[4][3], cu[4][3];
+  face_corners(H, d, c[0], c[1], c[2], cx, cu);
+  FacePoint P;
+  face_point(cx, cu, (gp >> 1) ? kGaussNode : -kGaussNode, (gp & 1) ? kGaussNode : -kGaussNode, P);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) X[e] = (P.x[e] - Ci.c[e]) * Ci.ih;
+}
+
+__device__ __forceinline__ double pbasis(int n, const double (&X)[3], const double (&m)[6]) {
+  switch (n) {
+    case 0: return X[0];
+    case 1: return X[1];
+    case 2: return X[2];
+    case 3: return X[0] * X[0] - m[0];
+    case 4: return X[1] * X[1] - m[1];
+    case 5: return X[2] * X[2] - m[2];
+    case 6: return X[0] * X[1] - m[3];
+    case 7: return X[1] * X[2] - m[4];
+    default: return X[0] * X[2] - m[5];
+  }
+}
+
+// WENO-AO reconstruction on a hexahedral cell (always in double): the
+// combined quadratic in the scaled basis, written as (mean, 9 coefficients)
+// per variable, and the fallback pre-test.
+template <typename TS>
+__global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* __restrict__ geo,
+                                                      const double* __restrict__ q, TS* __restrict__ coef,
+                                                      uint32_t* __restrict__ mask, WenoParams<double> P, double gm1,
+                                                      size_t N) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  HexCell Ci;
+  load_cell(geo, N, idx, Ci);
+  double qc[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qc[v] = q[v * N + idx];
+  double a[5][9];
+  big_fit(H, Ci, geo, q, N, i, j, k, qc, a);
+
+  // beta_0 in the scaled basis: mean |grad P|^2 over the cell (second
+  // moments m) plus the squared second derivatives, each multi-index once.
+  double beta0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double* c = a[v];
+    const double Hs[3][3] = {{2 * c[3], c[6], c[8]}, {c[6], 2 * c[4], c[7]}, {c[8], c[7], 2 * c[5]}};
+    const double Mm[3][3] = {{Ci.m[0], Ci.m[3], Ci.m[5]}, {Ci.m[3], Ci.m[1], Ci.m[4]}, {Ci.m[5], Ci.m[4], Ci.m[2]}};
+    double tr = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        double hh = 0.0;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) hh += Hs[t][r] * Hs[t][s];
+        tr += hh * Mm[s][r];
+      }
+    beta0[v] = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + tr + 4.0 * (c[3] * c[3] + c[4] * c[4] + c[5] * c[5]) +
+               c[6] * c[6] + c[7] * c[7] + c[8] * c[8];
+  }
+  // Pass 1: tau = mean |beta_0 - beta_m|.
+  double tau[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int m = 0; m < 24; ++m) {
+    double b[5][3];
+    sub_fit(H, Ci, geo, q, N, i, j, k, qc, m, b);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
+      tau[v] += fabs(beta0[v] - bm);
+    }
+  }
+  // Pass 2: weights and the combination; running sums per variable.
+  double S[5], wb[5][3], sb[5][3], bnd[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    tau[v] *= 1.0 / 24.0;
+    S[v] = P.gamma0 * (1.0 + tau[v] / (beta0[v] + P.eps));
+    wb[v][0] = wb[v][1] = wb[v][2] = 0.0;
+    sb[v][0] = sb[v][1] = sb[v][2] = 0.0;
+    bnd[v] = 0.0;
+  }
+  double w0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w0[v] = S[v];
+  // Largest |X| components and basis magnitudes over the 24 Gauss points,
+  // for the bound of |P_m - Q| used by the fallback pre-test.
+  double pmax[9];
+#pragma unroll
+  for (int n = 0; n < 9; ++n) pmax[n] = 0.0;
+#pragma unroll 1
+  for (int bit = 0; bit < 24; ++bit) {
+    double X[3];
+    cell_gp(H, Ci, i, j, k, bit, X);
+#pragma unroll
+    for (int n = 0; n < 9; ++n) pmax[n] = fmax(pmax[n], fabs(pbasis(n, X, Ci.m)));
+  }
+#pragma unroll 1
+  for (int m = 0; m < 24; ++m) {
+    double b[5][3];
+    sub_fit(H, Ci, geo, q, N, i, j, k, qc, m, b);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
+      const double om = P.Gamma * (1.0 + tau[v] / (bm + P.eps));
+      S[v] += om;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        wb[v][e] += om * b[v][e];
+        sb[v][e] += b[v][e];
+      }
+      bnd[v] = fmax(bnd[v], fabs(b[v][0]) * pmax[0] + fabs(b[v][1]) * pmax[1] + fabs(b[v][2]) * pmax[2]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double iS = 1.0 / S[v];
+    const double w0g = w0[v] * iS / P.gamma0;
+    double c[9];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) c[e] = w0g * a[v][e] + iS * wb[v][e] - w0g * P.Gamma * sb[v][e];
+#pragma unroll
+    for (int e = 3; e < 9; ++e) c[e] = w0g * a[v][e];
+    double b0 = 0.0;
+#pragma unroll
+    for (int n = 0; n < 9; ++n) b0 += fabs(a[v][n]) * pmax[n];
+    bnd[v] = fmax(bnd[v], b0);
+    TS* cv = coef + (size_t)v * 10 * N + idx;
+    cv[0] = TS(qc[v]);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) cv[(size_t)(e + 1) * N] = TS(c[e]);
+  }
+  const double margin = 1e-10;
+  const double rmin = qc[0] - bnd[0];
+  bool safe = rmin > margin * qc[0];
+  if (safe) {
+    double msq = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double mm = fabs(qc[1 + d]) + bnd[1 + d];
+      msq += mm * mm;
+    }
+    safe = gm1 * (qc[4] - bnd[4] - 0.5 * msq / rmin) > margin * gm1 * (fabs(qc[4]) + bnd[4]);
+  }
+  mask[idx] = safe ? 0u : kNeedsCheck;
+}
+
+// Exact fallback test of Sec. 4 for the cells the pre-test flagged.
+__global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const double* __restrict__ geo,
+                                                            const double* __restrict__ q, uint32_t* __restrict__ mask,
+                                                            double gm1, size_t N) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  if (mask[idx] != kNeedsCheck) return;
+  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  HexCell Ci;
+  load_cell(geo, N, idx, Ci);
+  double qc[5];
+  for (int v = 0; v < 5; ++v) qc[v] = q[v * N + idx];
+  double a[5][9];
+  big_fit(H, Ci, geo, q, N, i, j, k, qc, a);
+  uint32_t bits = 0;
+  for (int bit = 0; bit < 24; ++bit) {
+    double X[3];
+    cell_gp(H, Ci, i, j, k, bit, X);
+    bool bad = false;
+    for (int m = 0; m <= 24 && !bad; ++m) {
+      double val[5];
+      if (m == 0) {
+        for (int v = 0; v < 5; ++v) {
+          double s = qc[v];
+          for (int n = 0; n < 9; ++n) s += a[v][n] * pbasis(n, X, Ci.m);
+          val[v] = s;
+        }
+      } else {
+        double b[5][3];
+        sub_fit(H, Ci, geo, q, N, i, j, k, qc, m - 1, b);
+        for (int v = 0; v < 5; ++v) val[v] = qc[v] + b[v][0] * X[0] + b[v][1] * X[1] + b[v][2] * X[2];
+      }
+      bad = !(val[0] > 0.0);
+      if (!bad) bad = gm1 * (val[4] - 0.5 * (val[1] * val[1] + val[2] * val[2] + val[3] * val[3]) / val[0]) < 0.0;
+    }
+    if (bad) bits |= 1u << bit;
+  }
+  mask[idx] = bits;
+}
+
+// ---------------------------------------------------------------- K3
+// Value and physical gradient of the five variables of cell idx at the
+// physical point x (centroid shifted by `shift` for periodic images).
+template <typename TC>
+__device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const double* __restrict__ geo, size_t N,
+                                         size_t idx, const double (&shift)[3], const double (&x)[3], bool fb,
+                                         double (&val)[5], double (&grad)[5][3]) {
+  HexCell C;
+  load_cell(geo, N, idx, C);
+  double X[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) X[e] = (x[e] - C.c[e] - shift[e]) * C.ih;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const TC* cv = coef + (size_t)v * 10 * N + idx;
+    double c[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) c[e] = (double)cv[(size_t)(e + 1) * N];
+    const double q0 = (double)cv[0];
+    if (fb) {
+      val[v] = q0;
+      grad[v][0] = grad[v][1] = grad[v][2] = 0.0;
+      continue;
+    }
+    val[v] = q0 + c[0] * X[0] + c[1] * X[1] + c[2] * X[2] + c[3] * (X[0] * X[0] - C.m[0]) +
+             c[4] * (X[1] * X[1] - C.m[1]) + c[5] * (X[2] * X[2] - C.m[2]) + c[6] * (X[0] * X[1] - C.m[3]) +
+             c[7] * (X[1] * X[2] - C.m[4]) + c[8] * (X[0] * X[2] - C.m[5]);
+    grad[v][0] = (c[0] + 2.0 * c[3] * X[0] + c[6] * X[1] + c[8] * X[2]) * C.ih;
+    grad[v][1] = (c[1] + 2.0 * c[4] * X[1] + c[6] * X[0] + c[7] * X[2]) * C.ih;
+    grad[v][2] = (c[2] + 2.0 * c[5] * X[2] + c[8] * X[0] + c[7] * X[1]) * C.ih;
+  }
+}
+
+// Conservative variables seen from a frame moving with u (one vector, also
+// applied to the gradients), then rotated into the frame (nx, ny, nz).
+template <typename TC>
+__device__ __forceinline__ void to_local(const double (&val)[5], const double (&grad)[5][3], const double (&u)[3],
+                                         const double (&nx)[3], const double (&ny)[3], const double (&nz)[3],
+                                         TC (&W)[5], TC (&dW)[3][5]) {
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  // shifted values
+  double s[5];
+  s[0] = val[0];
+  double Mu = 0.0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    s[1 + e] = val[1 + e] - val[0] * u[e];
+    Mu += val[1 + e] * u[e];
+  }
+  s[4] = val[4] - Mu + 0.5 * val[0] * uu;
+  const double* n[3] = {nx, ny, nz};
+  W[0] = TC(s[0]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) W[1 + j] = TC(s[1] * n[j][0] + s[2] * n[j][1] + s[3] * n[j][2]);
+  W[4] = TC(s[4]);
+  // gradients: derivative along n_j of the shifted variables
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double g[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) g[v] = grad[v][0] * n[j][0] + grad[v][1] * n[j][1] + grad[v][2] * n[j][2];
+    double gs[5];
+    gs[0] = g[0];
+    double gMu = 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      gs[1 + e] = g[1 + e] - g[0] * u[e];
+      gMu += g[1 + e] * u[e];
+    }
+    gs[4] = g[4] - gMu + 0.5 * g[0] * uu;
+    dW[j][0] = TC(gs[0]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) dW[j][1 + r] = TC(gs[1] * n[r][0] + gs[2] * n[r][1] + gs[3] * n[r][2]);
+    dW[j][4] = TC(gs[4]);
+  }
+}
+
+// Local-frame flux vector back to global components and to the fixed frame.
+__device__ __forceinline__ void to_global(const double (&f)[5], const double (&u)[3], const double (&nx)[3],
+                                          const double (&ny)[3], const double (&nz)[3], double (&g)[5]) {
+  double M[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) M[e] = nx[e] * f[1] + ny[e] * f[2] + nz[e] * f[3];
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  g[0] = f[0];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) g[1 + e] = M[e] + u[e] * f[0];
+  g[4] = f[4] + (M[0] * u[0] + M[1] * u[1] + M[2] * u[2]) + 0.5 * uu * f[0];
+}
+
+template <int D, typename TC>
+__device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
+                                              const uint32_t* __restrict__ mask, TC* __restrict__ face,
+                                              const GasParams<TC>& gp, TC dt, size_t N, size_t tid) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+  const int gpi = (int)(tid & 3);
+  size_t f = tid >> 2;
+  const bool live = f < N;
+  if (!live) f = N - 1;
+  const int c[3] = {(int)(f % H.n[0]), (int)((f / H.n[0]) % H.n[1]), (int)(f / ((size_t)H.n[0] * H.n[1]))};
+  // Face on the lower side of cell c along D: plane c[D].
+  double cx[4][3], cu[4][3];
+  face_corners(H, D, c[0], c[1], c[2], cx, cu);
+  FacePoint Pt;
+  face_point(cx, cu, (gpi >> 1) ? kGaussNode : -kGaussNode, (gpi & 1) ? kGaussNode : -kGaussNode, Pt);
+  double av[3], adot[3], t1[3], t2[3];
+  cross3(Pt.xa, Pt.xb, av);
+  cross3(Pt.ua, Pt.xb, t1);
+  cross3(Pt.xa, Pt.ub, t2);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) adot[e] = t1[e] + t2[e];
+  const double area = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
+  double nx[3], ny[3], nz[3];
+  const double lb = sqrt(Pt.xb[0] * Pt.xb[0] + Pt.xb[1] * Pt.xb[1] + Pt.xb[2] * Pt.xb[2]);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    nx[e] = av[e] / area;
+    nz[e] = Pt.xb[e] / lb;
+  }
+  cross3(nz, nx, ny);
+
+  int cL[3] = {c[0], c[1], c[2]};
+  cL[D] -= 1;
+  double shL[3], shR[3];
+  const size_t iL = hex_index(H, cL[0], cL[1], cL[2], shL);
+  const size_t iR = hex_index(H, c[0], c[1], c[2], shR);
+  const bool fbL = (mask[iL] >> (4 * (2 * D + 1) + gpi)) & 1u;
+  const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
+
+  FluxAcc<TC> acc;
+  acc_zero(acc);
+  {
+    double val[5], grad[5][3];
+    eval_hex(coef, geo, N, iL, shL, Pt.x, fbL, val, grad);
+    TC W[5], dW[3][5];
+    to_local(val, grad, Pt.u, nx, ny, nz, W, dW);
+    side_terms<+1>(W, dW, gp, acc);
+  }
+  {
+    double val[5], grad[5][3];
+    eval_hex(coef, geo, N, iR, shR, Pt.x, fbR, val, grad);
+    TC W[5], dW[3][5];
+    to_local(val, grad, Pt.u, nx, ny, nz, W, dW);
+    side_terms<-1>(W, dW, gp, acc);
+  }
+  TC Fl[5], dFl[5];
+  finish_flux(acc, gp, dt, Fl, dFl);
+  double fl[5], dfl[5], q0l[5];
+#pragma unroll
+  for (int e = 0; e < 5; ++e) {
+    fl[e] = (double)Fl[e];
+    dfl[e] = (double)dFl[e];
+    q0l[e] = (double)acc.Q0[e];
+  }
+  double F[5], dF[5], Q0[5];
+  to_global(fl, Pt.u, nx, ny, nz, F);
+  to_global(dfl, Pt.u, nx, ny, nz, dF);
+  to_global(q0l, Pt.u, nx, ny, nz, Q0);
+  const double rate = Pt.u[0] * adot[0] + Pt.u[1] * adot[1] + Pt.u[2] * adot[2];
+  double out[12];
+#pragma unroll
+  for (int e = 0; e < 5; ++e) {
+    out[e] = 0.25 * area * F[e];
+    out[5 + e] = 0.25 * (area * dF[e] - Q0[e] * rate);
+  }
+  out[10] = 0.25 * (Pt.u[0] * av[0] + Pt.u[1] * av[1] + Pt.u[2] * av[2]);
+  out[11] = 0.25 * rate;
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    out[e] += __shfl_xor(out[e], 1);
+    out[e] += __shfl_xor(out[e], 2);
+  }
+  if (live && gpi == 0) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) face[(size_t)e * N + f] = TC(out[e]);
+  }
+}
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_flux_hex(HexGrid H, const TC* __restrict__ coef,
+                                                     const double* __restrict__ geo, const uint32_t* __restrict__ mask,
+                                                     TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
+                                                     GasParams<TC> gp, TC dt, size_t N, unsigned nb) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b < nb) {
+    flux_hex_face<0>(H, coef, geo, mask, fx, gp, dt, N, (size_t)b * kBlock + threadIdx.x);
+  } else if (b < 2 * nb) {
+    flux_hex_face<1>(H, coef, geo, mask, fy, gp, dt, N, (size_t)(b - nb) * kBlock + threadIdx.x);
+  } else if (b < 3 * nb) {
+    flux_hex_face<2>(H, coef, geo, mask, fz, gp, dt, N, (size_t)(b - 2 * nb) * kBlock + threadIdx.x);
+  }
+}
+
+// ---------------------------------------------------------------- K4
+// Stage update of U = |Omega| Q and |Omega|.
+// mode 0: one-stage; mode 1: first stage (writes qs, acc, vacc);
+// mode 2: second stage.
+template <typename TF>
+__global__ void __launch_bounds__(kBlock) k_update_hex(HexGrid H, double* __restrict__ q, double* __restrict__ qs,
+                                                       double* __restrict__ acc, double* __restrict__ vacc,
+                                                       const double* __restrict__ geo, const TF* __restrict__ fx,
+                                                       const TF* __restrict__ fy, const TF* __restrict__ fz,
+                                                       double dt, int mode, size_t N) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int c[3] = {(int)(idx % H.n[0]), (int)((idx / H.n[0]) % H.n[1]), (int)(idx / ((size_t)H.n[0] * H.n[1]))};
+  const TF* fs[3] = {fx, fy, fz};
+  double R[12];
+#pragma unroll
+  for (int e = 0; e < 12; ++e) R[e] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int hi[3] = {c[0], c[1], c[2]};
+    hi[d] = hi[d] + 1 == H.n[d] ? 0 : hi[d] + 1;
+    const size_t hi_i = ((size_t)hi[2] * H.n[1] + hi[1]) * H.n[0] + hi[0];
+#pragma unroll
+    for (int e = 0; e < 10; ++e) R[e] -= (double)fs[d][e * N + hi_i] - (double)fs[d][e * N + idx];
+    R[10] += (double)fs[d][10 * N + hi_i] - (double)fs[d][10 * N + idx];
+    R[11] += (double)fs[d][11 * N + hi_i] - (double)fs[d][11 * N + idx];
+  }
+  if (mode == 2) {
+    const double Vn = vacc[idx] + dt * dt / 3.0 * R[11];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v * N + idx] = (acc[v * N + idx] + dt * dt / 3.0 * R[5 + v]) / Vn;
+    return;
+  }
+  const double V = geo[idx];
+  if (mode == 0) {
+    const double Vn = V + dt * R[10] + 0.5 * dt * dt * R[11];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v * N + idx] = (V * q[v * N + idx] + dt * R[v] + 0.5 * dt * dt * R[5 + v]) / Vn;
+    return;
+  }
+  const double Vs = V + 0.5 * dt * R[10] + 0.125 * dt * dt * R[11];
+  vacc[idx] = V + dt * R[10] + dt * dt / 6.0 * R[11];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double U = V * q[v * N + idx];
+    qs[v * N + idx] = (U + 0.5 * dt * R[v] + 0.125 * dt * dt * R[5 + v]) / Vs;
+    acc[v * N + idx] = U + dt * R[v] + dt * dt / 6.0 * R[5 + v];
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__global__ void __launch_bounds__(kBlock) k_dt_hex(HexGrid H, const double* __restrict__ q, double gamma,
+                                                   double* __restrict__ part, size_t N) {
+  __shared__ double sh[kBlock];
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double val = 1e300;
+  if (idx < N) {
+    const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+    double cx[8][3];
+    for (int m = 0; m < 8; ++m) {
+      double u[3];
+      hex_vertex(H, i + ((m >> 2) & 1), j + ((m >> 1) & 1), k + (m & 1), cx[m], u);
+    }
+    double hmin = 1e300;
+    for (int d = 0; d < 3; ++d) {
+      const int bit = 4 >> d;
+      double lo[3] = {0, 0, 0}, up[3] = {0, 0, 0};
+      for (int m = 0; m < 8; ++m)
+        for (int e = 0; e < 3; ++e) {
+          if (m & bit) up[e] += 0.25 * cx[m][e];
+          else lo[e] += 0.25 * cx[m][e];
+        }
+      const double dd = sqrt((up[0] - lo[0]) * (up[0] - lo[0]) + (up[1] - lo[1]) * (up[1] - lo[1]) +
+                             (up[2] - lo[2]) * (up[2] - lo[2]));
+      hmin = fmin(hmin, dd);
+    }
+    const double rho = q[idx];
+    const double u = q[N + idx] / rho, v = q[2 * N + idx] / rho, w = q[3 * N + idx] / rho;
+    const double p = (gamma - 1.0) * (q[4 * N + idx] - 0.5 * rho * (u * u + v * v + w * w));
+    const double c = sqrt(gamma * p / rho);
+    val = hmin / (sqrt(u * u + v * v + w * w) + c);
+    if (!(val > 0.0)) val = -1.0;
+  }
+  const double r = block_reduce(val, sh, MinOp());
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_totals_hex(const double* __restrict__ q, const double* __restrict__ geo,
+                                                       double* __restrict__ part, size_t N, int nblk) {
+  __shared__ double sh[kBlock];
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  for (int v = 0; v < 5; ++v) {
+    const double x = idx < N ? q[(size_t)v * N + idx] * geo[idx] : 0.0;
+    const double r = block_reduce(x, sh, SumOp());
+    if (threadIdx.x == 0) part[(size_t)v * nblk + blockIdx.x] = r;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- debug
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_debug_gp_hex(HexGrid H, const TC* __restrict__ coef,
+                                                         const double* __restrict__ geo,
+                                                         const uint32_t* __restrict__ mask, size_t N,
+                                                         double* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  const double zero[3] = {0.0, 0.0, 0.0};
+  for (int bit = 0; bit < 24; ++bit) {
+    const int f = bit >> 2, gp = bit & 3, d = f >> 1;
+    int c[3] = {i, j, k};
+    c[d] += (f & 1);
+    double cx[4][3], cu[4][3];
+    face_corners(H, d, c[0], c[1], c[2], cx, cu);
+    FacePoint P;
+    face_point(cx, cu, (gp >> 1) ? kGaussNode : -kGaussNode, (gp & 1) ? kGaussNode : -kGaussNode, P);
+    double val[5], grad[5][3];
+    eval_hex(coef, geo, N, idx, zero, P.x, (mask[idx] >> bit) & 1u, val, grad);
+    for (int v = 0; v < 5; ++v) {
+      double* o = out + ((idx * 24 + bit) * 5 + v) * 4;
+      o[0] = val[v];
+      o[1] = grad[v][0];
+      o[2] = grad[v][1];
+      o[3] = grad[v][2];
+    }
+  }
+}
+
+template <typename TF>
+__global__ void __launch_bounds__(kBlock) k_debug_face_hex(const TF* __restrict__ face, int d, size_t N,
+                                                           double* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  for (int k = 0; k < 10; ++k) out[((size_t)d * N + idx) * 10 + k] = (double)face[(size_t)k * N + idx];
 }
 
 }  // namespace hgks

@@ -263,14 +263,119 @@ hgks_status box_step(hgks_ctx c, double dt, int n_stages) {
   return box_update<T>(c, dt, 2);
 }
 
-template <typename T>
-hgks_status hex_step(hgks_ctx, double, int) {
-  return fail(HGKS_EUNSUPPORTED, "hexahedral grids are not built yet");
+// ------------------------------------------------------------ hexahedral grids
+HexGrid hex_grid(hgks_ctx c, double dt, double alpha, bool moving) {
+  HexGrid H = c->H;
+  H.x0 = c->verts();
+  H.x1 = (moving && c->next_set) ? c->vnext() : nullptr;
+  H.alpha = alpha;
+  H.inv_dt = dt > 0.0 ? 1.0 / dt : 0.0;
+  return H;
 }
-hgks_status hex_dt(hgks_ctx, double*, unsigned) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
-hgks_status hex_totals(hgks_ctx, double*, unsigned) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
-hgks_status hex_debug_gp(hgks_ctx, double, double*) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
-hgks_status hex_debug_face(hgks_ctx, double, double*) { return fail(HGKS_EUNSUPPORTED, "hexahedral grids"); }
+
+hgks_status hex_geometry(hgks_ctx c, const HexGrid& H) {
+  hipLaunchKernelGGL(k_geometry_hex, dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H, c->geo(), c->D.N);
+  return launched(c, "geometry");
+}
+
+// Stage geometry, reconstruction (double; coefficients stored in TC), the
+// fallback mask and the face fluxes of the state qin at t_n + alpha dt.
+template <typename TC>
+hgks_status hex_stage(hgks_ctx c, const double* qin, double dt, double alpha) {
+  const HexGrid H = hex_grid(c, dt, alpha, true);
+  const size_t N = c->D.N;
+  if (hgks_status s = hex_geometry(c, H)) return s;
+  const double dx[3] = {1.0, 1.0, 1.0};
+  const WenoParams<double> P = weno_params<double>(c->cfg, dx);
+  const GasParams<TC> gp = gas_params<TC>(c->cfg);
+  prof_mark(c, HGKS_PHASE_RECON, true);
+  hipLaunchKernelGGL((k_recon_hex<TC>), dim3(blocks_for(N)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                     (TC*)c->coef(), c->mask(), P, c->cfg.gamma - 1.0, N);
+  prof_mark(c, HGKS_PHASE_RECON, false);
+  if (hgks_status s = launched(c, "recon")) return s;
+  prof_mark(c, HGKS_PHASE_FALLBACK, true);
+  hipLaunchKernelGGL(k_posit_exact_hex, dim3(blocks_for(N)), dim3(kBlock), 0, c->stream, H, c->geo(), qin, c->mask(),
+                     c->cfg.gamma - 1.0, N);
+  prof_mark(c, HGKS_PHASE_FALLBACK, false);
+  if (hgks_status s = launched(c, "positivity")) return s;
+  const unsigned nb = blocks_for(4 * N);
+  prof_mark(c, HGKS_PHASE_FLUX, true);
+  hipLaunchKernelGGL((k_flux_hex<TC>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H, (const TC*)c->coef(),
+                     c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), gp, TC(dt), N, nb);
+  prof_mark(c, HGKS_PHASE_FLUX, false);
+  return launched(c, "flux");
+}
+
+template <typename TF>
+hgks_status hex_update(hgks_ctx c, double dt, int mode) {
+  const HexGrid H = hex_grid(c, dt, 0.0, true);
+  prof_mark(c, HGKS_PHASE_UPDATE, true);
+  hipLaunchKernelGGL((k_update_hex<TF>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H, c->q(), c->qs(),
+                     c->acc(), c->vacc(), c->geo(), (const TF*)c->face(0), (const TF*)c->face(1),
+                     (const TF*)c->face(2), dt, mode, c->D.N);
+  prof_mark(c, HGKS_PHASE_UPDATE, false);
+  return launched(c, "update");
+}
+
+template <typename T>
+hgks_status hex_step(hgks_ctx c, double dt, int n_stages) {
+  if (hgks_status s = hex_stage<T>(c, c->q(), dt, 0.0)) return s;
+  if (n_stages == 1) {
+    if (hgks_status s = hex_update<T>(c, dt, 0)) return s;
+  } else {
+    if (hgks_status s = hex_update<T>(c, dt, 1)) return s;
+    if (hgks_status s = hex_stage<T>(c, c->qs(), dt, 0.5)) return s;
+    if (hgks_status s = hex_update<T>(c, dt, 2)) return s;
+  }
+  if (c->next_set) {
+    // The vertices at t_{n+1} become the current ones.
+    const size_t t = c->L.verts;
+    c->L.verts = c->L.vnext;
+    c->L.vnext = t;
+    c->next_set = false;
+  }
+  return HGKS_OK;
+}
+
+hgks_status hex_dt(hgks_ctx c, double* part, unsigned nb) {
+  const HexGrid H = hex_grid(c, 0.0, 0.0, false);
+  hipLaunchKernelGGL(k_dt_hex, dim3(nb), dim3(kBlock), 0, c->stream, H, c->q(), c->cfg.gamma, part, c->D.N);
+  return launched(c, "dt");
+}
+
+hgks_status hex_totals(hgks_ctx c, double* part, unsigned nb) {
+  const HexGrid H = hex_grid(c, 0.0, 0.0, false);
+  if (hgks_status s = hex_geometry(c, H)) return s;
+  hipLaunchKernelGGL(k_totals_hex, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), c->geo(), part, c->D.N, (int)nb);
+  return launched(c, "totals");
+}
+
+hgks_status hex_debug_gp(hgks_ctx c, double dt, double* out) {
+  hgks_status s = c->mixed() ? hex_stage<float>(c, c->q(), dt, 0.0) : hex_stage<double>(c, c->q(), dt, 0.0);
+  if (s) return s;
+  const HexGrid H = hex_grid(c, dt, 0.0, true);
+  if (c->mixed())
+    hipLaunchKernelGGL((k_debug_gp_hex<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H,
+                       (const float*)c->coef(), c->geo(), c->mask(), c->D.N, out);
+  else
+    hipLaunchKernelGGL((k_debug_gp_hex<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H,
+                       (const double*)c->coef(), c->geo(), c->mask(), c->D.N, out);
+  return launched(c, "debug gp");
+}
+
+hgks_status hex_debug_face(hgks_ctx c, double dt, double* out) {
+  hgks_status s = c->mixed() ? hex_stage<float>(c, c->q(), dt, 0.0) : hex_stage<double>(c, c->q(), dt, 0.0);
+  if (s) return s;
+  for (int d = 0; d < 3; ++d) {
+    if (c->mixed())
+      hipLaunchKernelGGL((k_debug_face_hex<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
+                         (const float*)c->face(d), d, c->D.N, out);
+    else
+      hipLaunchKernelGGL((k_debug_face_hex<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
+                         (const double*)c->face(d), d, c->D.N, out);
+  }
+  return launched(c, "debug face");
+}
 
 hgks_status sync_copy(hgks_ctx c, void* dst, const void* src, size_t bytes) {
   if (hgks_status s = check_hip(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream), "copy"))
