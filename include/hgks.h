@@ -167,6 +167,46 @@ hgks_status hgks_profile_end(hgks_ctx ctx, double ms_host[5], int64_t launches_h
 /* Waits for the context's stream. */
 hgks_status hgks_sync(hgks_ctx ctx);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent periodic box grids of uneven sizes advanced together
+ * by the same stage as hgks_step: one persistent launch per phase covers
+ * every grid, each grid with its own time step read from device memory, so
+ * whole steps can be captured in a HIP graph and replayed.
+ *
+ * cfgs[i] describes grid i (sizes, mu); every grid must be a uniform box
+ * (moving = 0) with all axes periodic, and gamma, weno_Gamma, weno_eps,
+ * tau_eps, tau_C and precision must equal those of cfgs[0].  The stream
+ * of cfgs[0] is used; it must not be the legacy default stream when
+ * hgks_batch_capture is used.  Grid i's state is [5][nz_i][ny_i][nx_i]. */
+hgks_status hgks_batch_workspace_size(const hgks_config* cfgs, int32_t n, size_t* bytes);
+hgks_status hgks_batch_create(const hgks_config* cfgs, int32_t n, void* workspace_dev, size_t bytes,
+                              hgks_batch* out);
+hgks_status hgks_batch_destroy(hgks_batch b);
+hgks_status hgks_batch_set_uniform_grid(hgks_batch b, int32_t i, const double origin_host[3],
+                                        const double length_host[3]);
+hgks_status hgks_batch_set_state(hgks_batch b, int32_t i, const double* q_dev);
+hgks_status hgks_batch_get_state(hgks_batch b, int32_t i, double* q_dev_out);
+/* dt_dev[i] = cfl * min over grid i of h / (|U| + c), as hgks_max_dt;
+ * asynchronous, dt_dev is a device array of n doubles. */
+hgks_status hgks_batch_max_dt(hgks_batch b, double cfl, double* dt_dev);
+/* One step of every grid i with time step dt_dev[i] (device array);
+ * asynchronous. */
+hgks_status hgks_batch_step(hgks_batch b, const double* dt_dev, int32_t n_stages);
+/* Workgroups of the persistent launch of a phase (hgks_phase; a multiple
+ * of 8 between 8 and 65536; 0 restores one workgroup per tile). */
+hgks_status hgks_batch_set_launch(hgks_batch b, int32_t phase, int32_t workgroups);
+/* Captures n_steps steps, each preceded by the per-grid time-step
+ * reduction into the batch's own dt array, into a HIP graph (replacing a
+ * previous one); hgks_batch_replay launches it.  Nothing runs at capture. */
+hgks_status hgks_batch_capture(hgks_batch b, double cfl, int32_t n_steps, int32_t n_stages);
+hgks_status hgks_batch_replay(hgks_batch b);
+/* The batch's own dt array (last reduction of a replayed graph or of
+ * hgks_batch_max_dt with dt_dev = NULL); synchronises. */
+hgks_status hgks_batch_dt(hgks_batch b, double* dt_host);
+/* out_host[5 i + v] = sum over grid i of |Omega| Q_v; synchronises. */
+hgks_status hgks_batch_totals(hgks_batch b, double* out_host);
+hgks_status hgks_batch_sync(hgks_batch b);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* hgks_last_error(void);
 

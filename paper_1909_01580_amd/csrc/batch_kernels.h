@@ -1,0 +1,178 @@
+// Batched stage: many independent periodic box grids of uneven sizes
+// advanced together, one persistent launch per phase (reconstruction,
+// fallback test, face flux, update) and per-grid time steps read from
+// device memory, so that whole steps can be captured in a HIP graph.
+//
+// Work is cut into tiles of 256 items (cells, or 64 faces x 4 Gauss
+// points); every grid owns a contiguous range of tiles.  A persistent
+// launch of P workgroups (P a multiple of 8) gives each of the eight XCDs
+// one contiguous eighth of the tile range, walked by its P/8 workgroups
+// with stride P/8, so that neighbouring tiles of a grid share an L2.
+#pragma once
+
+#include "box_kernels.h"
+
+namespace hgks {
+
+template <typename TC>
+struct BatchGrid {
+  BoxGrid G;
+  WenoParams<TC> P;
+  GasParams<TC> gp;
+  size_t N, NF[3];
+  size_t q_off;        // doubles: start of the grid's [5][N] state
+  size_t coef_off;     // TC: start of the grid's [5][10][N] coefficients
+  size_t mask_off;     // uint32: start of the grid's [N] masks
+  size_t face_off[3];  // TC: start of the grid's [10][NF_d] face sums
+  unsigned t_cell;     // first cell tile
+  unsigned t_flux;     // first flux tile
+  unsigned nt_cell;    // cell tiles
+  unsigned nt_flux[3]; // flux tiles per direction
+};
+
+// Grid owning tile t (binary search over the first-tile table).
+template <typename TC, bool FLUX>
+__device__ __forceinline__ int batch_grid_of(const BatchGrid<TC>* __restrict__ B, int ng, unsigned t) {
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const unsigned first = FLUX ? B[mid].t_flux : B[mid].t_cell;
+    if (first <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent tile walk: XCD x = blockIdx % 8 takes tiles
+// [x * chunk, (x + 1) * chunk), its workgroups striding by P / 8.
+struct TileWalk {
+  unsigned t, end, stride;
+  __device__ __forceinline__ TileWalk(unsigned ntiles) {
+    const unsigned P = gridDim.x, per = P >> 3;
+    const unsigned x = blockIdx.x & 7u, w = blockIdx.x >> 3;
+    const unsigned chunk = (ntiles + 7u) >> 3;
+    t = x * chunk + w;
+    end = min(ntiles, (x + 1) * chunk);
+    stride = per;
+  }
+};
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
+                                                        const double* __restrict__ q, TC* __restrict__ coef,
+                                                        uint32_t* __restrict__ mask, TC margin, TC gm1) {
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
+    const int g = batch_grid_of<TC, false>(B, ng, w.t);
+    const size_t idx = (size_t)(w.t - B[g].t_cell) * kBlock + threadIdx.x;
+    if (idx < B[g].N)
+      recon_box_cell(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin, gm1,
+                     B[g].N, idx);
+  }
+}
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
+                                                        const double* __restrict__ q, uint32_t* __restrict__ mask,
+                                                        TC gm1) {
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
+    const int g = batch_grid_of<TC, false>(B, ng, w.t);
+    const size_t idx = (size_t)(w.t - B[g].t_cell) * kBlock + threadIdx.x;
+    if (idx < B[g].N && mask[B[g].mask_off + idx] == kNeedsCheck)
+      posit_exact_box_cell(q + B[g].q_off, mask + B[g].mask_off, B[g].G, gm1, idx);
+  }
+}
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
+                                                       const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
+                                                       TC* __restrict__ face, const double* __restrict__ dt) {
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
+    const int g = batch_grid_of<TC, true>(B, ng, w.t);
+    const BatchGrid<TC>& b = B[g];
+    unsigned lt = w.t - b.t_flux;
+    const TC dtg = TC(dt[g]);
+    const TC* cf = coef + b.coef_off;
+    const uint32_t* mk = mask + b.mask_off;
+    if (lt < b.nt_flux[0]) {
+      flux_box_face<0>(cf, mk, face + b.face_off[0], b.G, b.gp, dtg, b.N, b.NF[0], (size_t)lt * kBlock + threadIdx.x);
+    } else if ((lt -= b.nt_flux[0]) < b.nt_flux[1]) {
+      flux_box_face<1>(cf, mk, face + b.face_off[1], b.G, b.gp, dtg, b.N, b.NF[1], (size_t)lt * kBlock + threadIdx.x);
+    } else {
+      lt -= b.nt_flux[1];
+      flux_box_face<2>(cf, mk, face + b.face_off[2], b.G, b.gp, dtg, b.N, b.NF[2], (size_t)lt * kBlock + threadIdx.x);
+    }
+  }
+}
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_update(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
+                                                         double* __restrict__ q, double* __restrict__ qs,
+                                                         double* __restrict__ acc, const TC* __restrict__ face,
+                                                         const double* __restrict__ dt, int mode) {
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
+    const int g = batch_grid_of<TC, false>(B, ng, w.t);
+    const BatchGrid<TC>& b = B[g];
+    const size_t idx = (size_t)(w.t - b.t_cell) * kBlock + threadIdx.x;
+    if (idx < b.N)
+      update_box_cell(q + b.q_off, qs + b.q_off, acc + b.q_off, face + b.face_off[0], face + b.face_off[1],
+                      face + b.face_off[2], b.G, dt[g], mode, b.N, idx);
+  }
+}
+
+// Per-tile minimum of h / (|U| + c), then per-grid dt = cfl * minimum.
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_dt_part(const BatchGrid<TC>* __restrict__ B, int ng,
+                                                          unsigned ntiles, const double* __restrict__ q, double gamma,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
+    const int g = batch_grid_of<TC, false>(B, ng, w.t);
+    const BatchGrid<TC>& b = B[g];
+    const size_t idx = (size_t)(w.t - b.t_cell) * kBlock + threadIdx.x;
+    double v = 1e300;
+    if (idx < b.N) {
+      const double* qg = q + b.q_off;
+      const size_t N = b.N;
+      const double rho = qg[idx];
+      const double u = qg[N + idx] / rho, v1 = qg[2 * N + idx] / rho, v2 = qg[3 * N + idx] / rho;
+      const double p = (gamma - 1.0) * (qg[4 * N + idx] - 0.5 * rho * (u * u + v1 * v1 + v2 * v2));
+      const double c = sqrt(gamma * p / rho);
+      const double h = fmin(fmin(1.0 / b.G.inv_dx[0], 1.0 / b.G.inv_dx[1]), 1.0 / b.G.inv_dx[2]);
+      v = h / (sqrt(u * u + v1 * v1 + v2 * v2) + c);
+      if (!(v > 0.0)) v = -1.0;
+    }
+    const double r = block_reduce(v, sh, MinOp());
+    if (threadIdx.x == 0) part[w.t] = r;
+    __syncthreads();
+  }
+}
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_dt_final(const BatchGrid<TC>* __restrict__ B,
+                                                           const double* __restrict__ part, double cfl,
+                                                           double* __restrict__ dt) {
+  __shared__ double sh[kBlock];
+  const int g = blockIdx.x;
+  double v = 1e300;
+  for (unsigned t = threadIdx.x; t < B[g].nt_cell; t += kBlock) v = fmin(v, part[B[g].t_cell + t]);
+  const double r = block_reduce(v, sh, MinOp());
+  if (threadIdx.x == 0) dt[g] = cfl * r;
+}
+
+// sum |Omega| Q_v per grid, fixed order.
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_totals(const BatchGrid<TC>* __restrict__ B,
+                                                         const double* __restrict__ q, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  const int g = blockIdx.x;
+  const BatchGrid<TC>& b = B[g];
+  for (int v = 0; v < 5; ++v) {
+    double s = 0.0;
+    for (size_t i = threadIdx.x; i < b.N; i += kBlock) s += q[b.q_off + v * b.N + i];
+    const double r = block_reduce(s, sh, SumOp());
+    if (threadIdx.x == 0) out[g * 5 + v] = r * b.G.vol;
+    __syncthreads();
+  }
+}
+
+}  // namespace hgks

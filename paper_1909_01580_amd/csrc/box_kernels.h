@@ -51,15 +51,11 @@ __device__ __forceinline__ int rec_index(const BoxGrid& G, int ax, int i) {
 }
 
 // ---------------------------------------------------------------- recon
+// Reconstruction of reconstruction-box cell idx (< NR).
 template <typename TC>
-__global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__ q, TC* __restrict__ coef,
-                                                      uint32_t* __restrict__ mask, BoxGrid G,
-                                                      WenoParams<TC> P, TC margin, TC gm1, size_t NR,
-                                                      unsigned nblk) {
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b >= nblk) return;
-  const size_t idx = (size_t)b * kBlock + threadIdx.x;
-  if (idx >= NR) return;
+__device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC* __restrict__ coef,
+                                               uint32_t* __restrict__ mask, const BoxGrid& G,
+                                               const WenoParams<TC>& P, TC margin, TC gm1, size_t NR, size_t idx) {
   const int ri = (int)(idx % G.nr[0]);
   const int rj = (int)((idx / G.nr[0]) % G.nr[1]);
   const int rk = (int)(idx / ((size_t)G.nr[0] * G.nr[1]));
@@ -118,14 +114,23 @@ __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__
   mask[idx] = safe ? 0u : kNeedsCheck;
 }
 
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__ q, TC* __restrict__ coef,
+                                                      uint32_t* __restrict__ mask, BoxGrid G,
+                                                      WenoParams<TC> P, TC margin, TC gm1, size_t NR,
+                                                      unsigned nblk) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nblk) return;
+  const size_t idx = (size_t)b * kBlock + threadIdx.x;
+  if (idx >= NR) return;
+  recon_box_cell(q, coef, mask, G, P, margin, gm1, NR, idx);
+}
+
 // Exact fallback test (Sec. 4): for every Gauss point of the cell, any of
 // the 25 polynomials with rho <= 0 or p < 0 marks the point.
 template <typename TC>
-__global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __restrict__ q, uint32_t* __restrict__ mask,
-                                                            BoxGrid G, TC gm1, size_t NR) {
-  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= NR) return;
-  if (mask[idx] != kNeedsCheck) return;
+__device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ q, uint32_t* __restrict__ mask,
+                                                     const BoxGrid& G, TC gm1, size_t idx) {
   const int ri = (int)(idx % G.nr[0]);
   const int rj = (int)((idx / G.nr[0]) % G.nr[1]);
   const int rk = (int)(idx / ((size_t)G.nr[0] * G.nr[1]));
@@ -187,6 +192,15 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __rest
     }
   }
   mask[idx] = bits;
+}
+
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __restrict__ q, uint32_t* __restrict__ mask,
+                                                            BoxGrid G, TC gm1, size_t NR) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= NR) return;
+  if (mask[idx] != kNeedsCheck) return;
+  posit_exact_box_cell(q, mask, G, gm1, idx);
 }
 
 // ---------------------------------------------------------------- flux
@@ -311,12 +325,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_box(const TC* __restrict__ coef
 // mode 1: first stage: qs = q + dt/2 L + dt^2/8 dL, acc = q + dt L + dt^2/6 dL
 // mode 2: second stage: q = acc + dt^2/3 dL(q*)
 template <typename TF>
-__global__ void __launch_bounds__(kBlock) k_update_box(double* __restrict__ q, double* __restrict__ qs,
-                                                       double* __restrict__ acc, const TF* __restrict__ fx,
-                                                       const TF* __restrict__ fy, const TF* __restrict__ fz,
-                                                       BoxGrid G, double dt, int mode, size_t N) {
-  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= N) return;
+__device__ __forceinline__ void update_box_cell(double* __restrict__ q, double* __restrict__ qs,
+                                                double* __restrict__ acc, const TF* __restrict__ fx,
+                                                const TF* __restrict__ fy, const TF* __restrict__ fz,
+                                                const BoxGrid& G, double dt, int mode, size_t N, size_t idx) {
   const int c[3] = {(int)(idx % G.n[0]), (int)((idx / G.n[0]) % G.n[1]), (int)(idx / ((size_t)G.n[0] * G.n[1]))};
   const TF* fs[3] = {fx, fy, fz};
   double R[10];
@@ -349,6 +361,16 @@ __global__ void __launch_bounds__(kBlock) k_update_box(double* __restrict__ q, d
       q[o] = acc[o] + dt * dt / 3.0 * dL;
     }
   }
+}
+
+template <typename TF>
+__global__ void __launch_bounds__(kBlock) k_update_box(double* __restrict__ q, double* __restrict__ qs,
+                                                       double* __restrict__ acc, const TF* __restrict__ fx,
+                                                       const TF* __restrict__ fy, const TF* __restrict__ fz,
+                                                       BoxGrid G, double dt, int mode, size_t N) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  update_box_cell(q, qs, acc, fx, fy, fz, G, dt, mode, N, idx);
 }
 
 // ---------------------------------------------------------------- reductions

@@ -14,6 +14,7 @@
 #include "../../include/hgks.h"
 #include "box_kernels.h"
 #include "hex_kernels.h"
+#include "batch_kernels.h"
 
 using namespace hgks;
 
@@ -658,5 +659,377 @@ hgks_status hgks_profile_end(hgks_ctx c, double ms[5], int64_t launches[5]) {
 }
 
 const char* hgks_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ================================================================ batches
+struct hgks_batch_s {
+  hgks_config base;
+  std::vector<hgks_config> cfgs;
+  int ng = 0;
+  hipStream_t stream;
+  char* ws = nullptr;
+  size_t desc = 0, q = 0, qs = 0, acc = 0, coef = 0, mask = 0, face = 0, part = 0, dt = 0, tot = 0, total = 0;
+  size_t tc = 8;
+  unsigned tiles_cell = 0, tiles_flux = 0;
+  std::vector<BatchGrid<double>> gd;  // host copies of the descriptors
+  std::vector<BatchGrid<float>> gf;
+  std::vector<bool> grid_set, state_set;
+  int wg[HGKS_NPHASES] = {0, 0, 0, 0, 0};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hgks_status sticky = HGKS_OK;
+  bool mixed() const { return base.precision == HGKS_MIXED; }
+};
+
+namespace {
+
+hgks_status bcheck(hgks_batch b, hipError_t e, const char* what) {
+  if (e == hipSuccess) return HGKS_OK;
+  b->sticky = HGKS_EDEVICE;
+  return fail(HGKS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+hgks_status busable(hgks_batch b) {
+  if (!b) return fail(HGKS_EINVAL, "null batch");
+  if (b->sticky != HGKS_OK) return fail(b->sticky, "batch has a previous device error");
+  return HGKS_OK;
+}
+
+bool batch_compatible(const hgks_config& a, const hgks_config& c) {
+  if (!valid_config(&c) || c.moving) return false;
+  for (int d = 0; d < 3; ++d)
+    if (c.bc[d] != HGKS_BC_PERIODIC) return false;
+  return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&
+         c.tau_eps == a.tau_eps && c.tau_C == a.tau_C && c.precision == a.precision;
+}
+
+// Offsets of every arena and the per-grid descriptors (without the grid
+// spacing, set later).
+template <typename TC>
+size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<BatchGrid<TC>>& G) {
+  G.assign(n, BatchGrid<TC>());
+  size_t N = 0, F = 0;
+  unsigned tc = 0, tf = 0;
+  for (int i = 0; i < n; ++i) {
+    const Dims D = make_dims(&cfgs[i]);
+    BatchGrid<TC>& g = G[i];
+    std::memset(&g, 0, sizeof g);
+    for (int d = 0; d < 3; ++d) {
+      g.G.n[d] = D.n[d];
+      g.G.g[d] = 0;
+      g.G.nr[d] = D.n[d];
+      g.G.per[d] = 1;
+      for (int e = 0; e < 3; ++e) g.G.nf[d][e] = D.nf[d][e];
+    }
+    g.N = D.N;
+    g.q_off = 5 * N;
+    g.coef_off = 50 * N;
+    g.mask_off = N;
+    g.t_cell = tc;
+    g.t_flux = tf;
+    g.nt_cell = blocks_for(D.N);
+    for (int d = 0; d < 3; ++d) {
+      g.NF[d] = D.NF[d];
+      g.face_off[d] = F;
+      F += 10 * D.NF[d];
+      g.nt_flux[d] = blocks_for(4 * D.NF[d]);
+      tf += g.nt_flux[d];
+    }
+    tc += g.nt_cell;
+    N += D.N;
+    g.gp = gas_params<TC>(cfgs[i]);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  if (b) {
+    b->tiles_cell = tc;
+    b->tiles_flux = tf;
+  }
+  const size_t desc = take(n * sizeof(BatchGrid<TC>));
+  const size_t q = take(5 * N * 8), qs = take(5 * N * 8), acc = take(5 * N * 8);
+  const size_t coef = take(50 * N * sizeof(TC)), mask = take(N * 4), face = take(F * sizeof(TC));
+  const size_t part = take((size_t)tc * 8), dt = take(n * 8), tot = take(5 * n * 8);
+  if (b) {
+    b->desc = desc; b->q = q; b->qs = qs; b->acc = acc; b->coef = coef; b->mask = mask; b->face = face;
+    b->part = part; b->dt = dt; b->tot = tot; b->total = off;
+  }
+  return off;
+}
+
+template <typename TC>
+std::vector<BatchGrid<TC>>& batch_desc(hgks_batch b);
+template <>
+std::vector<BatchGrid<double>>& batch_desc<double>(hgks_batch b) { return b->gd; }
+template <>
+std::vector<BatchGrid<float>>& batch_desc<float>(hgks_batch b) { return b->gf; }
+
+template <typename TC>
+hgks_status batch_upload(hgks_batch b) {
+  auto& G = batch_desc<TC>(b);
+  if (hgks_status s = bcheck(b, hipMemcpyAsync(b->ws + b->desc, G.data(), G.size() * sizeof(BatchGrid<TC>),
+                                               hipMemcpyHostToDevice, b->stream),
+                             "upload descriptors"))
+    return s;
+  return bcheck(b, hipStreamSynchronize(b->stream), "upload descriptors");
+}
+
+unsigned batch_wg(hgks_batch b, int phase, unsigned tiles) {
+  const int w = b->wg[phase];
+  if (w <= 0) return pad8(tiles);
+  return (unsigned)w;
+}
+
+template <typename TC>
+hgks_status batch_dt(hgks_batch b, double cfl, double* dt_dev) {
+  const BatchGrid<TC>* D = (const BatchGrid<TC>*)(b->ws + b->desc);
+  double* part = (double*)(b->ws + b->part);
+  hipLaunchKernelGGL((k_batch_dt_part<TC>), dim3(batch_wg(b, HGKS_PHASE_REDUCE, b->tiles_cell)), dim3(kBlock), 0,
+                     b->stream, D, b->ng, b->tiles_cell, (const double*)(b->ws + b->q), b->base.gamma, part);
+  hipLaunchKernelGGL((k_batch_dt_final<TC>), dim3(b->ng), dim3(kBlock), 0, b->stream, D, part, cfl, dt_dev);
+  return bcheck(b, hipGetLastError(), "batch dt");
+}
+
+template <typename TC>
+hgks_status batch_stage(hgks_batch b, const double* qin, const double* dt_dev) {
+  const BatchGrid<TC>* D = (const BatchGrid<TC>*)(b->ws + b->desc);
+  TC* coef = (TC*)(b->ws + b->coef);
+  uint32_t* mask = (uint32_t*)(b->ws + b->mask);
+  const TC margin = sizeof(TC) == 8 ? TC(1e-10) : TC(1e-5);
+  const TC gm1 = TC(b->base.gamma - 1.0);
+  hipLaunchKernelGGL((k_batch_recon<TC>), dim3(batch_wg(b, HGKS_PHASE_RECON, b->tiles_cell)), dim3(kBlock), 0,
+                     b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin, gm1);
+  hipLaunchKernelGGL((k_batch_posit<TC>), dim3(batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell)), dim3(kBlock), 0,
+                     b->stream, D, b->ng, b->tiles_cell, qin, mask, gm1);
+  hipLaunchKernelGGL((k_batch_flux<TC>), dim3(batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux)), dim3(kBlock), 0,
+                     b->stream, D, b->ng, b->tiles_flux, (const TC*)coef, (const uint32_t*)mask,
+                     (TC*)(b->ws + b->face), dt_dev);
+  return bcheck(b, hipGetLastError(), "batch stage");
+}
+
+template <typename TC>
+hgks_status batch_update(hgks_batch b, const double* dt_dev, int mode) {
+  const BatchGrid<TC>* D = (const BatchGrid<TC>*)(b->ws + b->desc);
+  hipLaunchKernelGGL((k_batch_update<TC>), dim3(batch_wg(b, HGKS_PHASE_UPDATE, b->tiles_cell)), dim3(kBlock), 0,
+                     b->stream, D, b->ng, b->tiles_cell, (double*)(b->ws + b->q), (double*)(b->ws + b->qs),
+                     (double*)(b->ws + b->acc), (const TC*)(b->ws + b->face), dt_dev, mode);
+  return bcheck(b, hipGetLastError(), "batch update");
+}
+
+template <typename TC>
+hgks_status batch_step(hgks_batch b, const double* dt_dev, int n_stages) {
+  if (hgks_status s = batch_stage<TC>(b, (const double*)(b->ws + b->q), dt_dev)) return s;
+  if (n_stages == 1) return batch_update<TC>(b, dt_dev, 0);
+  if (hgks_status s = batch_update<TC>(b, dt_dev, 1)) return s;
+  if (hgks_status s = batch_stage<TC>(b, (const double*)(b->ws + b->qs), dt_dev)) return s;
+  return batch_update<TC>(b, dt_dev, 2);
+}
+
+hgks_status batch_ready(hgks_batch b) {
+  if (hgks_status s = busable(b)) return s;
+  for (int i = 0; i < b->ng; ++i) {
+    if (!b->grid_set[i]) return fail(HGKS_ESTATE, "grid %d has no box", i);
+    if (!b->state_set[i]) return fail(HGKS_ESTATE, "grid %d has no state", i);
+  }
+  return HGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hgks_status hgks_batch_workspace_size(const hgks_config* cfgs, int32_t n, size_t* bytes) {
+  if (!cfgs || n < 1 || !bytes) return fail(HGKS_EINVAL, "bad arguments");
+  for (int i = 0; i < n; ++i)
+    if (!batch_compatible(cfgs[0], cfgs[i])) return fail(HGKS_EINVAL, "grid %d: incompatible configuration", i);
+  if (cfgs[0].precision == HGKS_MIXED) {
+    std::vector<BatchGrid<float>> G;
+    *bytes = batch_layout<float>(cfgs, n, nullptr, G);
+  } else {
+    std::vector<BatchGrid<double>> G;
+    *bytes = batch_layout<double>(cfgs, n, nullptr, G);
+  }
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_create(const hgks_config* cfgs, int32_t n, void* ws, size_t bytes, hgks_batch* out) {
+  if (!out) return fail(HGKS_EINVAL, "null output");
+  *out = nullptr;
+  size_t need = 0;
+  if (hgks_status s = hgks_batch_workspace_size(cfgs, n, &need)) return s;
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(HGKS_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < need) return fail(HGKS_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
+  hgks_batch b = new (std::nothrow) hgks_batch_s;
+  if (!b) return fail(HGKS_ENOMEM, "host allocation failed");
+  b->base = cfgs[0];
+  b->cfgs.assign(cfgs, cfgs + n);
+  b->ng = n;
+  b->stream = (hipStream_t)cfgs[0].stream;
+  b->ws = (char*)ws;
+  b->tc = b->mixed() ? 4 : 8;
+  if (b->mixed())
+    batch_layout<float>(cfgs, n, b, b->gf);
+  else
+    batch_layout<double>(cfgs, n, b, b->gd);
+  b->grid_set.assign(n, false);
+  b->state_set.assign(n, false);
+  *out = b;
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_destroy(hgks_batch b) {
+  if (b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+  }
+  delete b;
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_set_uniform_grid(hgks_batch b, int32_t i, const double origin[3], const double length[3]) {
+  if (hgks_status s = busable(b)) return s;
+  if (i < 0 || i >= b->ng || !origin || !length) return fail(HGKS_EINVAL, "bad grid index or box");
+  const int n[3] = {b->cfgs[i].nx, b->cfgs[i].ny, b->cfgs[i].nz};
+  double dx[3], vol = 1.0, inv[3];
+  for (int d = 0; d < 3; ++d) {
+    if (!(length[d] > 0.0)) return fail(HGKS_EINVAL, "bad box");
+    dx[d] = length[d] / n[d];
+    inv[d] = 1.0 / dx[d];
+    vol *= dx[d];
+  }
+  auto set = [&](auto& G) {
+    using TC = std::decay_t<decltype(G[0].P.eps)>;
+    for (int d = 0; d < 3; ++d) G[i].G.inv_dx[d] = inv[d];
+    G[i].G.vol = vol;
+    G[i].P = weno_params<TC>(b->cfgs[i], dx);
+  };
+  hgks_status s;
+  if (b->mixed()) {
+    set(b->gf);
+    s = batch_upload<float>(b);
+  } else {
+    set(b->gd);
+    s = batch_upload<double>(b);
+  }
+  if (s) return s;
+  b->grid_set[i] = true;
+  return HGKS_OK;
+}
+
+static size_t batch_qoff(hgks_batch b, int i) { return b->mixed() ? b->gf[i].q_off : b->gd[i].q_off; }
+static size_t batch_N(hgks_batch b, int i) { return b->mixed() ? b->gf[i].N : b->gd[i].N; }
+
+hgks_status hgks_batch_set_state(hgks_batch b, int32_t i, const double* q_dev) {
+  if (hgks_status s = busable(b)) return s;
+  if (i < 0 || i >= b->ng || !q_dev) return fail(HGKS_EINVAL, "bad grid index or state");
+  double* dst = (double*)(b->ws + b->q) + batch_qoff(b, i);
+  if (hgks_status s = bcheck(b, hipMemcpyAsync(dst, q_dev, 5 * batch_N(b, i) * 8, hipMemcpyDeviceToDevice, b->stream),
+                             "copy state"))
+    return s;
+  b->state_set[i] = true;
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_get_state(hgks_batch b, int32_t i, double* q_dev_out) {
+  if (hgks_status s = busable(b)) return s;
+  if (i < 0 || i >= b->ng || !q_dev_out) return fail(HGKS_EINVAL, "bad grid index or output");
+  const double* src = (const double*)(b->ws + b->q) + batch_qoff(b, i);
+  return bcheck(b, hipMemcpyAsync(q_dev_out, src, 5 * batch_N(b, i) * 8, hipMemcpyDeviceToDevice, b->stream),
+                "copy state out");
+}
+
+hgks_status hgks_batch_max_dt(hgks_batch b, double cfl, double* dt_dev) {
+  if (hgks_status s = batch_ready(b)) return s;
+  if (!(cfl > 0.0)) return fail(HGKS_EINVAL, "bad cfl");
+  double* out = dt_dev ? dt_dev : (double*)(b->ws + b->dt);
+  return b->mixed() ? batch_dt<float>(b, cfl, out) : batch_dt<double>(b, cfl, out);
+}
+
+hgks_status hgks_batch_step(hgks_batch b, const double* dt_dev, int32_t n_stages) {
+  if (hgks_status s = batch_ready(b)) return s;
+  if (!dt_dev || (n_stages != 1 && n_stages != 2)) return fail(HGKS_EINVAL, "bad dt array or n_stages");
+  return b->mixed() ? batch_step<float>(b, dt_dev, n_stages) : batch_step<double>(b, dt_dev, n_stages);
+}
+
+hgks_status hgks_batch_set_launch(hgks_batch b, int32_t phase, int32_t workgroups) {
+  if (hgks_status s = busable(b)) return s;
+  if (phase < 0 || phase >= HGKS_NPHASES) return fail(HGKS_EINVAL, "bad phase");
+  if (workgroups != 0 && (workgroups < 8 || workgroups > 65536 || (workgroups & 7)))
+    return fail(HGKS_EINVAL, "workgroups must be 0 or a multiple of 8 in [8, 65536]");
+  b->wg[phase] = workgroups;
+  return HGKS_OK;
+}
+
+hgks_status hgks_batch_capture(hgks_batch b, double cfl, int32_t n_steps, int32_t n_stages) {
+  if (hgks_status s = batch_ready(b)) return s;
+  if (!(cfl > 0.0) || n_steps < 1 || (n_stages != 1 && n_stages != 2)) return fail(HGKS_EINVAL, "bad arguments");
+  if (b->stream == nullptr) return fail(HGKS_EINVAL, "capture needs a non-default stream");
+  if (b->exec) {
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  if (hgks_status s = bcheck(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture"))
+    return s;
+  double* dt = (double*)(b->ws + b->dt);
+  hgks_status st = HGKS_OK;
+  for (int k = 0; k < n_steps && st == HGKS_OK; ++k) {
+    st = b->mixed() ? batch_dt<float>(b, cfl, dt) : batch_dt<double>(b, cfl, dt);
+    if (st == HGKS_OK) st = b->mixed() ? batch_step<float>(b, dt, n_stages) : batch_step<double>(b, dt, n_stages);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (st != HGKS_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (hgks_status s = bcheck(b, e, "end capture")) return s;
+  b->graph = g;
+  return bcheck(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "instantiate graph");
+}
+
+hgks_status hgks_batch_replay(hgks_batch b) {
+  if (hgks_status s = batch_ready(b)) return s;
+  if (!b->exec) return fail(HGKS_ESTATE, "no captured graph");
+  return bcheck(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
+}
+
+hgks_status hgks_batch_dt(hgks_batch b, double* dt_host) {
+  if (hgks_status s = busable(b)) return s;
+  if (!dt_host) return fail(HGKS_EINVAL, "null output");
+  if (hgks_status s = bcheck(b, hipMemcpyAsync(dt_host, b->ws + b->dt, b->ng * 8, hipMemcpyDeviceToHost, b->stream),
+                             "copy dt"))
+    return s;
+  return bcheck(b, hipStreamSynchronize(b->stream), "synchronise");
+}
+
+hgks_status hgks_batch_totals(hgks_batch b, double* out_host) {
+  if (hgks_status s = batch_ready(b)) return s;
+  if (!out_host) return fail(HGKS_EINVAL, "null output");
+  double* tot = (double*)(b->ws + b->tot);
+  if (b->mixed())
+    hipLaunchKernelGGL((k_batch_totals<float>), dim3(b->ng), dim3(kBlock), 0, b->stream,
+                       (const BatchGrid<float>*)(b->ws + b->desc), (const double*)(b->ws + b->q), tot);
+  else
+    hipLaunchKernelGGL((k_batch_totals<double>), dim3(b->ng), dim3(kBlock), 0, b->stream,
+                       (const BatchGrid<double>*)(b->ws + b->desc), (const double*)(b->ws + b->q), tot);
+  if (hgks_status s = bcheck(b, hipGetLastError(), "totals")) return s;
+  if (hgks_status s = bcheck(b, hipMemcpyAsync(out_host, tot, 5 * b->ng * 8, hipMemcpyDeviceToHost, b->stream),
+                             "copy totals"))
+    return s;
+  return bcheck(b, hipStreamSynchronize(b->stream), "synchronise");
+}
+
+hgks_status hgks_batch_sync(hgks_batch b) {
+  if (hgks_status s = busable(b)) return s;
+  return bcheck(b, hipStreamSynchronize(b->stream), "synchronise");
+}
 
 }  // extern "C"

@@ -27,6 +27,10 @@ EXPORTS = [
     "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_totals",
     "hgks_check", "hgks_debug_gp_states", "hgks_debug_face_flux", "hgks_sync",
     "hgks_last_error", "hgks_profile_begin", "hgks_profile_end",
+    "hgks_batch_workspace_size", "hgks_batch_create", "hgks_batch_destroy",
+    "hgks_batch_set_uniform_grid", "hgks_batch_set_state", "hgks_batch_get_state",
+    "hgks_batch_max_dt", "hgks_batch_step", "hgks_batch_set_launch", "hgks_batch_capture",
+    "hgks_batch_replay", "hgks_batch_dt", "hgks_batch_totals", "hgks_batch_sync",
 ]
 PHASES = ("recon", "fallback", "flux", "update", "reduce")
 
@@ -81,6 +85,20 @@ def load():
         "hgks_sync": [P],
         "hgks_profile_begin": [P],
         "hgks_profile_end": [P, DP, ctypes.POINTER(ctypes.c_int64)],
+        "hgks_batch_workspace_size": [ctypes.POINTER(hgks_config), I32, ctypes.POINTER(SZ)],
+        "hgks_batch_create": [ctypes.POINTER(hgks_config), I32, P, SZ, ctypes.POINTER(P)],
+        "hgks_batch_destroy": [P],
+        "hgks_batch_set_uniform_grid": [P, I32, DP, DP],
+        "hgks_batch_set_state": [P, I32, P],
+        "hgks_batch_get_state": [P, I32, P],
+        "hgks_batch_max_dt": [P, D, P],
+        "hgks_batch_step": [P, P, I32],
+        "hgks_batch_set_launch": [P, I32, I32],
+        "hgks_batch_capture": [P, D, I32, I32],
+        "hgks_batch_replay": [P],
+        "hgks_batch_dt": [P, DP],
+        "hgks_batch_totals": [P, DP],
+        "hgks_batch_sync": [P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -288,3 +306,146 @@ class Context:
 
     def profile_end(self):
         return hgks_profile_end(self.h)
+
+
+# ------------------------------------------------------------ batches
+def hgks_batch_workspace_size(cfgs):
+    arr = (hgks_config * len(cfgs))(*cfgs)
+    n = ctypes.c_size_t()
+    _check(load().hgks_batch_workspace_size(arr, len(cfgs), ctypes.byref(n)))
+    return n.value
+
+
+def hgks_batch_create(cfgs, workspace):
+    arr = (hgks_config * len(cfgs))(*cfgs)
+    h = ctypes.c_void_p()
+    _check(load().hgks_batch_create(arr, len(cfgs), ctypes.c_void_p(workspace.data_ptr()),
+                                    workspace.numel() * workspace.element_size(), ctypes.byref(h)))
+    return h
+
+
+def hgks_batch_destroy(h):
+    _check(load().hgks_batch_destroy(h))
+
+
+def hgks_batch_set_uniform_grid(h, i, origin, length):
+    _check(load().hgks_batch_set_uniform_grid(h, i, _arr3(origin), _arr3(length)))
+
+
+def hgks_batch_set_state(h, i, q):
+    _check(load().hgks_batch_set_state(h, i, _dptr(q)))
+
+
+def hgks_batch_get_state(h, i, out):
+    _check(load().hgks_batch_get_state(h, i, _dptr(out)))
+
+
+def hgks_batch_max_dt(h, cfl, dt=None):
+    _check(load().hgks_batch_max_dt(h, cfl, None if dt is None else _dptr(dt)))
+
+
+def hgks_batch_step(h, dt, n_stages=2):
+    _check(load().hgks_batch_step(h, _dptr(dt), n_stages))
+
+
+def hgks_batch_set_launch(h, phase, workgroups):
+    _check(load().hgks_batch_set_launch(h, phase, workgroups))
+
+
+def hgks_batch_capture(h, cfl, n_steps, n_stages=2):
+    _check(load().hgks_batch_capture(h, cfl, n_steps, n_stages))
+
+
+def hgks_batch_replay(h):
+    _check(load().hgks_batch_replay(h))
+
+
+def hgks_batch_dt(h, n):
+    out = (ctypes.c_double * n)()
+    _check(load().hgks_batch_dt(h, out))
+    return list(out)
+
+
+def hgks_batch_totals(h, n):
+    out = (ctypes.c_double * (5 * n))()
+    _check(load().hgks_batch_totals(h, out))
+    return [list(out[5 * i:5 * i + 5]) for i in range(n)]
+
+
+def hgks_batch_sync(h):
+    _check(load().hgks_batch_sync(h))
+
+
+class Batch:
+    """Independent periodic box grids advanced together.  ``grids`` is a
+    list of dicts with keys n (nx, ny, nz), length (Lx, Ly, Lz) and mu."""
+
+    def __init__(self, grids, gamma=1.4, precision="mixed", device="cuda:0", stream=None, **kw):
+        self.device = torch.device(device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.device)
+        self.stream = stream
+        cfgs = []
+        for g in grids:
+            cfg = hgks_default_config(*g["n"])
+            cfg.gamma, cfg.mu = gamma, g.get("mu", 0.0)
+            cfg.precision = PREC[precision]
+            for k, v in kw.items():
+                setattr(cfg, k, v)
+            cfg.stream = ctypes.c_void_p(stream.cuda_stream)
+            cfgs.append(cfg)
+        self.cfgs = cfgs
+        self.grids = [dict(g) for g in grids]
+        self.n = len(grids)
+        nbytes = hgks_batch_workspace_size(cfgs)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.h = hgks_batch_create(cfgs, self._ws)
+        for i, g in enumerate(grids):
+            hgks_batch_set_uniform_grid(self.h, i, g.get("origin", (0.0, 0.0, 0.0)), g["length"])
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.hgks_batch_destroy(h)
+            self.h = None
+
+    def shape(self, i):
+        nx, ny, nz = self.grids[i]["n"]
+        return (5, nz, ny, nx)
+
+    def set_state(self, i, q):
+        # q was produced on the caller's stream; the batch copies on its own.
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        hgks_batch_set_state(self.h, i, q)
+
+    def get_state(self, i):
+        out = torch.empty(self.shape(i), dtype=torch.float64, device=self.device)
+        hgks_batch_get_state(self.h, i, out)
+        hgks_batch_sync(self.h)
+        return out
+
+    def max_dt(self, cfl, dt=None):
+        hgks_batch_max_dt(self.h, cfl, dt)
+
+    def step(self, dt, n_stages=2):
+        hgks_batch_step(self.h, dt, n_stages)
+
+    def set_launch(self, phase, workgroups):
+        hgks_batch_set_launch(self.h, phase, workgroups)
+
+    def capture(self, cfl, n_steps, n_stages=2):
+        hgks_batch_capture(self.h, cfl, n_steps, n_stages)
+
+    def replay(self):
+        hgks_batch_replay(self.h)
+
+    def dt(self):
+        return hgks_batch_dt(self.h, self.n)
+
+    def totals(self):
+        return hgks_batch_totals(self.h, self.n)
+
+    def sync(self):
+        hgks_batch_sync(self.h)
