@@ -91,6 +91,61 @@ def run_gpu(n, steps, warmup, precision, cfl=0.35, record_first=False):
             "first": first, "q0": q0.cpu().numpy()}
 
 
+def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2):
+    """48 independent periodic problems of uneven sizes (32..96 per axis,
+    about 1.0e7 cells): autotuned persistent launches, a HIP graph of
+    ``steps`` steps (per-grid dt reduction inside), timed by replay."""
+    import torch
+    from paper_1909_01580_amd import autotune, hgks
+    from paper_1909_01580_amd import workloads as wl
+
+    problems = wl.batch_problems()
+    grids = [{"n": p["n"], "length": p["length"], "mu": p["mu"]} for p in problems]
+    cells = sum(int(np.prod(g["n"])) for g in grids)
+    b = hgks.Batch(grids, precision=precision)
+    for i, p in enumerate(problems):
+        b.set_state(i, torch.tensor(p["state"], device="cuda:0"))
+    b.sync()
+    table = None
+    if tune:
+        table, _ = autotune.tune(b)
+    b.capture(0.35, steps, 2)
+    b.replay()                      # warm-up replay
+    b.sync()
+    for i, p in enumerate(problems):  # time from the initial states
+        b.set_state(i, torch.tensor(p["state"], device="cuda:0"))
+    b.sync()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(b.stream)
+    b.replay()
+    ev1.record(b.stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    rho = [b.get_state(i)[0].cpu().numpy() for i in range(b.n)]
+    out = {"cells": cells, "grids": len(grids), "ms": ms, "steps": steps,
+           "value": cells * 2 * steps / (ms / 1e3), "launch_table": table, "rho": rho}
+    if unbatched_steps:
+        # The same problems one context at a time (same precision).
+        ctxs = []
+        for i, (g, p) in enumerate(zip(grids, problems)):
+            c = hgks.Context(g["n"], mu=g["mu"], precision=precision)
+            c.set_uniform_grid((0, 0, 0), g["length"])
+            c.set_state(torch.tensor(p["state"], device="cuda:0"))
+            ctxs.append(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(unbatched_steps):
+            for c in ctxs:
+                c.step(c.max_dt(0.35), 2)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["unbatched_value"] = cells * 2 * unbatched_steps / el
+        del ctxs
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def sampled_oracle_error(q0, first, n):
     """Error of the first GPU FP64 step against the oracle at sampled cells:
     the oracle advances a 13^3 periodic patch around each sampled cell (the
@@ -149,6 +204,8 @@ def main():
     ap.add_argument("--precision", choices=("both", "fp64", "mixed"), default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also copy this many MiB once (reference for HBM counters)")
     args = ap.parse_args()
@@ -217,6 +274,23 @@ def main():
             "flux_launch_ms": mx["prof"]["flux"][0] / max(mx["prof"]["flux"][1], 1),
             "roofline_frac_fp32": (flops_per_launch / (mx["prof"]["flux"][0] / max(mx["prof"]["flux"][1], 1) / 1e3)
                                    / 1e12) / PEAK["fp32"],
+        }
+    if not args.no_batched:
+        bm = run_batched(args.batched_steps, "mixed")
+        b64 = run_batched(args.batched_steps, "fp64", tune=False, unbatched_steps=0)
+        num = sum(np.abs(a - r).sum() for a, r in zip(bm["rho"], b64["rho"]))
+        den = sum(np.abs(r).sum() for r in b64["rho"])
+        out["batched"] = {
+            "workload": f"{bm['grids']} periodic Euler/NS boxes, edges in {{32,48,64,96}}, "
+                        f"{bm['cells']} cells, seeded Fourier-mode data, Ma 0.1-0.5",
+            "value": bm["value"], "unit": "cell-stage updates/s", "dtype": "f32 (f64 accumulation)",
+            "ms_per_step": bm["ms"] / bm["steps"], "steps_per_graph": bm["steps"],
+            "unbatched_value": bm.get("unbatched_value"),
+            "speedup_vs_unbatched": bm["value"] / bm["unbatched_value"] if bm.get("unbatched_value") else None,
+            "speedup_vs_plain_fp64": bm["value"] / value if head_prec == "fp64" else None,
+            "fp64_batched_value": b64["value"],
+            "l1_rho_rel_error_vs_fp64": float(num / den),
+            "launch_table": bm["launch_table"],
         }
     if head.get("first") is not None and not args.no_oracle_check:
         err, ns = sampled_oracle_error(head["q0"], head["first"], n)

@@ -183,13 +183,14 @@ def uniform_point(X, Y, Z, gamma=GAMMA):
 
 # ------------------------------------------------------------ batch
 def batch_problems(seed=190901580, count=48, sizes=(32, 48, 64, 96), h=2 * np.pi / 64,
-                   gamma=GAMMA):
+                   gamma=GAMMA, average=False):
     """Independent periodic problems of uneven box sizes with random smooth
     data: four Fourier modes per field with integer wave vectors in
     {-2..2}^3 (fitted to each box) and random phases; rho = 1 + 0.1 phi_rho,
     p = (1 + 0.1 phi_p)/gamma, velocity = Ma phi_u with Ma in [0.1, 0.5];
-    even problems inviscid, odd ones viscous with mu = 1/1600.
-    Returns a list of dicts (n, length, mu, state)."""
+    even problems inviscid, odd ones viscous with mu = 1/1600.  Values are
+    sampled at cell centres (or 3x3x3 Gauss averages with average=True).
+    Returns a list of dicts (n, length, mu, mach, state)."""
     rng = np.random.default_rng(seed)
     out = []
     for g in range(count):
@@ -218,7 +219,12 @@ def batch_problems(seed=190901580, count=48, sizes=(32, 48, 64, 96), h=2 * np.pi
             p = (1.0 + 0.1 * vals["p"]) / gamma
             return conservative(rho, mach * vals["u"], mach * vals["v"], mach * vals["w"], p, gamma)
 
-        state = _box_average(n, (0.0,) * 3, length, point)
+        if average:
+            state = _box_average(n, (0.0,) * 3, length, point)
+        else:
+            cx, cy, cz = _centres(n, (0.0,) * 3, length)
+            Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+            state = np.ascontiguousarray(point(X, Y, Z))
         out.append({"n": n, "length": length, "mu": 0.0 if g % 2 == 0 else 1.0 / 1600.0,
                     "mach": mach, "state": state})
     return out

@@ -1,0 +1,125 @@
+"""Full-size workloads in the launch configuration the benchmark times:
+sampled FP64 parity against the oracle (the oracle advances a 13^3 patch
+around each sampled cell; a two-stage step at a cell depends only on cells
+within 4 of it), mixed-precision tolerance against FP64, conservation and
+positivity.
+
+* 128^3 Taylor-Green vortex (periodic, viscous);
+* 256^3 spherical explosion (outflow, inviscid) with the fallback active;
+* 128^3 moving mesh with a density pulse (properties only: the oracle has
+  no non-periodic hexahedral grids for patches; small-grid parity covers
+  that path).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1909_01580_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hg():
+    from paper_1909_01580_amd import hgks
+    hgks.load()
+    return hgks
+
+
+def patch_step(Q, centre, h, bc, mu, dt):
+    """Oracle step of the 13^3 patch around `centre`; returns the centre."""
+    n = Q.shape[1:][::-1]
+    idx = []
+    for d, c in enumerate(centre):
+        r = np.arange(c - 6, c + 7)
+        idx.append(r % n[d] if bc == "periodic" else np.clip(r, 0, n[d] - 1))
+    patch = Q[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+    prob = oracle.uniform_problem((13, 13, 13), (0, 0, 0), (13 * h,) * 3, bc=("outflow",) * 3,
+                                  params=oracle.Params(mu=mu))
+    return oracle.step(prob, np.ascontiguousarray(patch), dt)[:, 6, 6, 6]
+
+
+def test_taylor_green_128(hg):
+    n = 128
+    q0 = wl.tgv_state(n)
+    h = 2 * np.pi / n
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        ctx = hg.Context((n, n, n), mu=wl.TGV_MU, precision=prec)
+        ctx.set_uniform_grid((-np.pi,) * 3, (2 * np.pi,) * 3)
+        ctx.set_state(torch.tensor(q0, device="cuda:0"))
+        dt0 = ctx.max_dt(0.35)
+        ctx.step(dt0, 2)
+        first = ctx.get_state().cpu().numpy()
+        for _ in range(9):
+            ctx.step(ctx.max_dt(0.35), 2)
+        runs[prec] = (dt0, first, ctx.get_state().cpu().numpy(), ctx.totals())
+    dt0, first, _, tot = runs["fp64"]
+    for c in [(0, 0, 0), (127, 5, 77), (64, 64, 64), (17, 127, 3)]:
+        ref = patch_step(q0, c, h, "periodic", wl.TGV_MU, dt0)
+        got = first[:, c[2], c[1], c[0]]
+        scale = np.array([1.0, 1.0, 1.0, 1.0, np.abs(q0[4]).max()])
+        assert np.all(np.abs(got - ref) / scale < 1e-12), (c, got - ref)
+    r64, rmx = runs["fp64"][2][0], runs["mixed"][2][0]
+    assert np.abs(rmx - r64).sum() / np.abs(r64).sum() < 1e-5
+    tot0 = np.array([q0[v].sum() * h ** 3 for v in range(5)])
+    assert np.abs(np.array(tot) - tot0).max() < 1e-13 * np.abs(tot0).max()
+
+
+def test_explosion_256(hg):
+    n = 256
+    q0 = wl.explosion_state(n)
+    h = 1.0 / n
+    ctx = hg.Context((n, n, n), bc=("outflow",) * 3)
+    ctx.set_uniform_grid((0, 0, 0), (1, 1, 1))
+    ctx.set_state(torch.tensor(q0, device="cuda:0"))
+    dt = ctx.max_dt(0.35)
+    ctx.step(dt, 2)
+    _, fallback = ctx.check()
+    assert fallback > 1000                    # the limiter is exercised
+    first = ctx.get_state().cpu().numpy()
+    i_front = int((0.5 + 0.4) / h)           # on the initial discontinuity
+    for c in [(0, 0, 0), (255, 128, 0), (128, 128, 128), (i_front, 128, 128), (i_front - 1, 131, 127)]:
+        ref = patch_step(q0, c, h, "outflow", 0.0, dt)
+        got = first[:, c[2], c[1], c[0]]
+        scale = np.array([1.0, 1.0, 1.0, 1.0, 2.5])
+        assert np.all(np.abs(got - ref) / scale < 1e-12), (c, got - ref)
+    for _ in range(19):
+        ctx.step(ctx.max_dt(0.35), 2)
+    nonphys, _ = ctx.check()
+    assert nonphys == 0
+    # The mixed path on the same 20 steps stays close in L1 density.
+    mx = hg.Context((n, n, n), bc=("outflow",) * 3, precision="mixed")
+    mx.set_uniform_grid((0, 0, 0), (1, 1, 1))
+    mx.set_state(torch.tensor(q0, device="cuda:0"))
+    for _ in range(20):
+        mx.step(mx.max_dt(0.35), 2)
+    r64 = ctx.get_state()[0]
+    r32 = mx.get_state()[0]
+    assert float((r32 - r64).abs().sum() / r64.abs().sum()) < 1e-4
+
+
+def test_moving_mesh_128(hg):
+    n = 128
+    P = (2.0, 2.0, 2.0)
+
+    def verts(t):
+        return wl.sine_mesh_vertices(n, t, amp=0.05, omega=2 * np.pi)
+    q0 = wl.hex_average(verts(0.0), P, wl.pulse_point)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ctx = hg.Context((n, n, n), moving=True, precision=prec)
+        ctx.set_vertices(torch.tensor(verts(0.0), device="cuda:0"), P)
+        ctx.set_state(torch.tensor(q0, device="cuda:0"))
+        tot0 = np.array(ctx.totals())
+        dt = 0.5 * ctx.max_dt(0.35)
+        t = 0.0
+        for _ in range(10):
+            ctx.set_next_vertices(torch.tensor(verts(t + dt), device="cuda:0"))
+            ctx.step(dt, 2)
+            t += dt
+        out[prec] = ctx.get_state()[0]
+        assert np.abs(np.array(ctx.totals()) - tot0).max() < 1e-13 * np.abs(tot0).max()
+    assert float((out["mixed"] - out["fp64"]).abs().sum() / out["fp64"].abs().sum()) < 1e-5
