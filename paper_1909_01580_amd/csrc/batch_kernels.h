@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __r
 }
 
 template <typename TC>
-__global__ void __launch_bounds__(kBlock) k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
+__global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                        const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                                        TC* __restrict__ face, const double* __restrict__ dt) {
   for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
@@ -93,14 +93,16 @@ __global__ void __launch_bounds__(kBlock) k_batch_flux(const BatchGrid<TC>* __re
     const TC dtg = TC(dt[g]);
     const TC* cf = coef + b.coef_off;
     const uint32_t* mk = mask + b.mask_off;
-    if (lt < b.nt_flux[0]) {
-      flux_box_face<0>(cf, mk, face + b.face_off[0], b.G, b.gp, dtg, b.N, b.NF[0], (size_t)lt * kBlock + threadIdx.x);
-    } else if ((lt -= b.nt_flux[0]) < b.nt_flux[1]) {
-      flux_box_face<1>(cf, mk, face + b.face_off[1], b.G, b.gp, dtg, b.N, b.NF[1], (size_t)lt * kBlock + threadIdx.x);
-    } else {
-      lt -= b.nt_flux[1];
-      flux_box_face<2>(cf, mk, face + b.face_off[2], b.G, b.gp, dtg, b.N, b.NF[2], (size_t)lt * kBlock + threadIdx.x);
+    int D = 0;
+    if (lt >= b.nt_flux[0]) {
+      lt -= b.nt_flux[0];
+      D = 1;
+      if (lt >= b.nt_flux[1]) {
+        lt -= b.nt_flux[1];
+        D = 2;
+      }
     }
+    flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, b.N, b.NF[D], (size_t)lt * kBlock + threadIdx.x, D);
   }
 }
 

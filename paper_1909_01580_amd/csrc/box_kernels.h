@@ -204,47 +204,58 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __rest
 }
 
 // ---------------------------------------------------------------- flux
+// Local frame of a face normal to axis D: local axes (D, A, B) with
+// A = (D + 1) % 3 and B = (D + 2) % 3.  D is uniform over a workgroup, so
+// the plane offsets below are scalar arithmetic and one copy of the flux
+// code serves the three directions.
+struct FaceAxes {
+  int D, A, B;
+};
+
+HGKS_FN FaceAxes face_axes(int D) {
+  return FaceAxes{D, D == 2 ? 0 : D + 1, D == 0 ? 2 : D - 1};
+}
+
 // Value and gradient of the five variables of reconstructed cell `cell` at
-// unit-cube point xi, in the local frame of a face normal to axis D:
-// W = (rho, M_D, M_A, M_B, E), dW[j] = derivative along axis (D, A, B)[j].
-template <int D, typename TC>
-HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, TC xD, TC xA,
-                                            TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
-                                            TC (&dW)[3][5]) {
-  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
-  constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
-  TC xi[3];
-  xi[D] = xD;
-  xi[A] = xA;
-  xi[B] = xB;
+// the point with local coordinates (xD, xA, xB) of the unit cube, in the
+// local frame: W = (rho, M_D, M_A, M_B, E), dW[j] = derivative along local
+// axis j.  The stored quadratic (x, y, z, xx, yy, zz, xy, yz, xz in global
+// axes) is read with its coefficients permuted to the local axes: local
+// linear and square terms of axis j come from global axis (D, A, B)[j], and
+// the local mixed terms (DA, AB, DB) from the global mixed terms 6 + D,
+// 6 + A, 6 + B.
+template <typename TC>
+HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, FaceAxes ax, TC xD, TC xA,
+                         TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5], TC (&dW)[3][5]) {
+  const int lv[5] = {0, 1 + ax.D, 1 + ax.A, 1 + ax.B, 4};
+  const int cp[9] = {ax.D, ax.A, ax.B, 3 + ax.D, 3 + ax.A, 3 + ax.B, 6 + ax.D, 6 + ax.A, 6 + ax.B};
 #pragma unroll
   for (int kk = 0; kk < 5; ++kk) {
     const TC* cv = coef + (size_t)lv[kk] * 10 * NR + cell;
     const TC q0 = cv[0];
     TC c[9];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) c[m] = cv[(size_t)(m + 1) * NR];
+    for (int m = 0; m < 9; ++m) c[m] = cv[(size_t)(cp[m] + 1) * NR];
     TC val, g[3];
-    quad_eval(q0, c, xi[0], xi[1], xi[2], val, g[0], g[1], g[2]);
+    quad_eval(q0, c, xD, xA, xB, val, g[0], g[1], g[2]);
     if (fallback) {
       val = q0;
       g[0] = g[1] = g[2] = TC(0);
     }
     W[kk] = val;
-    dW[0][kk] = g[D] * invd[D];
-    dW[1][kk] = g[A] * invd[A];
-    dW[2][kk] = g[B] * invd[B];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dW[j][kk] = g[j] * invd[j];
   }
 }
 
 // One lane = one Gauss point of one face normal to axis D; the four lanes of
 // a face sum their weighted fluxes with lane shuffles.  tid enumerates
 // (face, Gauss point) with the face index x-fastest.
-template <int D, typename TC>
+template <typename TC>
 __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
-                                              TC dt, size_t NR, size_t NF, size_t tid) {
-  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+                                              TC dt, size_t NR, size_t NF, size_t tid, int D) {
+  const FaceAxes ax = face_axes(D);
   const int gpi = (int)(tid & 3);
   size_t f = tid >> 2;
   const bool live = f < NF;
@@ -263,7 +274,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   }
   const TC xa = (gpi >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
   const TC xb = (gpi & 1) ? TC(kGaussNode) : TC(-kGaussNode);
-  const TC invd[3] = {TC(G.inv_dx[0]), TC(G.inv_dx[1]), TC(G.inv_dx[2])};
+  const TC invd[3] = {TC(G.inv_dx[ax.D]), TC(G.inv_dx[ax.A]), TC(G.inv_dx[ax.B])};
   const bool fbL = (mask[iL] >> (4 * (2 * D + 1) + gpi)) & 1u;
   const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
 
@@ -271,18 +282,19 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   acc_zero(acc);
   {
     TC W[5], dW[3][5];
-    eval_box_gp<D>(coef, NR, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
+    eval_box_gp(coef, NR, iL, ax, TC(0.5), xa, xb, fbL, invd, W, dW);
     side_terms<+1>(W, dW, gp, acc);
   }
+  after_left_side(iR, acc);
   {
     TC W[5], dW[3][5];
-    eval_box_gp<D>(coef, NR, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
+    eval_box_gp(coef, NR, iR, ax, TC(-0.5), xa, xb, fbR, invd, W, dW);
     side_terms<-1>(W, dW, gp, acc);
   }
   TC F[5], dF[5];
   finish_flux(acc, gp, dt, F, dF);
   // Face weight of Eq. (11): Gauss weight 1/4 times the area element.
-  const TC w = TC(0.25 / (G.inv_dx[A] * G.inv_dx[B]));
+  const TC w = TC(0.25 / (G.inv_dx[ax.A] * G.inv_dx[ax.B]));
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     F[i] *= w;
@@ -293,7 +305,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     dF[i] += __shfl_xor(dF[i], 2);
   }
   if (live && gpi == 0) {
-    constexpr int gv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
+    const int gv[5] = {0, 1 + ax.D, 1 + ax.A, 1 + ax.B, 4};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       face[(size_t)gv[i] * NF + f] = F[i];
@@ -305,19 +317,27 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
 // All faces of the three directions in one launch: logical blocks
 // [0, nb0) take x-faces, [nb0, nb0+nb1) y-faces, the rest z-faces.
 template <typename TC>
-__global__ void __launch_bounds__(kBlock) k_flux_box(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
-                                                     TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
-                                                     BoxGrid G, GasParams<TC> gp, TC dt, size_t NR, size_t NF0,
-                                                     size_t NF1, size_t NF2, unsigned nb0, unsigned nb1,
-                                                     unsigned nb2) {
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b < nb0) {
-    flux_box_face<0>(coef, mask, fx, G, gp, dt, NR, NF0, (size_t)b * kBlock + threadIdx.x);
-  } else if (b < nb0 + nb1) {
-    flux_box_face<1>(coef, mask, fy, G, gp, dt, NR, NF1, (size_t)(b - nb0) * kBlock + threadIdx.x);
-  } else if (b < nb0 + nb1 + nb2) {
-    flux_box_face<2>(coef, mask, fz, G, gp, dt, NR, NF2, (size_t)(b - nb0 - nb1) * kBlock + threadIdx.x);
+__global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
+    const TC* __restrict__ coef, const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy,
+    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, size_t NR, size_t NF0, size_t NF1, size_t NF2,
+    unsigned nb0, unsigned nb1, unsigned nb2) {
+  unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= nb0 + nb1 + nb2) return;
+  int D = 0;
+  TC* face = fx;
+  size_t NF = NF0;
+  if (b >= nb0 + nb1) {
+    D = 2;
+    b -= nb0 + nb1;
+    face = fz;
+    NF = NF2;
+  } else if (b >= nb0) {
+    D = 1;
+    b -= nb0;
+    face = fy;
+    NF = NF1;
   }
+  flux_box_face(coef, mask, face, G, gp, dt, NR, NF, (size_t)b * kBlock + threadIdx.x, D);
 }
 
 // ---------------------------------------------------------------- update

@@ -126,6 +126,15 @@ HGKS_FN T Gn(const Slope<T>& s, const T (&m)[7]) {
   return s.c0 * m[N] + s.a2 * m[N + 1] + s.h5 * m[N + 2];
 }
 
+template <bool ACC, typename T>
+HGKS_FN void put5(T (&out)[5], T r0, T r1, T r2, T r3, T r4) {
+  if (ACC) {
+    out[0] += r0; out[1] += r1; out[2] += r2; out[3] += r3; out[4] += r4;
+  } else {
+    out[0] = r0; out[1] = r1; out[2] = r2; out[3] = r3; out[4] = r4;
+  }
+}
+
 // out (+)= < u^k (a.psi) psi >
 template <int k, bool ACC, typename T>
 HGKS_FN void mom_a(const Slope<T>& s, const Tang<T>& t, const T (&m)[7], T (&out)[5]) {
@@ -134,35 +143,29 @@ HGKS_FN void mom_a(const Slope<T>& s, const Tang<T>& t, const T (&m)[7], T (&out
   const T r2 = t.V * g0 + s.t3 * m[k];
   const T r3 = t.W * g0 + s.t4 * m[k];
   const T r4 = T(0.5) * g2 + t.e * g0 + s.s5 * m[k];
-  if (ACC) {
-    out[0] += r0; out[1] += r1; out[2] += r2; out[3] += r3; out[4] += r4;
-  } else {
-    out[0] = r0; out[1] = r1; out[2] = r2; out[3] = r3; out[4] = r4;
-  }
+  put5<ACC>(out, r0, r1, r2, r3, r4);
 }
 
-// out += < u^k v (a.psi) psi >
-template <int k, typename T>
+// out (+)= < u^k v (a.psi) psi >
+template <int k, bool ACC, typename T>
 HGKS_FN void mom_av(const Slope<T>& s, const Tang<T>& t, const T (&m)[7], T (&out)[5]) {
   const T g0 = Gn<k>(s, m), g1 = Gn<k + 1>(s, m), g2 = Gn<k + 2>(s, m);
   const T A0 = t.V * g0 + s.t3 * m[k];
-  out[0] += A0;
-  out[1] += t.V * g1 + s.t3 * m[k + 1];
-  out[2] += (t.V * t.V + t.h) * g0 + (T(2) * t.V * s.t3 + s.a5 * t.h * t.h) * m[k];
-  out[3] += t.V * t.W * g0 + (t.W * s.t3 + t.V * s.t4) * m[k];
-  out[4] += T(0.5) * (t.V * g2 + s.t3 * m[k + 2]) + t.e * A0 + t.V * t.h * g0 + s.c5v * m[k];
+  put5<ACC>(out, A0, t.V * g1 + s.t3 * m[k + 1],
+            (t.V * t.V + t.h) * g0 + (T(2) * t.V * s.t3 + s.a5 * t.h * t.h) * m[k],
+            t.V * t.W * g0 + (t.W * s.t3 + t.V * s.t4) * m[k],
+            T(0.5) * (t.V * g2 + s.t3 * m[k + 2]) + t.e * A0 + t.V * t.h * g0 + s.c5v * m[k]);
 }
 
-// out += < u^k w (a.psi) psi >
-template <int k, typename T>
+// out (+)= < u^k w (a.psi) psi >
+template <int k, bool ACC, typename T>
 HGKS_FN void mom_aw(const Slope<T>& s, const Tang<T>& t, const T (&m)[7], T (&out)[5]) {
   const T g0 = Gn<k>(s, m), g1 = Gn<k + 1>(s, m), g2 = Gn<k + 2>(s, m);
   const T B0 = t.W * g0 + s.t4 * m[k];
-  out[0] += B0;
-  out[1] += t.W * g1 + s.t4 * m[k + 1];
-  out[2] += t.V * t.W * g0 + (t.V * s.t4 + t.W * s.t3) * m[k];
-  out[3] += (t.W * t.W + t.h) * g0 + (T(2) * t.W * s.t4 + s.a5 * t.h * t.h) * m[k];
-  out[4] += T(0.5) * (t.W * g2 + s.t4 * m[k + 2]) + t.e * B0 + t.W * t.h * g0 + s.c5w * m[k];
+  put5<ACC>(out, B0, t.W * g1 + s.t4 * m[k + 1],
+            t.V * t.W * g0 + (t.V * s.t4 + t.W * s.t3) * m[k],
+            (t.W * t.W + t.h) * g0 + (T(2) * t.W * s.t4 + s.a5 * t.h * t.h) * m[k],
+            T(0.5) * (t.W * g2 + s.t4 * m[k + 2]) + t.e * B0 + t.W * t.h * g0 + s.c5w * m[k]);
 }
 
 // out = < u^k psi >
@@ -175,10 +178,13 @@ HGKS_FN void mom_psi(const Tang<T>& t, const T (&m)[7], T (&out)[5]) {
   out[4] = T(0.5) * m[k + 2] + t.e * m[k];
 }
 
-// Micro-slope: the a with <a psi> = b for the Maxwellian (U, V, W, lambda),
-// b already divided by rho.  Closed-form inverse of the 5x5 moment matrix
-// with q = U^2 + V^2 + W^2 + (K+3)/(2 lambda), il = 2 lambda and
-// c5 = 4 lambda^2 / (K + 3).
+// Micro-slope: the a with <a psi> = b for the unit-mass Maxwellian
+// (U, V, W, lambda).  Closed-form inverse of the 5x5 moment matrix with
+// q = U^2 + V^2 + W^2 + (K+3)/(2 lambda), il = 2 lambda and
+// c5 = 4 lambda^2 / (K + 3).  The map is linear in b; the callers pass the
+// derivatives of the conservative variables themselves (not divided by
+// rho), so the result is rho times the micro-slope of Eq. (8) and every
+// moment taken with it carries that factor rho.
 template <typename T>
 HGKS_FN void micro_slope(const T (&b)[5], T U, T V, T W, T il, T q, T c5, T (&a)[5]) {
   const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = b[3] - W * b[0];
@@ -216,7 +222,10 @@ HGKS_FN void axpy5(T s, const T (&x)[5], T (&y)[5]) {
 
 // Contributions of one side (SIDE = +1: left state, particles with u > 0;
 // SIDE = -1: right state, u < 0).  W: conservative variables in the local
-// frame; dW[j]: their derivatives along n_x, n_y, n_z.
+// frame; dW[j]: their derivatives along n_x, n_y, n_z.  The three
+// micro-slopes are formed and consumed one at a time, so that only one is
+// live: each adds its full-line term to the compatibility residual (which
+// gives A) and its half-line terms to dQ0[j] and X5.
 template <int SIDE, typename T>
 HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>& g, FluxAcc<T>& A) {
   const T rho = W[0];
@@ -229,50 +238,70 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
   const T c5 = il * il / g.K3;  // 4 lambda^2 / (K + 3)
   Tang<T> t;
   tang_init(t, V, Wv, h, g);
-  T m[7];
-  full_line(U, h, m);
+  T mf[7], mh[7];
+  full_line(U, h, mf);
+  half_line<SIDE>(U, h, mh);
 
-  Slope<T> s[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    T b[5], a[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) b[i] = dW[j][i] * ir;
-    micro_slope(b, U, V, Wv, il, q, c5, a);
-    slope_prep(a, t, s[j]);
-  }
-  // <a_1 u + a_2 v + a_3 w + A> = 0 (time derivative from compatibility)
+  // r = rho <(a_1 u + a_2 v + a_3 w) psi>, then A from <(a.u + A) psi> = 0.
   T r[5];
-  mom_a<1, false>(s[0], t, m, r);
-  mom_av<0>(s[1], t, m, r);
-  mom_aw<0>(s[2], t, m, r);
+  {
+    T a[5];
+    Slope<T> s;
+    micro_slope(dW[0], U, V, Wv, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_a<1, false>(s, t, mf, r);
+    mom_a<0, true>(s, t, mh, A.dQ0[0]);
+    mom_a<2, true>(s, t, mh, A.X5);
+  }
+  {
+    T a[5];
+    Slope<T> s;
+    micro_slope(dW[1], U, V, Wv, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_av<0, true>(s, t, mf, r);
+    mom_a<0, true>(s, t, mh, A.dQ0[1]);
+    mom_av<1, true>(s, t, mh, A.X5);
+  }
+  {
+    T a[5];
+    Slope<T> s;
+    micro_slope(dW[2], U, V, Wv, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_aw<0, true>(s, t, mf, r);
+    mom_a<0, true>(s, t, mh, A.dQ0[2]);
+    mom_aw<1, true>(s, t, mh, A.X5);
+  }
 #pragma unroll
   for (int i = 0; i < 5; ++i) r[i] = -r[i];
-  Slope<T> sA;
   {
-    T Ac[5];
-    micro_slope(r, U, V, Wv, il, q, c5, Ac);
-    slope_prep(Ac, t, sA);
+    T a[5];
+    Slope<T> s;
+    micro_slope(r, U, V, Wv, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_a<1, true>(s, t, mh, A.X6);
   }
-
-  half_line<SIDE>(U, h, m);
   T v5[5];
-  mom_psi<0>(t, m, v5);
+  mom_psi<0>(t, mh, v5);
   axpy5(rho, v5, A.Q0);
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    mom_a<0, false>(s[j], t, m, v5);
-    axpy5(rho, v5, A.dQ0[j]);
-  }
-  mom_psi<1>(t, m, v5);
+  mom_psi<1>(t, mh, v5);
   axpy5(rho, v5, A.X4);
-  mom_a<2, false>(s[0], t, m, v5);
-  mom_av<1>(s[1], t, m, v5);
-  mom_aw<1>(s[2], t, m, v5);
-  axpy5(rho, v5, A.X5);
-  mom_a<1, false>(sA, t, m, v5);
-  axpy5(rho, v5, A.X6);
   A.p[SIDE > 0 ? 0 : 1] = p;
+}
+
+// Register budget of the flux kernels: at least two waves per SIMD, so
+// that one wave's memory and transcendental latency hides behind another's
+// arithmetic.  In FP64 the compiler would otherwise keep one wave per SIMD
+// (over 256 registers); the few values that do not fit are spilled.
+#define HGKS_FLUX_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 ? 2 : 3)))
+
+// Orders the loads of the right cell after the left side's terms.  The
+// address gets a dependence on the left side's last results through an
+// empty asm, so the compiler cannot hoist the right cell's coefficient
+// loads into the left side's work, where both sides' values would be live
+// at once.
+template <typename T>
+__device__ __forceinline__ void after_left_side(size_t& idx, const FluxAcc<T>& A) {
+  asm volatile("" : "+v"(idx) : "v"(A.X6[0]), "v"(A.X6[4]), "v"(A.Q0[4]), "v"(A.X4[4]));
 }
 
 // Time integrals over [0, delta] of the five time factors of Eq. (15).
@@ -289,7 +318,9 @@ HGKS_FN void time_integrals(T delta, T tau, T (&Tc)[5]) {
 
 // Equilibrium part, collision time and the time fit.  On return F and dF
 // hold the flux and its time derivative in the local frame; A.Q0 holds the
-// conservative variables of g_0.
+// conservative variables of g_0.  The collision time and the coefficients
+// of the time fit come first, so that every moment is folded into F and dF
+// as soon as it is formed.
 template <typename T>
 HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T (&F)[5], T (&dF)[5]) {
   const T r0 = A.Q0[0];
@@ -300,60 +331,89 @@ HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T (&F)[5], 
   const T il = r0 / p0;
   const T q = U * U + V * V + W * W + g.K3 * h;
   const T c5 = il * il / g.K3;
+
+  const T jump = d_abs((A.p[0] - A.p[1]) / (A.p[0] + A.p[1])) * dt;
+  const T tau = g.viscous ? g.mu / p0 + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
+  T c[5], d[5];
+  {
+    T Tf[5], Th[5];
+    time_integrals(dt, tau, Tf);
+    time_integrals(T(0.5) * dt, tau, Th);
+    const T idt = T(1) / dt;
+    const T idt2 = T(4) * idt * idt;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      c[i] = (T(4) * Th[i] - Tf[i]) * idt;
+      d[i] = (Tf[i] - T(2) * Th[i]) * idt2;
+    }
+  }
+  // Non-equilibrium part: T4, T5 and tau T4 terms.
+  {
+    const T c6 = tau * c[3], d6 = tau * d[3];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      F[i] = c[3] * A.X4[i] - c[4] * A.X5[i] - c6 * A.X6[i];
+      dF[i] = d[3] * A.X4[i] - d[4] * A.X5[i] - d6 * A.X6[i];
+    }
+  }
+
   Tang<T> t;
   tang_init(t, V, W, h, g);
   T m[7];
   full_line(U, h, m);
-
-  Slope<T> s[3];
+  T v5[5];
+  mom_psi<1>(t, m, v5);
+  {
+    const T c0 = c[0] * r0, d0 = d[0] * r0;
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    T b[5], a[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) b[i] = A.dQ0[j][i] * ir0;
-    micro_slope(b, U, V, W, il, q, c5, a);
-    slope_prep(a, t, s[j]);
+    for (int i = 0; i < 5; ++i) {
+      F[i] += c0 * v5[i];
+      dF[i] += d0 * v5[i];
+    }
   }
+  // abar_j from dQ0[j] (carrying rho_0), one at a time; the T2 term and the
+  // compatibility residual that gives Abar.
   T r[5];
-  mom_a<1, false>(s[0], t, m, r);
-  mom_av<0>(s[1], t, m, r);
-  mom_aw<0>(s[2], t, m, r);
+  {
+    T a[5];
+    Slope<T> s;
+    micro_slope(A.dQ0[0], U, V, W, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_a<1, false>(s, t, m, r);
+    mom_a<2, false>(s, t, m, v5);
+    axpy5(c[1], v5, F);
+    axpy5(d[1], v5, dF);
+  }
+  {
+    T a[5];
+    Slope<T> s;
+    micro_slope(A.dQ0[1], U, V, W, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_av<0, true>(s, t, m, r);
+    mom_av<1, false>(s, t, m, v5);
+    axpy5(c[1], v5, F);
+    axpy5(d[1], v5, dF);
+  }
+  {
+    T a[5];
+    Slope<T> s;
+    micro_slope(A.dQ0[2], U, V, W, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_aw<0, true>(s, t, m, r);
+    mom_aw<1, false>(s, t, m, v5);
+    axpy5(c[1], v5, F);
+    axpy5(d[1], v5, dF);
+  }
 #pragma unroll
   for (int i = 0; i < 5; ++i) r[i] = -r[i];
-  Slope<T> sA;
   {
-    T Ab[5];
-    micro_slope(r, U, V, W, il, q, c5, Ab);
-    slope_prep(Ab, t, sA);
-  }
-
-  T X1[5], X2[5], X3[5];
-  mom_psi<1>(t, m, X1);
-  mom_a<2, false>(s[0], t, m, X2);
-  mom_av<1>(s[1], t, m, X2);
-  mom_aw<1>(s[2], t, m, X2);
-  mom_a<1, false>(sA, t, m, X3);
-
-  const T jump = d_abs((A.p[0] - A.p[1]) / (A.p[0] + A.p[1])) * dt;
-  const T tau = g.viscous ? g.mu / p0 + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
-
-  T Tf[5], Th[5];
-  time_integrals(dt, tau, Tf);
-  time_integrals(T(0.5) * dt, tau, Th);
-  const T idt = T(1) / dt;
-  const T idt2 = T(4) * idt * idt;
-  T c[5], d[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    c[i] = (T(4) * Th[i] - Tf[i]) * idt;
-    d[i] = (Tf[i] - T(2) * Th[i]) * idt2;
-  }
-  const T c6 = tau * c[3], d6 = tau * d[3];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const T e1 = r0 * X1[i], e2 = r0 * X2[i], e3 = r0 * X3[i];
-    F[i] = c[0] * e1 + c[1] * e2 + c[2] * e3 + c[3] * A.X4[i] - c[4] * A.X5[i] - c6 * A.X6[i];
-    dF[i] = d[0] * e1 + d[1] * e2 + d[2] * e3 + d[3] * A.X4[i] - d[4] * A.X5[i] - d6 * A.X6[i];
+    T a[5];
+    Slope<T> s;
+    micro_slope(r, U, V, W, il, q, c5, a);
+    slope_prep(a, t, s);
+    mom_a<1, false>(s, t, m, v5);
+    axpy5(c[2], v5, F);
+    axpy5(d[2], v5, dF);
   }
 }
 

@@ -64,12 +64,12 @@ int main() {
   acc_zero(acc);
   {
     Cnt W[5], dW[3][5];
-    eval_box_gp<0>(coef, NR, 0, Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
+    eval_box_gp(coef, NR, 0, face_axes(0), Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
     side_terms<+1>(W, dW, g, acc);
   }
   {
     Cnt W[5], dW[3][5];
-    eval_box_gp<0>(coef, NR, 1, Cnt(-0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
+    eval_box_gp(coef, NR, 1, face_axes(0), Cnt(-0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
     side_terms<-1>(W, dW, g, acc);
   }
   Cnt F[5], dF[5];
