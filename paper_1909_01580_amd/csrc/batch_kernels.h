@@ -91,6 +91,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_batch_flux(const
     const BatchGrid<TC>& b = B[g];
     unsigned lt = w.t - b.t_flux;
     const TC dtg = TC(dt[g]);
+    const TC idtg = TC(1.0 / dt[g]);
     const TC* cf = coef + b.coef_off;
     const uint32_t* mk = mask + b.mask_off;
     int D = 0;
@@ -102,7 +103,8 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_batch_flux(const
         D = 2;
       }
     }
-    flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, b.N, b.NF[D], (size_t)lt * kBlock + threadIdx.x, D);
+    flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, b.NF[D], (size_t)lt * kBlock + threadIdx.x,
+                  D);
   }
 }
 

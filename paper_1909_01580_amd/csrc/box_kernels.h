@@ -2,10 +2,12 @@
 //
 // Layout in HBM (structure of arrays, x fastest):
 //   state     q[5][nz][ny][nx]                         double
-//   coef      c[5 vars][10][NRz][NRy][NRx]               TC (double/float)
-//             per variable: the cell mean and the nine coefficients of the
-//             reconstructed quadratic in the unit-cube coordinate xi;
-//             NR = n + 2 on outflow axes (one ghost layer), n on periodic.
+//   coef      per reconstructed cell and variable: the cell mean and the
+//             nine coefficients of the reconstructed quadratic in the
+//             unit-cube coordinate xi, TC (double/float), in blocks of
+//             64 / sizeof(TC) cells (coef_cell below); the cells are the
+//             reconstruction box [NRz][NRy][NRx], NR = n + 2 on outflow axes
+//             (one ghost layer), n on periodic.
 //   mask      m[NRz][NRy][NRx]                           uint32, bit 4 f + g
 //             set where Gauss point g of face f uses the first-order
 //             fallback (Sec. 4 limiting procedure)
@@ -33,8 +35,29 @@ struct BoxGrid {
   int per[3];   // periodic axis
   int nf[3][3]; // face grid per direction
   double inv_dx[3];
+  double wface[3];  // Gauss weight 1/4 times the face area, faces normal to d
   double vol;
 };
+
+// Coefficient layout: blocks of kCB = 64 / sizeof(TC) consecutive
+// reconstructed cells; a block holds the 50 values of its cells (variable
+// v, coefficient k, row 10 v + k; k = 0 the cell mean) as 50 rows of kCB
+// values.  All 50 values of a cell then lie within 3.2 KB of its first
+// value, so one address serves all its loads (immediate offsets), and one
+// row of a block is one 64-byte segment.
+template <typename TC>
+constexpr int kCB = 64 / (int)sizeof(TC);
+
+template <typename TC>
+HGKS_FN size_t coef_cell(size_t cell) {
+  return (cell / kCB<TC>) * 50 * kCB<TC> + cell % kCB<TC>;
+}
+
+// Elements of the coefficient array of NR reconstructed cells.
+constexpr size_t coef_elems(size_t NR, size_t elem_bytes) {
+  const size_t cb = 64 / elem_bytes;
+  return 50 * ((NR + cb - 1) / cb) * cb;
+}
 
 __device__ __forceinline__ int bc_index(const BoxGrid& G, int ax, int i) {
   // Real index after the boundary rule: periodic wrap or zero-gradient clamp.
@@ -89,10 +112,10 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
         }
     BoxRecon<TC> r;
     weno_box(d, P, r);
-    TC* cv = coef + (size_t)v * 10 * NR + idx;
+    TC* cv = coef + coef_cell<TC>(idx) + v * 10 * kCB<TC>;
     cv[0] = TC(c);
 #pragma unroll
-    for (int m = 0; m < 9; ++m) cv[(size_t)(m + 1) * NR] = r.c[m];
+    for (int m = 0; m < 9; ++m) cv[(m + 1) * kCB<TC>] = r.c[m];
     qc[v] = TC(c);
     bnd[v] = r.bound;
   }
@@ -218,34 +241,56 @@ HGKS_FN FaceAxes face_axes(int D) {
 
 // Value and gradient of the five variables of reconstructed cell `cell` at
 // the point with local coordinates (xD, xA, xB) of the unit cube, in the
-// local frame: W = (rho, M_D, M_A, M_B, E), dW[j] = derivative along local
-// axis j.  The stored quadratic (x, y, z, xx, yy, zz, xy, yz, xz in global
-// axes) is read with its coefficients permuted to the local axes: local
-// linear and square terms of axis j come from global axis (D, A, B)[j], and
-// the local mixed terms (DA, AB, DB) from the global mixed terms 6 + D,
-// 6 + A, 6 + B.
-template <typename TC>
-HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, FaceAxes ax, TC xD, TC xA,
-                         TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5], TC (&dW)[3][5]) {
-  const int lv[5] = {0, 1 + ax.D, 1 + ax.A, 1 + ax.B, 4};
-  const int cp[9] = {ax.D, ax.A, ax.B, 3 + ax.D, 3 + ax.A, 3 + ax.B, 6 + ax.D, 6 + ax.A, 6 + ax.B};
+// local frame of a face normal to axis D: W = (rho, M_D, M_A, M_B, E),
+// dW[j] = derivative along local axis j.  The stored quadratic (x, y, z,
+// xx, yy, zz, xy, yz, xz in global axes) is read with its coefficients
+// permuted to the local axes: local linear and square terms of axis j come
+// from global axis (D, A, B)[j], the local mixed terms (DA, AB, DB) from
+// the global mixed terms 6 + D, 6 + A, 6 + B.  D is a template parameter
+// so that every load has a constant offset from the cell's address.
+template <int D, typename TC>
+HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t cell, TC xD, TC xA, TC xB, bool fallback,
+                         const TC (&invd)[3], TC (&W)[5], TC (&dW)[3][5]) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3, CB = kCB<TC>;
+  constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
+  constexpr int cp[9] = {D, A, B, 3 + D, 3 + A, 3 + B, 6 + D, 6 + A, 6 + B};
+  const TC* cv = coef + coef_cell<TC>(cell);
 #pragma unroll
   for (int kk = 0; kk < 5; ++kk) {
-    const TC* cv = coef + (size_t)lv[kk] * 10 * NR + cell;
-    const TC q0 = cv[0];
+    const TC* ck = cv + lv[kk] * 10 * CB;
     TC c[9];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) c[m] = cv[(size_t)(cp[m] + 1) * NR];
+    for (int m = 0; m < 9; ++m) c[m] = ck[(cp[m] + 1) * CB];
     TC val, g[3];
-    quad_eval(q0, c, xD, xA, xB, val, g[0], g[1], g[2]);
-    if (fallback) {
-      val = q0;
-      g[0] = g[1] = g[2] = TC(0);
-    }
+    quad_eval(ck[0], c, xD, xA, xB, val, g[0], g[1], g[2]);
     W[kk] = val;
 #pragma unroll
     for (int j = 0; j < 3; ++j) dW[j][kk] = g[j] * invd[j];
   }
+  if (fallback) {
+    // First-order fallback of the Sec. 4 limiter: cell mean, zero gradient.
+    // Rare, so a real branch (the empty asm keeps the compiler from turning
+    // it into selects on every lane) that re-reads the means.
+    asm volatile("");
+#pragma unroll
+    for (int kk = 0; kk < 5; ++kk) {
+      W[kk] = cv[lv[kk] * 10 * CB];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dW[j][kk] = TC(0);
+    }
+  }
+}
+
+// eval_box_gp for a direction D that is uniform over the workgroup.
+template <typename TC>
+HGKS_FN void eval_box_gp_dir(int D, const TC* __restrict__ coef, size_t cell, TC xD, TC xA, TC xB,
+                             bool fallback, const TC (&invd)[3], TC (&W)[5], TC (&dW)[3][5]) {
+  if (D == 0)
+    eval_box_gp<0>(coef, cell, xD, xA, xB, fallback, invd, W, dW);
+  else if (D == 1)
+    eval_box_gp<1>(coef, cell, xD, xA, xB, fallback, invd, W, dW);
+  else
+    eval_box_gp<2>(coef, cell, xD, xA, xB, fallback, invd, W, dW);
 }
 
 // One lane = one Gauss point of one face normal to axis D; the four lanes of
@@ -254,7 +299,7 @@ HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t NR, size_t cell, Fa
 template <typename TC>
 __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
-                                              TC dt, size_t NR, size_t NF, size_t tid, int D) {
+                                              TC dt, TC idt, size_t NF, size_t tid, int D) {
   const FaceAxes ax = face_axes(D);
   const int gpi = (int)(tid & 3);
   size_t f = tid >> 2;
@@ -282,19 +327,19 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   acc_zero(acc);
   {
     TC W[5], dW[3][5];
-    eval_box_gp(coef, NR, iL, ax, TC(0.5), xa, xb, fbL, invd, W, dW);
+    eval_box_gp_dir(D, coef, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
     side_terms<+1>(W, dW, gp, acc);
   }
   after_left_side(iR, acc);
   {
     TC W[5], dW[3][5];
-    eval_box_gp(coef, NR, iR, ax, TC(-0.5), xa, xb, fbR, invd, W, dW);
+    eval_box_gp_dir(D, coef, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
     side_terms<-1>(W, dW, gp, acc);
   }
   TC F[5], dF[5];
-  finish_flux(acc, gp, dt, F, dF);
+  finish_flux(acc, gp, dt, idt, F, dF);
   // Face weight of Eq. (11): Gauss weight 1/4 times the area element.
-  const TC w = TC(0.25 / (G.inv_dx[ax.A] * G.inv_dx[ax.B]));
+  const TC w = TC(G.wface[D]);
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     F[i] *= w;
@@ -319,7 +364,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
     const TC* __restrict__ coef, const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy,
-    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, size_t NR, size_t NF0, size_t NF1, size_t NF2,
+    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, size_t NF0, size_t NF1, size_t NF2,
     unsigned nb0, unsigned nb1, unsigned nb2) {
   unsigned b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= nb0 + nb1 + nb2) return;
@@ -337,7 +382,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
     face = fy;
     NF = NF1;
   }
-  flux_box_face(coef, mask, face, G, gp, dt, NR, NF, (size_t)b * kBlock + threadIdx.x, D);
+  flux_box_face(coef, mask, face, G, gp, dt, idt, NF, (size_t)b * kBlock + threadIdx.x, D);
 }
 
 // ---------------------------------------------------------------- update
@@ -511,9 +556,9 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_box(const TC* __restrict__ 
     xi[(d + 2) % 3] = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
     const bool fb = (mk >> bit) & 1u;
     for (int v = 0; v < 5; ++v) {
-      const TC* cv = coef + (size_t)v * 10 * NR + r;
+      const TC* cv = coef + coef_cell<TC>(r) + v * 10 * kCB<TC>;
       TC c[9];
-      for (int m = 0; m < 9; ++m) c[m] = cv[(size_t)(m + 1) * NR];
+      for (int m = 0; m < 9; ++m) c[m] = cv[(m + 1) * kCB<TC>];
       TC val, g[3];
       quad_eval(cv[0], c, xi[0], xi[1], xi[2], val, g[0], g[1], g[2]);
       if (fb) {

@@ -13,9 +13,36 @@ namespace hgks {
 template <typename T> HGKS_FN T d_exp(T x);
 template <> HGKS_FN double d_exp<double>(double x) { return exp(x); }
 template <> HGKS_FN float d_exp<float>(float x) { return expf(x); }
+// erf(x) = (2/sqrt(pi)) sum_n (-1)^n x^(2n+1) / (n! (2n+1)), its Maclaurin
+// series, summed by Horner's rule in x^2 over the first N terms.  For
+// |x| <= 1 the first omitted term is below 5e-18 with N = 18 (double) and
+// 1.2e-9 with N = 11 (float).
+constexpr double erf_series_coef(int n) {
+  double f = 1.12837916709551257389615890312154517;  // 2/sqrt(pi)
+  for (int k = 1; k <= n; ++k) f = -f / k;
+  return f / (2 * n + 1);
+}
+
+template <int N, typename T>
+HGKS_FN T erf_series(T x) {
+  const T t = x * x;
+  T s = T(erf_series_coef(N - 1));
+#pragma unroll
+  for (int n = N - 2; n >= 0; --n) s = s * t + T(erf_series_coef(n));
+  return s * x;
+}
+
+// erfc: 1 - erf by the series where |x| <= 1 (every smooth-flow interface
+// state has |sqrt(lambda) U| well below 1); the library erfc elsewhere.
 template <typename T> HGKS_FN T d_erfc(T x);
-template <> HGKS_FN double d_erfc<double>(double x) { return erfc(x); }
-template <> HGKS_FN float d_erfc<float>(float x) { return erfcf(x); }
+template <> HGKS_FN double d_erfc<double>(double x) {
+  if (fabs(x) <= 1.0) return 1.0 - erf_series<18>(x);
+  return erfc(x);
+}
+template <> HGKS_FN float d_erfc<float>(float x) {
+  if (fabsf(x) <= 1.0f) return 1.0f - erf_series<11>(x);
+  return erfcf(x);
+}
 template <typename T> HGKS_FN T d_sqrt(T x);
 template <> HGKS_FN double d_sqrt<double>(double x) { return sqrt(x); }
 template <> HGKS_FN float d_sqrt<float>(float x) { return sqrtf(x); }

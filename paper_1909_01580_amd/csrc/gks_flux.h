@@ -54,6 +54,8 @@ struct GasParams {
   T K;        // internal degrees of freedom
   T K2;       // K + 2
   T K3;       // K + 3
+  T inv_K3;   // 1 / (K + 3)
+  T two_gm1;  // 2 / (gamma - 1)
   T mu;       // viscosity (0: inviscid collision time)
   T tau_eps, tau_C;
   int viscous;
@@ -83,14 +85,15 @@ HGKS_FN void full_line(T U, T h, T (&m)[7]) {
   for (int k = 1; k < 6; ++k) m[k + 1] = U * m[k] + T(k) * h * m[k - 1];
 }
 
-// Half-line u-moments; SIDE = +1: u > 0, SIDE = -1: u < 0.
+// Half-line u-moments; SIDE = +1: u > 0, SIDE = -1: u < 0.  il = 2 lambda
+// = 1/h; 1/sqrt(lambda) = 2 h sqrt(lambda), so no division is needed.
 template <int SIDE, typename T>
-HGKS_FN void half_line(T U, T h, T (&m)[7]) {
-  const T lam = T(0.5) / h;
+HGKS_FN void half_line(T U, T h, T il, T (&m)[7]) {
+  const T lam = T(0.5) * il;
   const T sl = d_sqrt(lam);
   const T inv_sqrt_pi = T(0.56418958354775628694807945156077259);
   m[0] = T(0.5) * d_erfc(T(-SIDE) * sl * U);
-  m[1] = U * m[0] + T(SIDE) * T(0.5) * inv_sqrt_pi * d_exp(-lam * U * U) / sl;
+  m[1] = U * m[0] + T(SIDE) * inv_sqrt_pi * h * sl * d_exp(-lam * U * U);
 #pragma unroll
   for (int k = 1; k < 6; ++k) m[k + 1] = U * m[k] + T(k) * h * m[k - 1];
 }
@@ -226,21 +229,42 @@ HGKS_FN void axpy5(T s, const T (&x)[5], T (&y)[5]) {
 // micro-slopes are formed and consumed one at a time, so that only one is
 // live: each adds its full-line term to the compatibility residual (which
 // gives A) and its half-line terms to dQ0[j] and X5.
+// Primitive quantities of a state with conservative variables Q, from one
+// reciprocal: with p2 = 2 rho E - |M|^2 = 2 rho p / (gamma - 1) and
+// R = 1 / (rho p2), 1/rho = p2 R and 2 lambda = rho/p = (2/(gamma-1)) rho^2/p2.
+template <typename T>
+struct Prim {
+  T rho, ir, U, V, W, p, h, il, q, c5;
+};
+
+template <typename T>
+HGKS_FN void primitives(const T (&Q)[5], const GasParams<T>& g, Prim<T>& s) {
+  const T rho = Q[0];
+  const T p2 = T(2) * rho * Q[4] - (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
+  const T R = T(1) / (rho * p2);
+  const T ir = p2 * R;
+  s.rho = rho;
+  s.ir = ir;
+  s.U = Q[1] * ir;
+  s.V = Q[2] * ir;
+  s.W = Q[3] * ir;
+  s.p = T(0.5) * g.gm1 * p2 * ir;
+  s.h = s.p * ir;                            // 1 / (2 lambda)
+  s.il = g.two_gm1 * (rho * rho) * (rho * R);  // 2 lambda
+  s.q = s.U * s.U + s.V * s.V + s.W * s.W + g.K3 * s.h;
+  s.c5 = s.il * s.il * g.inv_K3;             // 4 lambda^2 / (K + 3)
+}
+
 template <int SIDE, typename T>
 HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>& g, FluxAcc<T>& A) {
-  const T rho = W[0];
-  const T ir = T(1) / rho;
-  const T U = W[1] * ir, V = W[2] * ir, Wv = W[3] * ir;
-  const T p = g.gm1 * (W[4] - T(0.5) * rho * (U * U + V * V + Wv * Wv));
-  const T h = p * ir;           // 1 / (2 lambda)
-  const T il = rho / p;         // 2 lambda
-  const T q = U * U + V * V + Wv * Wv + g.K3 * h;
-  const T c5 = il * il / g.K3;  // 4 lambda^2 / (K + 3)
+  Prim<T> P;
+  primitives(W, g, P);
+  const T rho = P.rho, U = P.U, V = P.V, Wv = P.W, p = P.p, h = P.h, il = P.il, q = P.q, c5 = P.c5;
   Tang<T> t;
   tang_init(t, V, Wv, h, g);
   T mf[7], mh[7];
   full_line(U, h, mf);
-  half_line<SIDE>(U, h, mh);
+  half_line<SIDE>(U, h, il, mh);
 
   // r = rho <(a_1 u + a_2 v + a_3 w) psi>, then A from <(a.u + A) psi> = 0.
   T r[5];
@@ -306,8 +330,8 @@ __device__ __forceinline__ void after_left_side(size_t& idx, const FluxAcc<T>& A
 
 // Time integrals over [0, delta] of the five time factors of Eq. (15).
 template <typename T>
-HGKS_FN void time_integrals(T delta, T tau, T (&Tc)[5]) {
-  const T E = d_exp(-delta / tau);
+HGKS_FN void time_integrals(T delta, T tau, T itau, T (&Tc)[5]) {
+  const T E = d_exp(-delta * itau);
   const T om = T(1) - E;
   Tc[0] = delta - tau * om;
   Tc[1] = T(2) * tau * tau * om - tau * delta * (T(1) + E);
@@ -322,24 +346,20 @@ HGKS_FN void time_integrals(T delta, T tau, T (&Tc)[5]) {
 // of the time fit come first, so that every moment is folded into F and dF
 // as soon as it is formed.
 template <typename T>
-HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T (&F)[5], T (&dF)[5]) {
-  const T r0 = A.Q0[0];
-  const T ir0 = T(1) / r0;
-  const T U = A.Q0[1] * ir0, V = A.Q0[2] * ir0, W = A.Q0[3] * ir0;
-  const T p0 = g.gm1 * (A.Q0[4] - T(0.5) * r0 * (U * U + V * V + W * W));
-  const T h = p0 * ir0;
-  const T il = r0 / p0;
-  const T q = U * U + V * V + W * W + g.K3 * h;
-  const T c5 = il * il / g.K3;
+HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&F)[5], T (&dF)[5]) {
+  Prim<T> P;
+  primitives(A.Q0, g, P);
+  const T r0 = P.rho, U = P.U, V = P.V, W = P.W, h = P.h, il = P.il, q = P.q, c5 = P.c5;
 
   const T jump = d_abs((A.p[0] - A.p[1]) / (A.p[0] + A.p[1])) * dt;
-  const T tau = g.viscous ? g.mu / p0 + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
+  // mu / p_0 = mu (rho_0 / p_0) (1 / rho_0)
+  const T tau = g.viscous ? g.mu * il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
+  const T itau = T(1) / tau;
   T c[5], d[5];
   {
     T Tf[5], Th[5];
-    time_integrals(dt, tau, Tf);
-    time_integrals(T(0.5) * dt, tau, Th);
-    const T idt = T(1) / dt;
+    time_integrals(dt, tau, itau, Tf);
+    time_integrals(T(0.5) * dt, tau, itau, Th);
     const T idt2 = T(4) * idt * idt;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {

@@ -680,8 +680,7 @@ __device__ __forceinline__ void to_global(const double (&f)[5], const double (&u
 template <int D, typename TC>
 __device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
                                               const uint32_t* __restrict__ mask, TC* __restrict__ face,
-                                              const GasParams<TC>& gp, TC dt, size_t N, size_t tid) {
-  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+                                              const GasParams<TC>& gp, TC dt, TC idt, size_t N, size_t tid) {
   const int gpi = (int)(tid & 3);
   size_t f = tid >> 2;
   const bool live = f < N;
@@ -733,7 +732,7 @@ __device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ 
     side_terms<-1>(W, dW, gp, acc);
   }
   TC Fl[5], dFl[5];
-  finish_flux(acc, gp, dt, Fl, dFl);
+  finish_flux(acc, gp, dt, idt, Fl, dFl);
   double fl[5], dfl[5], q0l[5];
 #pragma unroll
   for (int e = 0; e < 5; ++e) {
@@ -769,14 +768,14 @@ template <typename TC>
 __global__ void __launch_bounds__(kBlock) k_flux_hex(HexGrid H, const TC* __restrict__ coef,
                                                      const double* __restrict__ geo, const uint32_t* __restrict__ mask,
                                                      TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
-                                                     GasParams<TC> gp, TC dt, size_t N, unsigned nb) {
+                                                     GasParams<TC> gp, TC dt, TC idt, size_t N, unsigned nb) {
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   if (b < nb) {
-    flux_hex_face<0>(H, coef, geo, mask, fx, gp, dt, N, (size_t)b * kBlock + threadIdx.x);
+    flux_hex_face<0>(H, coef, geo, mask, fx, gp, dt, idt, N, (size_t)b * kBlock + threadIdx.x);
   } else if (b < 2 * nb) {
-    flux_hex_face<1>(H, coef, geo, mask, fy, gp, dt, N, (size_t)(b - nb) * kBlock + threadIdx.x);
+    flux_hex_face<1>(H, coef, geo, mask, fy, gp, dt, idt, N, (size_t)(b - nb) * kBlock + threadIdx.x);
   } else if (b < 3 * nb) {
-    flux_hex_face<2>(H, coef, geo, mask, fz, gp, dt, N, (size_t)(b - 2 * nb) * kBlock + threadIdx.x);
+    flux_hex_face<2>(H, coef, geo, mask, fz, gp, dt, idt, N, (size_t)(b - 2 * nb) * kBlock + threadIdx.x);
   }
 }
 

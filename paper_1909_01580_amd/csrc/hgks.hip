@@ -97,7 +97,7 @@ Layout make_layout(const hgks_config* c, const Dims& D) {
   L.q = take(5 * D.N * sizeof(double));
   L.qs = take(5 * D.N * sizeof(double));
   L.acc = take(5 * D.N * sizeof(double));
-  L.coef = take(50 * D.NR * tc);
+  L.coef = take(coef_elems(D.NR, tc) * tc);
   L.mask = take(D.NR * sizeof(uint32_t));
   const size_t nface = c->moving ? 12 : 10;
   for (int d = 0; d < 3; ++d) L.face[d] = take(nface * D.NF[d] * tc);
@@ -206,6 +206,8 @@ GasParams<T> gas_params(const hgks_config& cfg) {
   g.gm1 = T(cfg.gamma - 1.0);
   g.K = T(K);
   g.K3 = T(K + 3.0);
+  g.inv_K3 = T(1.0 / (K + 3.0));
+  g.two_gm1 = T(2.0 / (cfg.gamma - 1.0));
   g.K2 = T(K + 2.0);
   g.mu = T(cfg.mu);
   g.tau_eps = T(cfg.tau_eps);
@@ -239,8 +241,8 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
   const unsigned nbx = blocks_for(4 * D.NF[0]), nby = blocks_for(4 * D.NF[1]), nbz = blocks_for(4 * D.NF[2]);
   prof_mark(c, HGKS_PHASE_FLUX, true);
   hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nbx + nby + nbz)), dim3(kBlock), 0, c->stream, coef, c->mask(),
-                     (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), D.NR, D.NF[0], D.NF[1],
-                     D.NF[2], nbx, nby, nbz);
+                     (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), TC(1.0 / dt), D.NF[0],
+                     D.NF[1], D.NF[2], nbx, nby, nbz);
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
@@ -302,7 +304,8 @@ hgks_status hex_stage(hgks_ctx c, const double* qin, double dt, double alpha) {
   const unsigned nb = blocks_for(4 * N);
   prof_mark(c, HGKS_PHASE_FLUX, true);
   hipLaunchKernelGGL((k_flux_hex<TC>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H, (const TC*)c->coef(),
-                     c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), gp, TC(dt), N, nb);
+                     c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), gp, TC(dt),
+                     TC(1.0 / dt), N, nb);
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
@@ -459,6 +462,7 @@ hgks_status hgks_set_uniform_grid(hgks_ctx c, const double origin[3], const doub
     c->G.inv_dx[d] = 1.0 / h;
     vol *= h;
   }
+  for (int d = 0; d < 3; ++d) c->G.wface[d] = 0.25 * vol * c->G.inv_dx[d];
   c->G.vol = vol;
   c->grid_set = true;
   return HGKS_OK;
@@ -709,7 +713,7 @@ bool batch_compatible(const hgks_config& a, const hgks_config& c) {
 template <typename TC>
 size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<BatchGrid<TC>>& G) {
   G.assign(n, BatchGrid<TC>());
-  size_t N = 0, F = 0;
+  size_t N = 0, F = 0, C = 0;
   unsigned tc = 0, tf = 0;
   for (int i = 0; i < n; ++i) {
     const Dims D = make_dims(&cfgs[i]);
@@ -724,7 +728,7 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
     }
     g.N = D.N;
     g.q_off = 5 * N;
-    g.coef_off = 50 * N;
+    g.coef_off = C;
     g.mask_off = N;
     g.t_cell = tc;
     g.t_flux = tf;
@@ -738,6 +742,7 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
     }
     tc += g.nt_cell;
     N += D.N;
+    C += coef_elems(D.N, sizeof(TC));
     g.gp = gas_params<TC>(cfgs[i]);
   }
   size_t off = 0;
@@ -752,7 +757,7 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
   }
   const size_t desc = take(n * sizeof(BatchGrid<TC>));
   const size_t q = take(5 * N * 8), qs = take(5 * N * 8), acc = take(5 * N * 8);
-  const size_t coef = take(50 * N * sizeof(TC)), mask = take(N * 4), face = take(F * sizeof(TC));
+  const size_t coef = take(C * sizeof(TC)), mask = take(N * 4), face = take(F * sizeof(TC));
   const size_t part = take((size_t)tc * 8), dt = take(n * 8), tot = take(5 * n * 8);
   if (b) {
     b->desc = desc; b->q = q; b->qs = qs; b->acc = acc; b->coef = coef; b->mask = mask; b->face = face;
@@ -903,7 +908,10 @@ hgks_status hgks_batch_set_uniform_grid(hgks_batch b, int32_t i, const double or
   }
   auto set = [&](auto& G) {
     using TC = std::decay_t<decltype(G[0].P.eps)>;
-    for (int d = 0; d < 3; ++d) G[i].G.inv_dx[d] = inv[d];
+    for (int d = 0; d < 3; ++d) {
+      G[i].G.inv_dx[d] = inv[d];
+      G[i].G.wface[d] = 0.25 * vol * inv[d];
+    }
     G[i].G.vol = vol;
     G[i].P = weno_params<TC>(b->cfgs[i], dx);
   };

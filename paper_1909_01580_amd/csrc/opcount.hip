@@ -48,15 +48,17 @@ int main() {
   GasParams<Cnt> g;
   const double K = (5.0 - 3.0 * 1.4) / 0.4;
   g.gm1 = Cnt(0.4); g.K = Cnt(K); g.K3 = Cnt(K + 3.0); g.K2 = Cnt(K + 2.0);
+  g.inv_K3 = Cnt(1.0 / (K + 3.0)); g.two_gm1 = Cnt(2.0 / 0.4);
   g.mu = Cnt(1.0 / 1600.0); g.tau_eps = Cnt(0.01); g.tau_C = Cnt(1.0); g.viscous = 1;
 
   // Coefficients of two cells (5 variables x 10) in the kernel layout.
   const size_t NR = 2;
-  Cnt coef[50 * 2];
+  static Cnt coef[coef_elems(NR, sizeof(Cnt))];
   const double base[5] = {1.0, 0.6, -0.4, 0.1, 178.9};
   for (int v = 0; v < 5; ++v)
     for (int k = 0; k < 10; ++k)
-      for (int c = 0; c < 2; ++c) coef[(v * 10 + k) * NR + c] = Cnt(k == 0 ? base[v] : 0.01 * (k + v + c));
+      for (size_t c = 0; c < NR; ++c)
+        coef[coef_cell<Cnt>(c) + (v * 10 + k) * kCB<Cnt>] = Cnt(k == 0 ? base[v] : 0.01 * (k + v + c));
   const Cnt invd[3] = {Cnt(20.0), Cnt(20.0), Cnt(20.0)};
 
   cnt::reset();
@@ -64,16 +66,16 @@ int main() {
   acc_zero(acc);
   {
     Cnt W[5], dW[3][5];
-    eval_box_gp(coef, NR, 0, face_axes(0), Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
+    eval_box_gp<0>(coef, 0, Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
     side_terms<+1>(W, dW, g, acc);
   }
   {
     Cnt W[5], dW[3][5];
-    eval_box_gp(coef, NR, 1, face_axes(0), Cnt(-0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
+    eval_box_gp<0>(coef, 1, Cnt(-0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
     side_terms<-1>(W, dW, g, acc);
   }
   Cnt F[5], dF[5];
-  finish_flux(acc, g, Cnt(1.5e-3), F, dF);
+  finish_flux(acc, g, Cnt(1.5e-3), Cnt(1.0 / 1.5e-3), F, dF);
   // Face weight and the four-point face sum: 10 products per point and
   // 3 additions per face and value (7.5 per point).
   const double flux_gp = (double)cnt::total() + 10.0 + 7.5;

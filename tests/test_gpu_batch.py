@@ -63,10 +63,14 @@ def test_batch_equals_single_grids(hg, precision):
         b.step(dt, 2)
     b.sync()
     single = run_single(hg, precision, qs, dts_per_step)
+    # The batch and single-grid kernels run the same per-face and per-cell
+    # code, but the compiler may fuse float operations differently in the
+    # two kernels: FP64 agrees to round-off, mixed to float rounding.
+    tol = 1e-14 if precision == "fp64" else 1e-6
     for i in range(len(GRIDS)):
         got = b.get_state(i).cpu().numpy()
         err = np.abs(got - single[i]).max() / np.abs(single[i]).max()
-        assert err < 1e-14, (i, err)
+        assert err < tol, (i, err)
     # per-grid dt equals the single-grid reduction
     for i, g in enumerate(GRIDS):
         ctx = hg.Context(g["n"], mu=g["mu"], precision=precision)
