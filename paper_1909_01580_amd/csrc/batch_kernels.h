@@ -21,7 +21,7 @@ struct BatchGrid {
   GasParams<TC> gp;
   size_t N, NF[3];
   size_t q_off;        // doubles: start of the grid's [5][N] state
-  size_t coef_off;     // TC: start of the grid's [5][10][N] coefficients
+  size_t coef_off;     // TC: start of the grid's coefficients (coef_cell layout)
   size_t mask_off;     // uint32: start of the grid's [N] masks
   size_t face_off[3];  // TC: start of the grid's [10][NF_d] face sums
   unsigned t_cell;     // first cell tile
@@ -57,39 +57,54 @@ struct TileWalk {
   }
 };
 
-template <typename TC>
+// Tiles of this workgroup: LOOP = false, a launch of one workgroup per tile
+// (rounded up to a multiple of 8, logical tile = xcd_block of the block
+// id, the same order as the walk); LOOP = true, the persistent walk.  The
+// loop-free form keeps the compiler from holding loop-invariant values in
+// registers across the whole walk, which costs the flux kernel spills.
+template <bool LOOP, typename F>
+__device__ __forceinline__ void for_tiles(unsigned ntiles, F&& body) {
+  if constexpr (LOOP) {
+    for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) body(w.t);
+  } else {
+    const unsigned t = xcd_block(blockIdx.x, gridDim.x);
+    if (t < ntiles) body(t);
+  }
+}
+
+template <typename TC, bool LOOP>
 __global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                         const double* __restrict__ q, TC* __restrict__ coef,
                                                         uint32_t* __restrict__ mask, TC margin, TC gm1) {
-  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
-    const int g = batch_grid_of<TC, false>(B, ng, w.t);
-    const size_t idx = (size_t)(w.t - B[g].t_cell) * kBlock + threadIdx.x;
+  for_tiles<LOOP>(ntiles, [&](unsigned t) {
+    const int g = batch_grid_of<TC, false>(B, ng, t);
+    const size_t idx = (size_t)(t - B[g].t_cell) * kBlock + threadIdx.x;
     if (idx < B[g].N)
       recon_box_cell(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin, gm1,
                      B[g].N, idx);
-  }
+  });
 }
 
-template <typename TC>
+template <typename TC, bool LOOP>
 __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                         const double* __restrict__ q, uint32_t* __restrict__ mask,
                                                         TC gm1) {
-  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
-    const int g = batch_grid_of<TC, false>(B, ng, w.t);
-    const size_t idx = (size_t)(w.t - B[g].t_cell) * kBlock + threadIdx.x;
+  for_tiles<LOOP>(ntiles, [&](unsigned t) {
+    const int g = batch_grid_of<TC, false>(B, ng, t);
+    const size_t idx = (size_t)(t - B[g].t_cell) * kBlock + threadIdx.x;
     if (idx < B[g].N && mask[B[g].mask_off + idx] == kNeedsCheck)
       posit_exact_box_cell(q + B[g].q_off, mask + B[g].mask_off, B[g].G, gm1, idx);
-  }
+  });
 }
 
-template <typename TC>
-__global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
-                                                       const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
-                                                       TC* __restrict__ face, const double* __restrict__ dt) {
-  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
-    const int g = batch_grid_of<TC, true>(B, ng, w.t);
+template <typename TC, bool LOOP>
+__global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
+    k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles, const TC* __restrict__ coef,
+                 const uint32_t* __restrict__ mask, TC* __restrict__ face, const double* __restrict__ dt) {
+  for_tiles<LOOP>(ntiles, [&](unsigned t) {
+    const int g = batch_grid_of<TC, true>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
-    unsigned lt = w.t - b.t_flux;
+    unsigned lt = t - b.t_flux;
     const TC dtg = TC(dt[g]);
     const TC idtg = TC(1.0 / dt[g]);
     const TC* cf = coef + b.coef_off;
@@ -105,34 +120,34 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_batch_flux(const
     }
     flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, b.NF[D], (size_t)lt * kBlock + threadIdx.x,
                   D);
-  }
+  });
 }
 
-template <typename TC>
+template <typename TC, bool LOOP>
 __global__ void __launch_bounds__(kBlock) k_batch_update(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                          double* __restrict__ q, double* __restrict__ qs,
                                                          double* __restrict__ acc, const TC* __restrict__ face,
                                                          const double* __restrict__ dt, int mode) {
-  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
-    const int g = batch_grid_of<TC, false>(B, ng, w.t);
+  for_tiles<LOOP>(ntiles, [&](unsigned t) {
+    const int g = batch_grid_of<TC, false>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
-    const size_t idx = (size_t)(w.t - b.t_cell) * kBlock + threadIdx.x;
+    const size_t idx = (size_t)(t - b.t_cell) * kBlock + threadIdx.x;
     if (idx < b.N)
       update_box_cell(q + b.q_off, qs + b.q_off, acc + b.q_off, face + b.face_off[0], face + b.face_off[1],
                       face + b.face_off[2], b.G, dt[g], mode, b.N, idx);
-  }
+  });
 }
 
 // Per-tile minimum of h / (|U| + c), then per-grid dt = cfl * minimum.
-template <typename TC>
+template <typename TC, bool LOOP>
 __global__ void __launch_bounds__(kBlock) k_batch_dt_part(const BatchGrid<TC>* __restrict__ B, int ng,
                                                           unsigned ntiles, const double* __restrict__ q, double gamma,
                                                           double* __restrict__ part) {
   __shared__ double sh[kBlock];
-  for (TileWalk w(ntiles); w.t < w.end; w.t += w.stride) {
-    const int g = batch_grid_of<TC, false>(B, ng, w.t);
+  for_tiles<LOOP>(ntiles, [&](unsigned t) {
+    const int g = batch_grid_of<TC, false>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
-    const size_t idx = (size_t)(w.t - b.t_cell) * kBlock + threadIdx.x;
+    const size_t idx = (size_t)(t - b.t_cell) * kBlock + threadIdx.x;
     double v = 1e300;
     if (idx < b.N) {
       const double* qg = q + b.q_off;
@@ -146,9 +161,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_dt_part(const BatchGrid<TC>* _
       if (!(v > 0.0)) v = -1.0;
     }
     const double r = block_reduce(v, sh, MinOp());
-    if (threadIdx.x == 0) part[w.t] = r;
+    if (threadIdx.x == 0) part[t] = r;
     __syncthreads();
-  }
+  });
 }
 
 template <typename TC>

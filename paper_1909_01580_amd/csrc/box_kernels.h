@@ -118,6 +118,10 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
     for (int m = 0; m < 9; ++m) cv[(m + 1) * kCB<TC>] = r.c[m];
     qc[v] = TC(c);
     bnd[v] = r.bound;
+    // The next variable's stencil loads wait for this variable's results
+    // (an empty asm ties their indices to them), so the compiler does not
+    // hoist all five stencils ahead and hold them in registers at once.
+    asm volatile("" : "+v"(iz[0]), "+v"(iz[1]), "+v"(iz[2]) : "v"(r.c[0]), "v"(r.bound));
   }
   // Sufficient test that no polynomial can give rho <= 0 or p < 0 at a
   // Gauss point: bounds of every variable over all 25 polynomials and 24
@@ -132,7 +136,7 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
       msq += mm * mm;
     }
     const TC emin = qc[4] - bnd[4];
-    safe = gm1 * (emin - TC(0.5) * msq / rmin) > margin * gm1 * (d_abs(qc[4]) + bnd[4]);
+    safe = gm1 * (emin - TC(0.5) * msq * d_rcp(rmin)) > margin * gm1 * (d_abs(qc[4]) + bnd[4]);
   }
   mask[idx] = safe ? 0u : kNeedsCheck;
 }

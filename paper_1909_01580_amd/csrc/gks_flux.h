@@ -241,7 +241,7 @@ template <typename T>
 HGKS_FN void primitives(const T (&Q)[5], const GasParams<T>& g, Prim<T>& s) {
   const T rho = Q[0];
   const T p2 = T(2) * rho * Q[4] - (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]);
-  const T R = T(1) / (rho * p2);
+  const T R = d_rcp(rho * p2);
   const T ir = p2 * R;
   s.rho = rho;
   s.ir = ir;
@@ -351,7 +351,7 @@ HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&
   primitives(A.Q0, g, P);
   const T r0 = P.rho, U = P.U, V = P.V, W = P.W, h = P.h, il = P.il, q = P.q, c5 = P.c5;
 
-  const T jump = d_abs((A.p[0] - A.p[1]) / (A.p[0] + A.p[1])) * dt;
+  const T jump = d_abs(A.p[0] - A.p[1]) * d_rcp(A.p[0] + A.p[1]) * dt;
   // mu / p_0 = mu (rho_0 / p_0) (1 / rho_0)
   const T tau = g.viscous ? g.mu * il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
   const T itau = T(1) / tau;

@@ -789,12 +789,24 @@ unsigned batch_wg(hgks_batch b, int phase, unsigned tiles) {
   return (unsigned)w;
 }
 
+// Persistent tile walk (a workgroup count was set) or one workgroup per tile.
+bool batch_loop(hgks_batch b, int phase) { return b->wg[phase] > 0; }
+
+#define HGKS_BATCH_LAUNCH(kernel, TC, loop, grid, ...)                                                   \
+  do {                                                                                                 \
+    if (loop)                                                                                          \
+      hipLaunchKernelGGL((kernel<TC, true>), dim3(grid), dim3(kBlock), 0, __VA_ARGS__);               \
+    else                                                                                               \
+      hipLaunchKernelGGL((kernel<TC, false>), dim3(grid), dim3(kBlock), 0, __VA_ARGS__);              \
+  } while (0)
+
 template <typename TC>
 hgks_status batch_dt(hgks_batch b, double cfl, double* dt_dev) {
   const BatchGrid<TC>* D = (const BatchGrid<TC>*)(b->ws + b->desc);
   double* part = (double*)(b->ws + b->part);
-  hipLaunchKernelGGL((k_batch_dt_part<TC>), dim3(batch_wg(b, HGKS_PHASE_REDUCE, b->tiles_cell)), dim3(kBlock), 0,
-                     b->stream, D, b->ng, b->tiles_cell, (const double*)(b->ws + b->q), b->base.gamma, part);
+  HGKS_BATCH_LAUNCH(k_batch_dt_part, TC, batch_loop(b, HGKS_PHASE_REDUCE),
+                    batch_wg(b, HGKS_PHASE_REDUCE, b->tiles_cell), b->stream, D, b->ng, b->tiles_cell,
+                    (const double*)(b->ws + b->q), b->base.gamma, part);
   hipLaunchKernelGGL((k_batch_dt_final<TC>), dim3(b->ng), dim3(kBlock), 0, b->stream, D, part, cfl, dt_dev);
   return bcheck(b, hipGetLastError(), "batch dt");
 }
@@ -806,22 +818,24 @@ hgks_status batch_stage(hgks_batch b, const double* qin, const double* dt_dev) {
   uint32_t* mask = (uint32_t*)(b->ws + b->mask);
   const TC margin = sizeof(TC) == 8 ? TC(1e-10) : TC(1e-5);
   const TC gm1 = TC(b->base.gamma - 1.0);
-  hipLaunchKernelGGL((k_batch_recon<TC>), dim3(batch_wg(b, HGKS_PHASE_RECON, b->tiles_cell)), dim3(kBlock), 0,
-                     b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin, gm1);
-  hipLaunchKernelGGL((k_batch_posit<TC>), dim3(batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell)), dim3(kBlock), 0,
-                     b->stream, D, b->ng, b->tiles_cell, qin, mask, gm1);
-  hipLaunchKernelGGL((k_batch_flux<TC>), dim3(batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux)), dim3(kBlock), 0,
-                     b->stream, D, b->ng, b->tiles_flux, (const TC*)coef, (const uint32_t*)mask,
-                     (TC*)(b->ws + b->face), dt_dev);
+  HGKS_BATCH_LAUNCH(k_batch_recon, TC, batch_loop(b, HGKS_PHASE_RECON), batch_wg(b, HGKS_PHASE_RECON, b->tiles_cell),
+                    b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin, gm1);
+  HGKS_BATCH_LAUNCH(k_batch_posit, TC, batch_loop(b, HGKS_PHASE_FALLBACK),
+                    batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell), b->stream, D, b->ng, b->tiles_cell, qin, mask,
+                    gm1);
+  HGKS_BATCH_LAUNCH(k_batch_flux, TC, batch_loop(b, HGKS_PHASE_FLUX), batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux),
+                    b->stream, D, b->ng, b->tiles_flux, (const TC*)coef, (const uint32_t*)mask,
+                    (TC*)(b->ws + b->face), dt_dev);
   return bcheck(b, hipGetLastError(), "batch stage");
 }
 
 template <typename TC>
 hgks_status batch_update(hgks_batch b, const double* dt_dev, int mode) {
   const BatchGrid<TC>* D = (const BatchGrid<TC>*)(b->ws + b->desc);
-  hipLaunchKernelGGL((k_batch_update<TC>), dim3(batch_wg(b, HGKS_PHASE_UPDATE, b->tiles_cell)), dim3(kBlock), 0,
-                     b->stream, D, b->ng, b->tiles_cell, (double*)(b->ws + b->q), (double*)(b->ws + b->qs),
-                     (double*)(b->ws + b->acc), (const TC*)(b->ws + b->face), dt_dev, mode);
+  HGKS_BATCH_LAUNCH(k_batch_update, TC, batch_loop(b, HGKS_PHASE_UPDATE),
+                    batch_wg(b, HGKS_PHASE_UPDATE, b->tiles_cell), b->stream, D, b->ng, b->tiles_cell,
+                    (double*)(b->ws + b->q), (double*)(b->ws + b->qs), (double*)(b->ws + b->acc),
+                    (const TC*)(b->ws + b->face), dt_dev, mode);
   return bcheck(b, hipGetLastError(), "batch update");
 }
 

@@ -39,6 +39,7 @@ namespace hgks {
 template <> HGKS_FN Cnt d_exp<Cnt>(Cnt x) { ++cnt::tr; return Cnt(std::exp(x.v)); }
 template <> HGKS_FN Cnt d_erfc<Cnt>(Cnt x) { ++cnt::tr; return Cnt(std::erfc(x.v)); }
 template <> HGKS_FN Cnt d_sqrt<Cnt>(Cnt x) { ++cnt::tr; return Cnt(std::sqrt(x.v)); }
+template <> HGKS_FN Cnt d_rcp<Cnt>(Cnt x) { ++cnt::dv; return Cnt(1.0 / x.v); }
 }  // namespace hgks
 
 using namespace hgks;

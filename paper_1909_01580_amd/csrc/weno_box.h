@@ -147,15 +147,15 @@ HGKS_FN void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out
 #pragma unroll
   for (int m = 0; m < 24; ++m) tau += d_abs(beta0 - beta[m]);
   tau *= T(1.0 / 24.0);
-  const T w0 = P.gamma0 * (T(1) + tau / (beta0 + P.eps));
-  T wsum = w0;
+  const T w0r = T(1) + tau * d_rcp(beta0 + P.eps);  // omega_0 / gamma_0
+  T wsum = P.gamma0 * w0r;
 #pragma unroll
   for (int m = 0; m < 24; ++m) {
-    beta[m] = P.Gamma * (T(1) + tau / (beta[m] + P.eps));  // omega_m
+    beta[m] = P.Gamma * (T(1) + tau * d_rcp(beta[m] + P.eps));  // omega_m
     wsum += beta[m];
   }
-  const T iw = T(1) / wsum;
-  const T w0g = w0 * iw / P.gamma0;  // wbar_0 / gamma_0
+  const T iw = d_rcp(wsum);
+  const T w0g = w0r * iw;  // wbar_0 / gamma_0
   const T off = w0g * P.Gamma;
 
   T cl[3] = {w0g * a[0], w0g * a[1], w0g * a[2]};
