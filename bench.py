@@ -168,10 +168,10 @@ def sampled_oracle_error(q0, first, n):
     return float(worst.max()), len(samples)
 
 
-def cpu_baseline(q0, n, budget_cells=20):
+def cpu_baseline(q0, n, budget_cells=32):
     """The oracle on a bounded sample of the same workload: one two-stage
-    step of a 20^3 block of the 128^3 Taylor-Green state (outflow at the
-    block faces), single-threaded."""
+    step of a 32^3 block of the 128^3 Taylor-Green state (outflow at the
+    block faces), single-threaded; about 10-15 s of CPU work."""
     import oracle
     from paper_1909_01580_amd import workloads as wl
     try:
