@@ -61,7 +61,8 @@ typedef enum {
 } hgks_prec;
 
 typedef struct {
-  int32_t nx, ny, nz;     /* cells per axis, each >= 2                        */
+  int32_t nx, ny, nz;     /* cells per axis, each >= 2, with
+                             (nx+2)(ny+2)(nz+2) < 2^32                        */
   int32_t bc[3];          /* hgks_bc per axis (x, y, z)                       */
   double gamma;           /* ratio of specific heats, 1 < gamma < 5/3 (1.4)   */
   double mu;              /* dynamic viscosity; 0 selects the inviscid

@@ -37,7 +37,32 @@ struct BoxGrid {
   double inv_dx[3];
   double wface[3];  // Gauss weight 1/4 times the face area, faces normal to d
   double vol;
+  // Reciprocals for index splitting (split_index): extents n[0], n[1];
+  // nr[0], nr[1]; nf[d][0], nf[d][1].
+  double inv_n[2], inv_nr[2], inv_nf[3][2];
 };
+
+// floor(k / d) for k < 2^32 from inv = (1 + 2^-40) / d: the double product
+// is at least k / d and exceeds it by less than the distance to the next
+// integer, so truncation is exact and no integer divide is needed.
+inline double div_inv(int d) { return (1.0 + 0x1p-40) / (double)d; }
+
+HGKS_FN void split_index(uint32_t k, int e0, int e1, double i0, double i1, int& c0, int& c1, int& c2) {
+  const uint32_t q0 = (uint32_t)((double)k * i0);
+  const uint32_t q1 = (uint32_t)((double)q0 * i1);
+  c0 = (int)(k - q0 * (uint32_t)e0);
+  c1 = (int)(q0 - q1 * (uint32_t)e1);
+  c2 = (int)q1;
+}
+
+// Fills the reciprocals of a grid whose extents are set.
+inline void set_index_split(BoxGrid& G) {
+  for (int a = 0; a < 2; ++a) {
+    G.inv_n[a] = div_inv(G.n[a]);
+    G.inv_nr[a] = div_inv(G.nr[a]);
+    for (int d = 0; d < 3; ++d) G.inv_nf[d][a] = div_inv(G.nf[d][a]);
+  }
+}
 
 // Coefficient layout: blocks of kCB = 64 / sizeof(TC) consecutive
 // reconstructed cells; a block holds the 50 values of its cells (variable
@@ -79,9 +104,8 @@ template <typename TC>
 __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC* __restrict__ coef,
                                                uint32_t* __restrict__ mask, const BoxGrid& G,
                                                const WenoParams<TC>& P, TC margin, TC gm1, size_t NR, size_t idx) {
-  const int ri = (int)(idx % G.nr[0]);
-  const int rj = (int)((idx / G.nr[0]) % G.nr[1]);
-  const int rk = (int)(idx / ((size_t)G.nr[0] * G.nr[1]));
+  int ri, rj, rk;
+  split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
   const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
   int ix[3], iy[3], iz[3];
 #pragma unroll
@@ -309,9 +333,8 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   size_t f = tid >> 2;
   const bool live = f < NF;
   if (!live) f = NF - 1;  // keep the lane in the 4-lane sum; its result is not written
-  const int f0 = (int)(f % G.nf[D][0]);
-  const int f1 = (int)((f / G.nf[D][0]) % G.nf[D][1]);
-  const int f2 = (int)(f / ((size_t)G.nf[D][0] * G.nf[D][1]));
+  int f0, f1, f2;
+  split_index((uint32_t)f, G.nf[D][0], G.nf[D][1], G.inv_nf[D][0], G.inv_nf[D][1], f0, f1, f2);
   int cR[3] = {f0, f1, f2};
   int cL[3] = {f0, f1, f2};
   cL[D] -= 1;
@@ -398,7 +421,8 @@ __device__ __forceinline__ void update_box_cell(double* __restrict__ q, double* 
                                                 double* __restrict__ acc, const TF* __restrict__ fx,
                                                 const TF* __restrict__ fy, const TF* __restrict__ fz,
                                                 const BoxGrid& G, double dt, int mode, size_t N, size_t idx) {
-  const int c[3] = {(int)(idx % G.n[0]), (int)((idx / G.n[0]) % G.n[1]), (int)(idx / ((size_t)G.n[0] * G.n[1]))};
+  int c[3];
+  split_index((uint32_t)idx, G.n[0], G.n[1], G.inv_n[0], G.inv_n[1], c[0], c[1], c[2]);
   const TF* fs[3] = {fx, fy, fz};
   double R[10];
 #pragma unroll

@@ -60,6 +60,8 @@ bool valid_config(const hgks_config* c) {
   if (c->moving)
     for (int d = 0; d < 3; ++d)
       if (c->bc[d] != HGKS_BC_PERIODIC) return false;
+  // Cell and face indices are split in 32-bit arithmetic.
+  if ((uint64_t)(c->nx + 2) * (uint64_t)(c->ny + 2) * (uint64_t)(c->nz + 2) >= (1ull << 32)) return false;
   return true;
 }
 
@@ -438,6 +440,7 @@ hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t byte
     c->G.per[d] = c->D.per[d];
     for (int e = 0; e < 3; ++e) c->G.nf[d][e] = c->D.nf[d][e];
   }
+  set_index_split(c->G);
   std::memset(&c->H, 0, sizeof c->H);
   *out = c;
   return HGKS_OK;
@@ -726,6 +729,7 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
       g.G.per[d] = 1;
       for (int e = 0; e < 3; ++e) g.G.nf[d][e] = D.nf[d][e];
     }
+    set_index_split(g.G);
     g.N = D.N;
     g.q_off = 5 * N;
     g.coef_off = C;
