@@ -104,22 +104,15 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, true>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
-    unsigned lt = t - b.t_flux;
+    unsigned lt;
     const TC dtg = TC(dt[g]);
     const TC idtg = TC(1.0 / dt[g]);
     const TC* cf = coef + b.coef_off;
     const uint32_t* mk = mask + b.mask_off;
-    int D = 0;
-    if (lt >= b.nt_flux[0]) {
-      lt -= b.nt_flux[0];
-      D = 1;
-      if (lt >= b.nt_flux[1]) {
-        lt -= b.nt_flux[1];
-        D = 2;
-      }
-    }
-    flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, b.NF[D], (size_t)lt * kBlock + threadIdx.x,
-                  D);
+    const unsigned nb[3] = {b.nt_flux[0], b.nt_flux[1], b.nt_flux[2]};
+    int D;
+    flux_block(t - b.t_flux, nb, D, lt);
+    flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D);
   });
 }
 

@@ -40,12 +40,16 @@ struct BoxGrid {
   // Reciprocals for index splitting (split_index): extents n[0], n[1];
   // nr[0], nr[1]; nf[d][0], nf[d][1].
   double inv_n[2], inv_nr[2], inv_nf[3][2];
+  // Banded cell order of the flux blocks (face_cell): bands of `band`
+  // rows along y; reciprocals of n0 band n2, n0 band and n0 (tail height).
+  int band, band_full, band_tail;
+  double inv_band[3];
 };
 
 // floor(k / d) for k < 2^32 from inv = (1 + 2^-40) / d: the double product
 // is at least k / d and exceeds it by less than the distance to the next
 // integer, so truncation is exact and no integer divide is needed.
-inline double div_inv(int d) { return (1.0 + 0x1p-40) / (double)d; }
+HGKS_FN double div_inv(int d) { return (1.0 + 0x1p-40) / (double)d; }
 
 HGKS_FN void split_index(uint32_t k, int e0, int e1, double i0, double i1, int& c0, int& c1, int& c2) {
   const uint32_t q0 = (uint32_t)((double)k * i0);
@@ -55,6 +59,10 @@ HGKS_FN void split_index(uint32_t k, int e0, int e1, double i0, double i1, int& 
   c2 = (int)q1;
 }
 
+// Rows per band of the flux block order: the z-neighbour row of a cell is
+// band * n0 cells earlier in that order, close enough to be found in L2.
+constexpr int kFluxBand = 16;
+
 // Fills the reciprocals of a grid whose extents are set.
 inline void set_index_split(BoxGrid& G) {
   for (int a = 0; a < 2; ++a) {
@@ -62,6 +70,89 @@ inline void set_index_split(BoxGrid& G) {
     G.inv_nr[a] = div_inv(G.nr[a]);
     for (int d = 0; d < 3; ++d) G.inv_nf[d][a] = div_inv(G.nf[d][a]);
   }
+  G.band = G.n[1] < kFluxBand ? G.n[1] : kFluxBand;
+  G.band_full = G.n[1] / G.band;
+  G.band_tail = G.n[1] - G.band_full * G.band;
+  G.inv_band[0] = div_inv(G.n[0] * G.band * G.n[2]);
+  G.inv_band[1] = div_inv(G.n[0] * G.band);
+  G.inv_band[2] = div_inv(G.n[0] * (G.band_tail > 0 ? G.band_tail : 1));
+}
+
+// Flux blocks of 64 faces per direction d: one per 64 cells (the faces on
+// the lower side of every cell) plus, on an outflow axis d, the faces of
+// the upper boundary plane.
+inline unsigned flux_main_blocks(const BoxGrid& G) {
+  return (unsigned)(((size_t)G.n[0] * G.n[1] * G.n[2] + 63) / 64);
+}
+inline void flux_block_counts(const BoxGrid& G, unsigned (&nb)[3]) {
+  for (int d = 0; d < 3; ++d) {
+    nb[d] = flux_main_blocks(G);
+    if (!G.per[d]) {
+      const size_t nbnd = (size_t)G.n[0] * G.n[1] * G.n[2] / G.n[d];
+      nb[d] += (unsigned)((nbnd + 63) / 64);
+    }
+  }
+}
+
+// Cell (i, j, k) at position p of the banded order: bands of `band` rows
+// along y, then z, then y within the band, then x.  Consecutive flux blocks
+// cover consecutive positions, so the lower y- and z-neighbours of a
+// block's cells were read by blocks shortly before it.
+HGKS_FN void banded_cell(const BoxGrid& G, uint32_t p, int (&c)[3]) {
+  const uint32_t full = (uint32_t)G.n[0] * G.band * G.band_full * G.n[2];
+  int jb, jj;
+  if (p < full) {
+    const uint32_t band = (uint32_t)((double)p * G.inv_band[0]);
+    const uint32_t r = p - band * (uint32_t)(G.n[0] * G.band * G.n[2]);
+    const uint32_t k = (uint32_t)((double)r * G.inv_band[1]);
+    const uint32_t r2 = r - k * (uint32_t)(G.n[0] * G.band);
+    const uint32_t j = (uint32_t)((double)r2 * G.inv_n[0]);
+    c[0] = (int)(r2 - j * (uint32_t)G.n[0]);
+    c[2] = (int)k;
+    jb = (int)band * G.band;
+    jj = (int)j;
+  } else {
+    const uint32_t r = p - full;
+    const uint32_t k = (uint32_t)((double)r * G.inv_band[2]);
+    const uint32_t r2 = r - k * (uint32_t)(G.n[0] * G.band_tail);
+    const uint32_t j = (uint32_t)((double)r2 * G.inv_n[0]);
+    c[0] = (int)(r2 - j * (uint32_t)G.n[0]);
+    c[2] = (int)k;
+    jb = G.band_full * G.band;
+    jj = (int)j;
+  }
+  c[1] = jb + jj;
+}
+
+// Face of lane `slot` (0..63) of block lb of direction D: the cell on its
+// upper side (which may be the outflow ghost beyond the last cell) and its
+// index in the face grid.  Returns false for slots past the end (their
+// face is the last one of the range, so that the four-lane sums stay
+// well-defined; the result is not written).
+HGKS_FN bool face_of_block(const BoxGrid& G, int D, unsigned lb, unsigned slot, int (&c)[3], size_t& f) {
+  const unsigned nmain = (unsigned)(((size_t)G.n[0] * G.n[1] * G.n[2] + 63) / 64);
+  const uint32_t N = (uint32_t)G.n[0] * G.n[1] * G.n[2];
+  bool live;
+  if (lb < nmain) {
+    uint32_t p = lb * 64u + slot;
+    live = p < N;
+    if (!live) p = N - 1;
+    banded_cell(G, p, c);
+  } else {
+    // Upper boundary plane of an outflow axis D: the other two axes in
+    // increasing order, the first fastest.
+    const int a0 = D == 0 ? 1 : 0, a1 = D == 2 ? 1 : 2;
+    const uint32_t nbnd = (uint32_t)G.n[a0] * G.n[a1];
+    uint32_t e = (lb - nmain) * 64u + slot;
+    live = e < nbnd;
+    if (!live) e = nbnd - 1;
+    const uint32_t q = (uint32_t)((double)e * div_inv(G.n[a0]));
+    c[a0] = (int)(e - q * (uint32_t)G.n[a0]);
+    c[a1] = (int)q;
+    c[D] = G.n[D];
+  }
+  f = (size_t)c[0] + (size_t)G.nf[D][0] * ((size_t)c[1] + (size_t)G.nf[D][1] * c[2]);
+  return live;
 }
 
 // Coefficient layout: blocks of kCB = 64 / sizeof(TC) consecutive
@@ -322,21 +413,19 @@ HGKS_FN void eval_box_gp_dir(int D, const TC* __restrict__ coef, size_t cell, TC
 }
 
 // One lane = one Gauss point of one face normal to axis D; the four lanes of
-// a face sum their weighted fluxes with lane shuffles.  tid enumerates
-// (face, Gauss point) with the face index x-fastest.
+// a face sum their weighted fluxes with lane shuffles.  Lane l of the
+// 256-lane block lb of direction D takes Gauss point l % 4 of face slot
+// l / 4 (face_of_block).
 template <typename TC>
 __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
-                                              TC dt, TC idt, size_t NF, size_t tid, int D) {
+                                              TC dt, TC idt, unsigned lb, int D) {
   const FaceAxes ax = face_axes(D);
-  const int gpi = (int)(tid & 3);
-  size_t f = tid >> 2;
-  const bool live = f < NF;
-  if (!live) f = NF - 1;  // keep the lane in the 4-lane sum; its result is not written
-  int f0, f1, f2;
-  split_index((uint32_t)f, G.nf[D][0], G.nf[D][1], G.inv_nf[D][0], G.inv_nf[D][1], f0, f1, f2);
-  int cR[3] = {f0, f1, f2};
-  int cL[3] = {f0, f1, f2};
+  const int gpi = (int)(threadIdx.x & 3);
+  int cR[3];
+  size_t f;
+  const bool live = face_of_block(G, D, lb, threadIdx.x >> 2, cR, f);
+  int cL[3] = {cR[0], cR[1], cR[2]};
   cL[D] -= 1;
   size_t iL = 0, iR = 0;
   {
@@ -377,6 +466,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     dF[i] += __shfl_xor(dF[i], 2);
   }
   if (live && gpi == 0) {
+    const size_t NF = (size_t)G.nf[D][0] * G.nf[D][1] * G.nf[D][2];
     const int gv[5] = {0, 1 + ax.D, 1 + ax.A, 1 + ax.B, 4};
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -386,30 +476,41 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   }
 }
 
-// All faces of the three directions in one launch: logical blocks
-// [0, nb0) take x-faces, [nb0, nb0+nb1) y-faces, the rest z-faces.
+// Direction and block within that direction of logical flux block b, for
+// nb[d] blocks of 64 faces per direction.  The three directions are
+// interleaved (b % 3) while all have blocks left, so that the x-, y- and
+// z-faces of the same cells run at nearly the same time on the same XCD
+// and share its L2 for the cells' coefficients; the remaining blocks of
+// the longer directions follow in order.
+HGKS_FN void flux_block(unsigned b, const unsigned (&nb)[3], int& D, unsigned& lb) {
+  const unsigned m = min(nb[0], min(nb[1], nb[2]));
+  if (b < 3 * m) {
+    D = (int)(b % 3);
+    lb = b / 3;
+    return;
+  }
+  b -= 3 * m;
+  D = 0;
+  while (D < 2 && b >= nb[D] - m) {
+    b -= nb[D] - m;
+    ++D;
+  }
+  lb = m + b;
+}
+
+// All faces of the three directions in one launch (see flux_block).
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
     const TC* __restrict__ coef, const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy,
-    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, size_t NF0, size_t NF1, size_t NF2,
-    unsigned nb0, unsigned nb1, unsigned nb2) {
-  unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, unsigned nb0, unsigned nb1, unsigned nb2) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= nb0 + nb1 + nb2) return;
-  int D = 0;
-  TC* face = fx;
-  size_t NF = NF0;
-  if (b >= nb0 + nb1) {
-    D = 2;
-    b -= nb0 + nb1;
-    face = fz;
-    NF = NF2;
-  } else if (b >= nb0) {
-    D = 1;
-    b -= nb0;
-    face = fy;
-    NF = NF1;
-  }
-  flux_box_face(coef, mask, face, G, gp, dt, idt, NF, (size_t)b * kBlock + threadIdx.x, D);
+  const unsigned nb[3] = {nb0, nb1, nb2};
+  int D;
+  unsigned lb;
+  flux_block(b, nb, D, lb);
+  TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
+  flux_box_face(coef, mask, face, G, gp, dt, idt, lb, D);
 }
 
 // ---------------------------------------------------------------- update

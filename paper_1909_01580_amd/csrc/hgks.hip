@@ -240,11 +240,12 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
     prof_mark(c, HGKS_PHASE_FALLBACK, false);
     if (hgks_status s = launched(c, "positivity")) return s;
   }
-  const unsigned nbx = blocks_for(4 * D.NF[0]), nby = blocks_for(4 * D.NF[1]), nbz = blocks_for(4 * D.NF[2]);
+  unsigned nb[3];
+  flux_block_counts(c->G, nb);
   prof_mark(c, HGKS_PHASE_FLUX, true);
-  hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nbx + nby + nbz)), dim3(kBlock), 0, c->stream, coef, c->mask(),
-                     (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), TC(1.0 / dt), D.NF[0],
-                     D.NF[1], D.NF[2], nbx, nby, nbz);
+  hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nb[0] + nb[1] + nb[2])), dim3(kBlock), 0, c->stream, coef,
+                     c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), TC(1.0 / dt),
+                     nb[0], nb[1], nb[2]);
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
@@ -737,11 +738,13 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
     g.t_cell = tc;
     g.t_flux = tf;
     g.nt_cell = blocks_for(D.N);
+    unsigned nb[3];
+    flux_block_counts(g.G, nb);
     for (int d = 0; d < 3; ++d) {
       g.NF[d] = D.NF[d];
       g.face_off[d] = F;
       F += 10 * D.NF[d];
-      g.nt_flux[d] = blocks_for(4 * D.NF[d]);
+      g.nt_flux[d] = nb[d];
       tf += g.nt_flux[d];
     }
     tc += g.nt_cell;
