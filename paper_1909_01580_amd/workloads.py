@@ -115,9 +115,9 @@ def sine_mesh_vertices(n, t, amp=0.1, omega=np.pi, length=2.0, static=False):
     return np.ascontiguousarray(np.stack([X + disp, Y + disp, Z + disp]))
 
 
-def _trilinear_points(verts, period, node):
-    """Physical points and |J| at parametric offsets ``node`` (3,) in every
-    cell of a periodic vertex grid (library layout)."""
+def _cell_corners(verts, period):
+    """The eight corner arrays (3, i, j, k) of every cell of a periodic
+    vertex grid (library layout), keyed by the corner bits (a, b, c)."""
     v = np.transpose(verts, (0, 3, 2, 1))  # (3, i, j, k)
     n = v.shape[1:]
     corners = {}
@@ -131,6 +131,14 @@ def _trilinear_points(verts, period, node):
                         last[d] = n[d] - 1
                         arr[(d,) + tuple(last)] += period[d]
                 corners[(a, b, c)] = arr
+    return corners
+
+
+def _trilinear_points(verts, period, node, corners=None):
+    """Physical points and |J| at parametric offsets ``node`` (3,) in every
+    cell of a periodic vertex grid (library layout)."""
+    if corners is None:
+        corners = _cell_corners(verts, period)
     xi, eta, zeta = node
     X = 0.0
     dX = [0.0, 0.0, 0.0]
@@ -150,10 +158,11 @@ def hex_average(verts, period, point_fn):
     Returns the library layout [5][nz][ny][nx]."""
     acc = 0.0
     vol = 0.0
+    corners = _cell_corners(verts, period)
     for a in range(3):
         for b in range(3):
             for c in range(3):
-                X, J = _trilinear_points(verts, period, (_GL3_X[a], _GL3_X[b], _GL3_X[c]))
+                X, J = _trilinear_points(verts, period, (_GL3_X[a], _GL3_X[b], _GL3_X[c]), corners)
                 w = _GL3_W[a] * _GL3_W[b] * _GL3_W[c] * J
                 acc = acc + w * point_fn(X[0], X[1], X[2])
                 vol = vol + w
