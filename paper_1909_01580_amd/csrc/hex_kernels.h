@@ -13,7 +13,7 @@
 //
 // Per-stage geometry record of a cell (doubles, SoA [kHexGeo][N]): volume,
 // centroid (3), central second moments xx, yy, zz, xy, yz, xz (6), all by
-// the 2x2x2 rule.  The average over neighbour cell o of the scaled
+// the 2x2x2 rule, then h = |Omega|^(1/3) and 1/h.  The average over neighbour cell o of the scaled
 // monomials X^n, X = (x - c_i)/h_i, h_i = |Omega_i|^(1/3), follows from
 // o's record: mean X = (c_o - c_i)/h_i, mean X_a X_b = (M_o,ab + (c_o -
 // c_i)_a (c_o - c_i)_b)/h_i^2; this fills the rows of the least-squares
@@ -31,13 +31,15 @@
 // and the stage update acts on |Omega| Q and |Omega| together.
 #pragma once
 
+#include <cstring>
+
 #include "box_kernels.h"
 #include "common.h"
 #include "gks_flux.h"
 
 namespace hgks {
 
-constexpr int kHexGeo = 10;
+constexpr int kHexGeo = 12;
 constexpr int kHexFace = 12;  // F (5), dF (5), R_V, dR_V
 
 struct HexGrid {
@@ -47,6 +49,7 @@ struct HexGrid {
   const double* x1;  // vertices at t_{n+1}, or null for a static grid
   double alpha;      // stage time (t - t_n) / dt
   double inv_dt;
+  BoxGrid box;       // the same extents (all periodic) for index splitting and flux block order
 };
 
 inline void hex_setup(HexGrid& H, const int n[3], const double period[3]) {
@@ -57,9 +60,22 @@ inline void hex_setup(HexGrid& H, const int n[3], const double period[3]) {
   H.x0 = H.x1 = nullptr;
   H.alpha = 0.0;
   H.inv_dt = 0.0;
+  std::memset(&H.box, 0, sizeof H.box);
+  for (int d = 0; d < 3; ++d) {
+    H.box.n[d] = H.box.nr[d] = n[d];
+    H.box.per[d] = 1;
+    for (int e = 0; e < 3; ++e) H.box.nf[d][e] = n[e];
+  }
+  set_index_split(H.box);
 }
 
-__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+// Index within [0, n) of a periodic index c in [-n, 2n) and the number of
+// periods w it was moved by (c = wrapped + w n).  Every caller stays within
+// one period of the grid.
+__device__ __forceinline__ int wrap_once(int c, int n, int& w) {
+  w = c < 0 ? -1 : (c >= n ? 1 : 0);
+  return c - w * n;
+}
 
 // Position and velocity of vertex (i, j, k) (indices may leave [0, n): the
 // periodic image is shifted by the period along that axis).
@@ -68,8 +84,8 @@ __device__ __forceinline__ void hex_vertex(const HexGrid& H, int i, int j, int k
   double s[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int w = floordiv(c[d], H.n[d]);
-    c[d] -= w * H.n[d];
+    int w;
+    c[d] = wrap_once(c[d], H.n[d], w);
     s[d] = w * H.period[d];
   }
   const size_t N = (size_t)H.n[0] * H.n[1] * H.n[2];
@@ -146,7 +162,8 @@ __device__ __forceinline__ void face_corners(const HexGrid& H, int d, int i, int
 __global__ void __launch_bounds__(kBlock) k_geometry_hex(HexGrid H, double* __restrict__ geo, size_t N) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
-  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  int i, j, k;
+  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
   double cx[8][3];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
@@ -200,6 +217,9 @@ __global__ void __launch_bounds__(kBlock) k_geometry_hex(HexGrid H, double* __re
   for (int e = 0; e < 3; ++e) geo[(1 + e) * N + idx] = c[e];
 #pragma unroll
   for (int e = 0; e < 6; ++e) geo[(4 + e) * N + idx] = M[e] / V;
+  const double h = cbrt(V);
+  geo[10 * N + idx] = h;
+  geo[11 * N + idx] = 1.0 / h;
 }
 
 // ---------------------------------------------------------------- K2
@@ -214,17 +234,16 @@ __device__ __forceinline__ size_t hex_index(const HexGrid& H, int i, int j, int 
   int c[3] = {i, j, k};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const int w = floordiv(c[d], H.n[d]);
-    c[d] -= w * H.n[d];
+    int w;
+    c[d] = wrap_once(c[d], H.n[d], w);
     shift[d] = w * H.period[d];
   }
   return ((size_t)c[2] * H.n[1] + c[1]) * H.n[0] + c[0];
 }
 
 __device__ __forceinline__ void load_cell(const double* __restrict__ geo, size_t N, size_t idx, HexCell& C) {
-  const double V = geo[idx];
-  C.h = cbrt(V);
-  C.ih = 1.0 / C.h;
+  C.h = geo[10 * N + idx];
+  C.ih = geo[11 * N + idx];
 #pragma unroll
   for (int e = 0; e < 3; ++e) C.c[e] = geo[(1 + e) * N + idx];
   const double ih2 = C.ih * C.ih;
@@ -430,7 +449,8 @@ __global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* _
                                                       size_t N) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
-  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  int i, j, k;
+  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
   HexCell Ci;
   load_cell(geo, N, idx, Ci);
   double qc[5];
@@ -485,17 +505,29 @@ __global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* _
   double w0[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) w0[v] = S[v];
-  // Largest |X| components and basis magnitudes over the 24 Gauss points,
-  // for the bound of |P_m - Q| used by the fallback pre-test.
+  // Bounds of the basis magnitudes over the 24 face Gauss points, for the
+  // bound of |P_m - Q| used by the fallback pre-test.  The Gauss points
+  // are convex combinations of the cell's vertices (bilinear faces), so
+  // |X_e| <= max over the vertices; then |X_e^2 - m_ee| <= max(Xmax_e^2,
+  // m_ee) and |X_a X_b - m_ab| <= Xmax_a Xmax_b + |m_ab|.
   double pmax[9];
+  {
+    double xm[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int n = 0; n < 9; ++n) pmax[n] = 0.0;
-#pragma unroll 1
-  for (int bit = 0; bit < 24; ++bit) {
-    double X[3];
-    cell_gp(H, Ci, i, j, k, bit, X);
+    for (int m = 0; m < 8; ++m) {
+      double xv[3], uv[3];
+      hex_vertex(H, i + ((m >> 2) & 1), j + ((m >> 1) & 1), k + (m & 1), xv, uv);
 #pragma unroll
-    for (int n = 0; n < 9; ++n) pmax[n] = fmax(pmax[n], fabs(pbasis(n, X, Ci.m)));
+      for (int e = 0; e < 3; ++e) xm[e] = fmax(xm[e], fabs((xv[e] - Ci.c[e]) * Ci.ih));
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      pmax[e] = xm[e];
+      pmax[3 + e] = fmax(xm[e] * xm[e], Ci.m[e]);
+    }
+    pmax[6] = xm[0] * xm[1] + fabs(Ci.m[3]);
+    pmax[7] = xm[1] * xm[2] + fabs(Ci.m[4]);
+    pmax[8] = xm[0] * xm[2] + fabs(Ci.m[5]);
   }
 #pragma unroll 1
   for (int m = 0; m < 24; ++m) {
@@ -554,7 +586,8 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
   if (mask[idx] != kNeedsCheck) return;
-  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  int i, j, k;
+  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
   HexCell Ci;
   load_cell(geo, N, idx, Ci);
   double qc[5];
@@ -677,15 +710,18 @@ __device__ __forceinline__ void to_global(const double (&f)[5], const double (&u
   g[4] = f[4] + (M[0] * u[0] + M[1] * u[1] + M[2] * u[2]) + 0.5 * uu * f[0];
 }
 
-template <int D, typename TC>
-__device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
-                                              const uint32_t* __restrict__ mask, TC* __restrict__ face,
-                                              const GasParams<TC>& gp, TC dt, TC idt, size_t N, size_t tid) {
-  const int gpi = (int)(tid & 3);
-  size_t f = tid >> 2;
-  const bool live = f < N;
-  if (!live) f = N - 1;
-  const int c[3] = {(int)(f % H.n[0]), (int)((f / H.n[0]) % H.n[1]), (int)(f / ((size_t)H.n[0] * H.n[1]))};
+// One lane = one Gauss point of one face normal to axis D (uniform over the
+// workgroup); lane l of block lb takes Gauss point l % 4 of face slot l / 4
+// in the flux block order of the box kernels (face_of_block).
+template <typename TC>
+__device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __restrict__ coef,
+                                              const double* __restrict__ geo, const uint32_t* __restrict__ mask,
+                                              TC* __restrict__ face, const GasParams<TC>& gp, TC dt, TC idt, size_t N,
+                                              unsigned lb, int D) {
+  const int gpi = (int)(threadIdx.x & 3);
+  int c[3];
+  size_t f;
+  const bool live = face_of_block(H.box, D, lb, threadIdx.x >> 2, c, f);
   // Face on the lower side of cell c along D: plane c[D].
   double cx[4][3], cu[4][3];
   face_corners(H, D, c[0], c[1], c[2], cx, cu);
@@ -699,11 +735,12 @@ __device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ 
   for (int e = 0; e < 3; ++e) adot[e] = t1[e] + t2[e];
   const double area = sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]);
   double nx[3], ny[3], nz[3];
-  const double lb = sqrt(Pt.xb[0] * Pt.xb[0] + Pt.xb[1] * Pt.xb[1] + Pt.xb[2] * Pt.xb[2]);
+  const double iarea = d_rcp(area);
+  const double ilb = d_rcp(sqrt(Pt.xb[0] * Pt.xb[0] + Pt.xb[1] * Pt.xb[1] + Pt.xb[2] * Pt.xb[2]));
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    nx[e] = av[e] / area;
-    nz[e] = Pt.xb[e] / lb;
+    nx[e] = av[e] * iarea;
+    nz[e] = Pt.xb[e] * ilb;
   }
   cross3(nz, nx, ny);
 
@@ -724,9 +761,11 @@ __device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ 
     to_local(val, grad, Pt.u, nx, ny, nz, W, dW);
     side_terms<+1>(W, dW, gp, acc);
   }
+  size_t iRt = iR;
+  after_left_side(iRt, acc);
   {
     double val[5], grad[5][3];
-    eval_hex(coef, geo, N, iR, shR, Pt.x, fbR, val, grad);
+    eval_hex(coef, geo, N, iRt, shR, Pt.x, fbR, val, grad);
     TC W[5], dW[3][5];
     to_local(val, grad, Pt.u, nx, ny, nz, W, dW);
     side_terms<-1>(W, dW, gp, acc);
@@ -764,19 +803,21 @@ __device__ __forceinline__ void flux_hex_face(HexGrid H, const TC* __restrict__ 
   }
 }
 
+// All faces of the three directions in one launch, nb blocks of 64 faces per
+// direction, interleaved (flux_block).
 template <typename TC>
-__global__ void __launch_bounds__(kBlock) k_flux_hex(HexGrid H, const TC* __restrict__ coef,
-                                                     const double* __restrict__ geo, const uint32_t* __restrict__ mask,
-                                                     TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
-                                                     GasParams<TC> gp, TC dt, TC idt, size_t N, unsigned nb) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+    k_flux_hex(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
+               const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
+               GasParams<TC> gp, TC dt, TC idt, size_t N, unsigned nb) {
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b < nb) {
-    flux_hex_face<0>(H, coef, geo, mask, fx, gp, dt, idt, N, (size_t)b * kBlock + threadIdx.x);
-  } else if (b < 2 * nb) {
-    flux_hex_face<1>(H, coef, geo, mask, fy, gp, dt, idt, N, (size_t)(b - nb) * kBlock + threadIdx.x);
-  } else if (b < 3 * nb) {
-    flux_hex_face<2>(H, coef, geo, mask, fz, gp, dt, idt, N, (size_t)(b - 2 * nb) * kBlock + threadIdx.x);
-  }
+  if (b >= 3 * nb) return;
+  const unsigned nbs[3] = {nb, nb, nb};
+  int D;
+  unsigned lb;
+  flux_block(b, nbs, D, lb);
+  TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
+  flux_hex_face(H, coef, geo, mask, face, gp, dt, idt, N, lb, D);
 }
 
 // ---------------------------------------------------------------- K4
@@ -791,7 +832,8 @@ __global__ void __launch_bounds__(kBlock) k_update_hex(HexGrid H, double* __rest
                                                        double dt, int mode, size_t N) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
-  const int c[3] = {(int)(idx % H.n[0]), (int)((idx / H.n[0]) % H.n[1]), (int)(idx / ((size_t)H.n[0] * H.n[1]))};
+  int c[3];
+  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], c[0], c[1], c[2]);
   const TF* fs[3] = {fx, fy, fz};
   double R[12];
 #pragma unroll
@@ -836,7 +878,8 @@ __global__ void __launch_bounds__(kBlock) k_dt_hex(HexGrid H, const double* __re
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   double val = 1e300;
   if (idx < N) {
-    const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+    int i, j, k;
+  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
     double cx[8][3];
     for (int m = 0; m < 8; ++m) {
       double u[3];
@@ -886,7 +929,8 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_hex(HexGrid H, const TC* __
                                                          double* __restrict__ out) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
-  const int i = (int)(idx % H.n[0]), j = (int)((idx / H.n[0]) % H.n[1]), k = (int)(idx / ((size_t)H.n[0] * H.n[1]));
+  int i, j, k;
+  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
   const double zero[3] = {0.0, 0.0, 0.0};
   for (int bit = 0; bit < 24; ++bit) {
     const int f = bit >> 2, gp = bit & 3, d = f >> 1;
