@@ -251,39 +251,76 @@ __device__ __forceinline__ void load_cell(const double* __restrict__ geo, size_t
   for (int e = 0; e < 6; ++e) C.m[e] = geo[(4 + e) * N + idx] * ih2;
 }
 
-// Row of the least-squares system for neighbour cell o in the scaled basis
-// of cell i: mean over o of (X, X_x^2 - m_xx, ..., X_x X_z - m_xz).
-__device__ __forceinline__ void ls_row(const HexCell& Ci, const double* __restrict__ geo, size_t N, size_t io,
-                                       const double (&shift)[3], double (&r)[9]) {
-  double d[3];
+// Neighbour data of the least-squares rows of cell i: for the neighbour at
+// offset o, the scaled centroid offset d = (c_o - c_i) / h_i, optionally
+// the neighbour's central second moments over h_i^2, and q_o - q_i of the
+// five variables.  Two sources with identical arithmetic: global memory
+// (any cell) and a workgroup tile staged in LDS.
+struct NbrGlobal {
+  const HexGrid& H;
+  const double* __restrict__ geo;
+  const double* __restrict__ q;
+  size_t N;
+  int i, j, k;
+  template <bool MOM>
+  __device__ __forceinline__ void get(int ox, int oy, int oz, const HexCell& Ci, const double (&qc)[5],
+                                      double (&d)[3], double (&mo)[6], double (&dq)[5]) const {
+    double sh[3];
+    const size_t io = hex_index(H, i + ox, j + oy, k + oz, sh);
 #pragma unroll
-  for (int e = 0; e < 3; ++e) d[e] = (geo[(1 + e) * N + io] + shift[e] - Ci.c[e]) * Ci.ih;
-  const double ih2 = Ci.ih * Ci.ih;
-  double mo[6];
+    for (int e = 0; e < 3; ++e) d[e] = (geo[(1 + e) * N + io] + sh[e] - Ci.c[e]) * Ci.ih;
+    if (MOM) {
+      const double ih2 = Ci.ih * Ci.ih;
 #pragma unroll
-  for (int e = 0; e < 6; ++e) mo[e] = geo[(4 + e) * N + io] * ih2;
-  r[0] = d[0];
-  r[1] = d[1];
-  r[2] = d[2];
-  r[3] = mo[0] + d[0] * d[0] - Ci.m[0];
-  r[4] = mo[1] + d[1] * d[1] - Ci.m[1];
-  r[5] = mo[2] + d[2] * d[2] - Ci.m[2];
-  r[6] = mo[3] + d[0] * d[1] - Ci.m[3];
-  r[7] = mo[4] + d[1] * d[2] - Ci.m[4];
-  r[8] = mo[5] + d[0] * d[2] - Ci.m[5];
-}
+      for (int e = 0; e < 6; ++e) mo[e] = geo[(4 + e) * N + io] * ih2;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) dq[v] = q[v * N + io] - qc[v];
+  }
+};
+
+// LDS tile of the reconstruction: a kTX x kTY x kTZ block of cells and one
+// layer around it; per cell the centroid of its periodic image (shift
+// included), the central second moments and the five variables.
+constexpr int kTX = 8, kTY = 8, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHalo = kHX * kHY * kHZ;
+
+struct HexTile {
+  double c[3][kHalo];
+  double m[6][kHalo];
+  double q[5][kHalo];
+};
+
+struct NbrTile {
+  const HexTile& T;
+  int base;  // tile index of the cell itself
+  template <bool MOM>
+  __device__ __forceinline__ void get(int ox, int oy, int oz, const HexCell& Ci, const double (&qc)[5],
+                                      double (&d)[3], double (&mo)[6], double (&dq)[5]) const {
+    const int s = base + (oz * kHY + oy) * kHX + ox;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) d[e] = (T.c[e][s] - Ci.c[e]) * Ci.ih;
+    if (MOM) {
+      const double ih2 = Ci.ih * Ci.ih;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) mo[e] = T.m[e][s] * ih2;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) dq[v] = T.q[v][s] - qc[v];
+  }
+};
 
 // In-place Cholesky factorisation of a symmetric positive definite 9x9
-// matrix stored as its lower triangle L[i*(i+1)/2 + j].
+// matrix stored as its lower triangle L[i*(i+1)/2 + j]; the diagonal
+// entries are left as their reciprocals, which is all the solves need.
 __device__ __forceinline__ void chol9(double (&L)[45]) {
 #pragma unroll
   for (int j = 0; j < 9; ++j) {
     double s = L[j * (j + 1) / 2 + j];
 #pragma unroll
     for (int k = 0; k < j; ++k) s -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-    const double djj = sqrt(s);
-    L[j * (j + 1) / 2 + j] = djj;
-    const double inv = 1.0 / djj;
+    const double inv = d_rcp(sqrt(s));
+    L[j * (j + 1) / 2 + j] = inv;
 #pragma unroll
     for (int i = j + 1; i < 9; ++i) {
       double t = L[i * (i + 1) / 2 + j];
@@ -300,14 +337,14 @@ __device__ __forceinline__ void chol9_solve(const double (&L)[45], double (&x)[9
     double t = x[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) t -= L[i * (i + 1) / 2 + k] * x[k];
-    x[i] = t / L[i * (i + 1) / 2 + i];
+    x[i] = t * L[i * (i + 1) / 2 + i];
   }
 #pragma unroll
   for (int i = 8; i >= 0; --i) {
     double t = x[i];
 #pragma unroll
     for (int k = i + 1; k < 9; ++k) t -= L[k * (k + 1) / 2 + i] * x[k];
-    x[i] = t / L[i * (i + 1) / 2 + i];
+    x[i] = t * L[i * (i + 1) / 2 + i];
   }
 }
 
@@ -328,10 +365,10 @@ __device__ __forceinline__ void sub_offsets(int m, int (&o)[4][3]) {
 }
 
 // Linear least squares of sub-stencil m for all five variables of cell
-// (i,j,k): b[v][3] in the scaled basis.
-__device__ __forceinline__ void sub_fit(const HexGrid& H, const HexCell& Ci, const double* __restrict__ geo,
-                                        const double* __restrict__ q, size_t N, int i, int j, int k,
-                                        const double (&qc)[5], int m, double (&b)[5][3]) {
+// i: b[v][3] in the scaled basis.
+template <typename NB>
+__device__ __forceinline__ void sub_fit(const NB& nb, const HexCell& Ci, const double (&qc)[5], int m,
+                                        double (&b)[5][3]) {
   int o[4][3];
   sub_offsets(m, o);
   double A[6] = {0, 0, 0, 0, 0, 0};  // xx, yy, zz, xy, yz, xz
@@ -340,11 +377,8 @@ __device__ __forceinline__ void sub_fit(const HexGrid& H, const HexCell& Ci, con
   for (int v = 0; v < 5; ++v) r[v][0] = r[v][1] = r[v][2] = 0.0;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    double sh[3];
-    const size_t io = hex_index(H, i + o[s][0], j + o[s][1], k + o[s][2], sh);
-    double d[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) d[e] = (geo[(1 + e) * N + io] + sh[e] - Ci.c[e]) * Ci.ih;
+    double d[3], mo[6], dq[5];
+    nb.template get<false>(o[s][0], o[s][1], o[s][2], Ci, qc, d, mo, dq);
     A[0] += d[0] * d[0];
     A[1] += d[1] * d[1];
     A[2] += d[2] * d[2];
@@ -353,9 +387,8 @@ __device__ __forceinline__ void sub_fit(const HexGrid& H, const HexCell& Ci, con
     A[5] += d[0] * d[2];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double dq = q[v * N + io] - qc[v];
 #pragma unroll
-      for (int e = 0; e < 3; ++e) r[v][e] += d[e] * dq;
+      for (int e = 0; e < 3; ++e) r[v][e] += d[e] * dq[v];
     }
   }
   // closed-form inverse of the symmetric 3x3 normal matrix
@@ -365,7 +398,7 @@ __device__ __forceinline__ void sub_fit(const HexGrid& H, const HexCell& Ci, con
   const double c11 = A[0] * A[2] - A[5] * A[5];
   const double c12 = A[3] * A[5] - A[0] * A[4];
   const double c22 = A[0] * A[1] - A[3] * A[3];
-  const double idet = 1.0 / (A[0] * c00 + A[3] * c01 + A[5] * c02);
+  const double idet = d_rcp(A[0] * c00 + A[3] * c01 + A[5] * c02);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     b[v][0] = idet * (c00 * r[v][0] + c01 * r[v][1] + c02 * r[v][2]);
@@ -374,10 +407,12 @@ __device__ __forceinline__ void sub_fit(const HexGrid& H, const HexCell& Ci, con
   }
 }
 
-// Quadratic least squares of the big stencil for all five variables.
-__device__ __forceinline__ void big_fit(const HexGrid& H, const HexCell& Ci, const double* __restrict__ geo,
-                                        const double* __restrict__ q, size_t N, int i, int j, int k,
-                                        const double (&qc)[5], double (&a)[5][9]) {
+// Quadratic least squares of the big stencil for all five variables: the
+// row of neighbour o is the mean over o of (X, X_x^2 - m_xx, ...,
+// X_x X_z - m_xz) in the scaled basis of cell i.
+template <typename NB>
+__device__ __forceinline__ void big_fit(const NB& nb, const HexCell& Ci, const double (&qc)[5],
+                                        double (&a)[5][9]) {
   double L[45];
 #pragma unroll
   for (int e = 0; e < 45; ++e) L[e] = 0.0;
@@ -390,19 +425,26 @@ __device__ __forceinline__ void big_fit(const HexGrid& H, const HexCell& Ci, con
     const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = s / 9 - 1;
     const int nz = (ox != 0) + (oy != 0) + (oz != 0);
     if (nz == 0 || nz == 3) continue;
-    double sh[3];
-    const size_t io = hex_index(H, i + ox, j + oy, k + oz, sh);
+    double d[3], mo[6], dq[5];
+    nb.template get<true>(ox, oy, oz, Ci, qc, d, mo, dq);
     double r[9];
-    ls_row(Ci, geo, N, io, sh, r);
+    r[0] = d[0];
+    r[1] = d[1];
+    r[2] = d[2];
+    r[3] = mo[0] + d[0] * d[0] - Ci.m[0];
+    r[4] = mo[1] + d[1] * d[1] - Ci.m[1];
+    r[5] = mo[2] + d[2] * d[2] - Ci.m[2];
+    r[6] = mo[3] + d[0] * d[1] - Ci.m[3];
+    r[7] = mo[4] + d[1] * d[2] - Ci.m[4];
+    r[8] = mo[5] + d[0] * d[2] - Ci.m[5];
 #pragma unroll
     for (int p = 0; p < 9; ++p)
 #pragma unroll
       for (int t = 0; t <= p; ++t) L[p * (p + 1) / 2 + t] += r[p] * r[t];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double dq = q[v * N + io] - qc[v];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) a[v][e] += r[e] * dq;
+      for (int e = 0; e < 9; ++e) a[v][e] += r[e] * dq[v];
     }
   }
   chol9(L);
@@ -442,22 +484,56 @@ __device__ __forceinline__ double pbasis(int n, const double (&X)[3], const doub
 // WENO-AO reconstruction on a hexahedral cell (always in double): the
 // combined quadratic in the scaled basis, written as (mean, 9 coefficients)
 // per variable, and the fallback pre-test.
+//
+// One workgroup per kTX x kTY x kTZ tile of cells (tiles x-fastest): the
+// tile and one layer around it are staged in LDS first, so that the 18
+// big-stencil rows and the 2 x 24 sub-stencil fits of every cell read their
+// neighbours from LDS instead of issuing some 1,800 global loads per cell.
+// Grid extents need not be multiples of the tile: the lanes of cells beyond
+// the grid only help to fill the tile.
 template <typename TS>
-__global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* __restrict__ geo,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_recon_hex(HexGrid H, const double* __restrict__ geo,
                                                       const double* __restrict__ q, TS* __restrict__ coef,
                                                       uint32_t* __restrict__ mask, WenoParams<double> P, double gm1,
-                                                      size_t N) {
-  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= N) return;
-  int i, j, k;
-  split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
+                                                      size_t N, unsigned ntx, unsigned nty, unsigned ntiles) {
+  static_assert(kTX * kTY * kTZ == kBlock, "one lane per tile cell");
+  __shared__ HexTile T;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= ntiles) return;
+  const int tx = (int)(b % ntx), ty = (int)((b / ntx) % nty), tz = (int)(b / (ntx * nty));
+  const int o0 = tx * kTX, o1 = ty * kTY, o2 = tz * kTZ;
+  for (int t = threadIdx.x; t < kHalo; t += kBlock) {
+    const int g[3] = {o0 + t % kHX - 1, o1 + (t / kHX) % kHY - 1, o2 + t / (kHX * kHY) - 1};
+    int c[3];
+    double sh[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      // the tile may reach several periods past a very small grid
+      const int w = g[d] >= 0 ? g[d] / H.n[d] : -((-g[d] + H.n[d] - 1) / H.n[d]);
+      c[d] = g[d] - w * H.n[d];
+      sh[d] = w * H.period[d];
+    }
+    const size_t io = ((size_t)c[2] * H.n[1] + c[1]) * H.n[0] + c[0];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) T.c[e][t] = geo[(1 + e) * N + io] + sh[e];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) T.m[e][t] = geo[(4 + e) * N + io];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) T.q[v][t] = q[v * N + io];
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
+  const int i = o0 + lx, j = o1 + ly, k = o2 + lz;
+  if (i >= H.n[0] || j >= H.n[1] || k >= H.n[2]) return;
+  const size_t idx = ((size_t)k * H.n[1] + j) * H.n[0] + i;
+  const NbrTile nb{T, ((lz + 1) * kHY + (ly + 1)) * kHX + (lx + 1)};
   HexCell Ci;
   load_cell(geo, N, idx, Ci);
   double qc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) qc[v] = q[v * N + idx];
   double a[5][9];
-  big_fit(H, Ci, geo, q, N, i, j, k, qc, a);
+  big_fit(nb, Ci, qc, a);
 
   // beta_0 in the scaled basis: mean |grad P|^2 over the cell (second
   // moments m) plus the squared second derivatives, each multi-index once.
@@ -485,26 +561,26 @@ __global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* _
 #pragma unroll 1
   for (int m = 0; m < 24; ++m) {
     double b[5][3];
-    sub_fit(H, Ci, geo, q, N, i, j, k, qc, m, b);
+    sub_fit(nb, Ci, qc, m, b);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
       tau[v] += fabs(beta0[v] - bm);
     }
   }
-  // Pass 2: weights and the combination; running sums per variable.
-  double S[5], wb[5][3], sb[5][3], bnd[5];
+  // Pass 2: weights and the combination.  With W = sum of all weights,
+  // w0r = omega_0 / gamma_0 and off = w0r Gamma, the combined linear part
+  // is (w0r a + sum_m (omega_m - off) b^m) / W, so one running sum per
+  // variable and component suffices.
+  double S[5], wb[5][3], bnd[5], w0r[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     tau[v] *= 1.0 / 24.0;
-    S[v] = P.gamma0 * (1.0 + tau[v] / (beta0[v] + P.eps));
+    w0r[v] = 1.0 + tau[v] * d_rcp(beta0[v] + P.eps);
+    S[v] = P.gamma0 * w0r[v];
     wb[v][0] = wb[v][1] = wb[v][2] = 0.0;
-    sb[v][0] = sb[v][1] = sb[v][2] = 0.0;
     bnd[v] = 0.0;
   }
-  double w0[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) w0[v] = S[v];
   // Bounds of the basis magnitudes over the 24 face Gauss points, for the
   // bound of |P_m - Q| used by the fallback pre-test.  The Gauss points
   // are convex combinations of the cell's vertices (bilinear faces), so
@@ -532,37 +608,35 @@ __global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* _
 #pragma unroll 1
   for (int m = 0; m < 24; ++m) {
     double b[5][3];
-    sub_fit(H, Ci, geo, q, N, i, j, k, qc, m, b);
+    sub_fit(nb, Ci, qc, m, b);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
-      const double om = P.Gamma * (1.0 + tau[v] / (bm + P.eps));
+      const double om = P.Gamma * (1.0 + tau[v] * d_rcp(bm + P.eps));
       S[v] += om;
+      const double cm = om - w0r[v] * P.Gamma;
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        wb[v][e] += om * b[v][e];
-        sb[v][e] += b[v][e];
-      }
+      for (int e = 0; e < 3; ++e) wb[v][e] += cm * b[v][e];
       bnd[v] = fmax(bnd[v], fabs(b[v][0]) * pmax[0] + fabs(b[v][1]) * pmax[1] + fabs(b[v][2]) * pmax[2]);
     }
   }
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double iS = 1.0 / S[v];
-    const double w0g = w0[v] * iS / P.gamma0;
+    const double iS = d_rcp(S[v]);
+    const double w0g = w0r[v] * iS;  // wbar_0 / gamma_0
     double c[9];
 #pragma unroll
-    for (int e = 0; e < 3; ++e) c[e] = w0g * a[v][e] + iS * wb[v][e] - w0g * P.Gamma * sb[v][e];
+    for (int e = 0; e < 3; ++e) c[e] = w0g * a[v][e] + iS * wb[v][e];
 #pragma unroll
     for (int e = 3; e < 9; ++e) c[e] = w0g * a[v][e];
     double b0 = 0.0;
 #pragma unroll
     for (int n = 0; n < 9; ++n) b0 += fabs(a[v][n]) * pmax[n];
     bnd[v] = fmax(bnd[v], b0);
-    TS* cv = coef + (size_t)v * 10 * N + idx;
+    TS* cv = coef + coef_cell<TS>(idx) + v * 10 * kCB<TS>;
     cv[0] = TS(qc[v]);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) cv[(size_t)(e + 1) * N] = TS(c[e]);
+    for (int e = 0; e < 9; ++e) cv[(e + 1) * kCB<TS>] = TS(c[e]);
   }
   const double margin = 1e-10;
   const double rmin = qc[0] - bnd[0];
@@ -574,7 +648,7 @@ __global__ void __launch_bounds__(kBlock) k_recon_hex(HexGrid H, const double* _
       const double mm = fabs(qc[1 + d]) + bnd[1 + d];
       msq += mm * mm;
     }
-    safe = gm1 * (qc[4] - bnd[4] - 0.5 * msq / rmin) > margin * gm1 * (fabs(qc[4]) + bnd[4]);
+    safe = gm1 * (qc[4] - bnd[4] - 0.5 * msq * d_rcp(rmin)) > margin * gm1 * (fabs(qc[4]) + bnd[4]);
   }
   mask[idx] = safe ? 0u : kNeedsCheck;
 }
@@ -592,8 +666,9 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
   load_cell(geo, N, idx, Ci);
   double qc[5];
   for (int v = 0; v < 5; ++v) qc[v] = q[v * N + idx];
+  const NbrGlobal nb{H, geo, q, N, i, j, k};
   double a[5][9];
-  big_fit(H, Ci, geo, q, N, i, j, k, qc, a);
+  big_fit(nb, Ci, qc, a);
   uint32_t bits = 0;
   for (int bit = 0; bit < 24; ++bit) {
     double X[3];
@@ -609,7 +684,7 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
         }
       } else {
         double b[5][3];
-        sub_fit(H, Ci, geo, q, N, i, j, k, qc, m - 1, b);
+        sub_fit(nb, Ci, qc, m - 1, b);
         for (int v = 0; v < 5; ++v) val[v] = qc[v] + b[v][0] * X[0] + b[v][1] * X[1] + b[v][2] * X[2];
       }
       bad = !(val[0] > 0.0);
@@ -622,78 +697,97 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
 
 // ---------------------------------------------------------------- K3
 // Value and physical gradient of the five variables of cell idx at the
-// physical point x (centroid shifted by `shift` for periodic images).
+// physical point x (centroid shifted by `shift` for periodic images), in
+// the compute type: the scaled coordinates are formed in double (absolute
+// positions), the polynomial is evaluated in TC.  A first-order fallback
+// point gives the cell mean and zero gradient (Sec. 4).
 template <typename TC>
 __device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const double* __restrict__ geo, size_t N,
                                          size_t idx, const double (&shift)[3], const double (&x)[3], bool fb,
-                                         double (&val)[5], double (&grad)[5][3]) {
+                                         TC (&val)[5], TC (&grad)[5][3]) {
   HexCell C;
   load_cell(geo, N, idx, C);
-  double X[3];
+  TC X[3], m[6];
 #pragma unroll
-  for (int e = 0; e < 3; ++e) X[e] = (x[e] - C.c[e] - shift[e]) * C.ih;
+  for (int e = 0; e < 3; ++e) X[e] = TC((x[e] - C.c[e] - shift[e]) * C.ih);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) m[e] = TC(C.m[e]);
+  const TC ih = TC(C.ih);
+  const TC* cv = coef + coef_cell<TC>(idx);
+  constexpr int CB = kCB<TC>;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const TC* cv = coef + (size_t)v * 10 * N + idx;
-    double c[9];
+    const TC* ck = cv + v * 10 * CB;
+    TC c[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) c[e] = (double)cv[(size_t)(e + 1) * N];
-    const double q0 = (double)cv[0];
-    if (fb) {
-      val[v] = q0;
-      grad[v][0] = grad[v][1] = grad[v][2] = 0.0;
-      continue;
+    for (int e = 0; e < 9; ++e) c[e] = ck[(e + 1) * CB];
+    const TC q0 = ck[0];
+    val[v] = q0 + c[0] * X[0] + c[1] * X[1] + c[2] * X[2] + c[3] * (X[0] * X[0] - m[0]) +
+             c[4] * (X[1] * X[1] - m[1]) + c[5] * (X[2] * X[2] - m[2]) + c[6] * (X[0] * X[1] - m[3]) +
+             c[7] * (X[1] * X[2] - m[4]) + c[8] * (X[0] * X[2] - m[5]);
+    grad[v][0] = (c[0] + TC(2) * c[3] * X[0] + c[6] * X[1] + c[8] * X[2]) * ih;
+    grad[v][1] = (c[1] + TC(2) * c[4] * X[1] + c[6] * X[0] + c[7] * X[2]) * ih;
+    grad[v][2] = (c[2] + TC(2) * c[5] * X[2] + c[8] * X[0] + c[7] * X[1]) * ih;
+  }
+  if (fb) {
+    asm volatile("");
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      val[v] = cv[v * 10 * CB];
+      grad[v][0] = grad[v][1] = grad[v][2] = TC(0);
     }
-    val[v] = q0 + c[0] * X[0] + c[1] * X[1] + c[2] * X[2] + c[3] * (X[0] * X[0] - C.m[0]) +
-             c[4] * (X[1] * X[1] - C.m[1]) + c[5] * (X[2] * X[2] - C.m[2]) + c[6] * (X[0] * X[1] - C.m[3]) +
-             c[7] * (X[1] * X[2] - C.m[4]) + c[8] * (X[0] * X[2] - C.m[5]);
-    grad[v][0] = (c[0] + 2.0 * c[3] * X[0] + c[6] * X[1] + c[8] * X[2]) * C.ih;
-    grad[v][1] = (c[1] + 2.0 * c[4] * X[1] + c[6] * X[0] + c[7] * X[2]) * C.ih;
-    grad[v][2] = (c[2] + 2.0 * c[5] * X[2] + c[8] * X[0] + c[7] * X[1]) * C.ih;
   }
 }
 
 // Conservative variables seen from a frame moving with u (one vector, also
-// applied to the gradients), then rotated into the frame (nx, ny, nz).
+// applied to the gradients), then rotated into the frame (nx, ny, nz); in
+// the compute type.
 template <typename TC>
-__device__ __forceinline__ void to_local(const double (&val)[5], const double (&grad)[5][3], const double (&u)[3],
-                                         const double (&nx)[3], const double (&ny)[3], const double (&nz)[3],
+__device__ __forceinline__ void to_local(const TC (&val)[5], const TC (&grad)[5][3], const double (&ud)[3],
+                                         const double (&nxd)[3], const double (&nyd)[3], const double (&nzd)[3],
                                          TC (&W)[5], TC (&dW)[3][5]) {
-  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  TC u[3], n[3][3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    u[e] = TC(ud[e]);
+    n[0][e] = TC(nxd[e]);
+    n[1][e] = TC(nyd[e]);
+    n[2][e] = TC(nzd[e]);
+  }
+  const TC uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   // shifted values
-  double s[5];
+  TC s[5];
   s[0] = val[0];
-  double Mu = 0.0;
+  TC Mu = TC(0);
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     s[1 + e] = val[1 + e] - val[0] * u[e];
     Mu += val[1 + e] * u[e];
   }
-  s[4] = val[4] - Mu + 0.5 * val[0] * uu;
-  const double* n[3] = {nx, ny, nz};
-  W[0] = TC(s[0]);
+  s[4] = val[4] - Mu + TC(0.5) * val[0] * uu;
+  W[0] = s[0];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) W[1 + j] = TC(s[1] * n[j][0] + s[2] * n[j][1] + s[3] * n[j][2]);
-  W[4] = TC(s[4]);
+  for (int j = 0; j < 3; ++j) W[1 + j] = s[1] * n[j][0] + s[2] * n[j][1] + s[3] * n[j][2];
+  W[4] = s[4];
   // gradients: derivative along n_j of the shifted variables
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    double g[5];
+    TC g[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) g[v] = grad[v][0] * n[j][0] + grad[v][1] * n[j][1] + grad[v][2] * n[j][2];
-    double gs[5];
+    TC gs[5];
     gs[0] = g[0];
-    double gMu = 0.0;
+    TC gMu = TC(0);
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       gs[1 + e] = g[1 + e] - g[0] * u[e];
       gMu += g[1 + e] * u[e];
     }
-    gs[4] = g[4] - gMu + 0.5 * g[0] * uu;
-    dW[j][0] = TC(gs[0]);
+    gs[4] = g[4] - gMu + TC(0.5) * g[0] * uu;
+    dW[j][0] = gs[0];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) dW[j][1 + r] = TC(gs[1] * n[r][0] + gs[2] * n[r][1] + gs[3] * n[r][2]);
-    dW[j][4] = TC(gs[4]);
+    for (int r = 0; r < 3; ++r) dW[j][1 + r] = gs[1] * n[r][0] + gs[2] * n[r][1] + gs[3] * n[r][2];
+    dW[j][4] = gs[4];
   }
 }
 
@@ -717,7 +811,7 @@ template <typename TC>
 __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __restrict__ coef,
                                               const double* __restrict__ geo, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const GasParams<TC>& gp, TC dt, TC idt, size_t N,
-                                              unsigned lb, int D) {
+                                              unsigned lb, int D, double (&stash)[18][kBlock]) {
   const int gpi = (int)(threadIdx.x & 3);
   int c[3];
   size_t f;
@@ -743,6 +837,29 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     nz[e] = Pt.xb[e] * ilb;
   }
   cross3(nz, nx, ny);
+  // The point's geometry is parked in LDS (one slot per lane, no sharing)
+  // and read back where each side needs it, so that it does not occupy
+  // registers across the two sides' gas-kinetic terms: x, u, the frame,
+  // area, d|a|/dt rate and the volume rate.
+  {
+    double* g = &stash[0][threadIdx.x];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      g[(0 + e) * kBlock] = Pt.x[e];
+      g[(3 + e) * kBlock] = Pt.u[e];
+      g[(6 + e) * kBlock] = nx[e];
+      g[(9 + e) * kBlock] = ny[e];
+      g[(12 + e) * kBlock] = nz[e];
+    }
+    g[15 * kBlock] = area;
+    g[16 * kBlock] = Pt.u[0] * adot[0] + Pt.u[1] * adot[1] + Pt.u[2] * adot[2];
+    g[17 * kBlock] = 0.25 * (Pt.u[0] * av[0] + Pt.u[1] * av[1] + Pt.u[2] * av[2]);
+  }
+  const volatile double* gs = &stash[0][threadIdx.x];
+  auto get3 = [&](int k, double (&v)[3]) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) v[e] = gs[(k + e) * kBlock];
+  };
 
   int cL[3] = {c[0], c[1], c[2]};
   cL[D] -= 1;
@@ -755,21 +872,39 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   FluxAcc<TC> acc;
   acc_zero(acc);
   {
-    double val[5], grad[5][3];
-    eval_hex(coef, geo, N, iL, shL, Pt.x, fbL, val, grad);
+    double x[3], u[3], n0[3], n1[3], n2[3];
+    get3(0, x);
+    get3(3, u);
+    get3(6, n0);
+    get3(9, n1);
+    get3(12, n2);
+    TC val[5], grad[5][3];
+    eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
     TC W[5], dW[3][5];
-    to_local(val, grad, Pt.u, nx, ny, nz, W, dW);
+    to_local(val, grad, u, n0, n1, n2, W, dW);
     side_terms<+1>(W, dW, gp, acc);
   }
   size_t iRt = iR;
   after_left_side(iRt, acc);
   {
-    double val[5], grad[5][3];
-    eval_hex(coef, geo, N, iRt, shR, Pt.x, fbR, val, grad);
+    double x[3], u[3], n0[3], n1[3], n2[3];
+    get3(0, x);
+    get3(3, u);
+    get3(6, n0);
+    get3(9, n1);
+    get3(12, n2);
+    TC val[5], grad[5][3];
+    eval_hex(coef, geo, N, iRt, shR, x, fbR, val, grad);
     TC W[5], dW[3][5];
-    to_local(val, grad, Pt.u, nx, ny, nz, W, dW);
+    to_local(val, grad, u, n0, n1, n2, W, dW);
     side_terms<-1>(W, dW, gp, acc);
   }
+  double u[3], n0[3], n1[3], n2[3];
+  get3(3, u);
+  get3(6, n0);
+  get3(9, n1);
+  get3(12, n2);
+  const double area2 = gs[15 * kBlock], rate = gs[16 * kBlock], vrate = gs[17 * kBlock];
   TC Fl[5], dFl[5];
   finish_flux(acc, gp, dt, idt, Fl, dFl);
   double fl[5], dfl[5], q0l[5];
@@ -780,17 +915,16 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     q0l[e] = (double)acc.Q0[e];
   }
   double F[5], dF[5], Q0[5];
-  to_global(fl, Pt.u, nx, ny, nz, F);
-  to_global(dfl, Pt.u, nx, ny, nz, dF);
-  to_global(q0l, Pt.u, nx, ny, nz, Q0);
-  const double rate = Pt.u[0] * adot[0] + Pt.u[1] * adot[1] + Pt.u[2] * adot[2];
+  to_global(fl, u, n0, n1, n2, F);
+  to_global(dfl, u, n0, n1, n2, dF);
+  to_global(q0l, u, n0, n1, n2, Q0);
   double out[12];
 #pragma unroll
   for (int e = 0; e < 5; ++e) {
-    out[e] = 0.25 * area * F[e];
-    out[5 + e] = 0.25 * (area * dF[e] - Q0[e] * rate);
+    out[e] = 0.25 * area2 * F[e];
+    out[5 + e] = 0.25 * (area2 * dF[e] - Q0[e] * rate);
   }
-  out[10] = 0.25 * (Pt.u[0] * av[0] + Pt.u[1] * av[1] + Pt.u[2] * av[2]);
+  out[10] = vrate;
   out[11] = 0.25 * rate;
 #pragma unroll
   for (int e = 0; e < 12; ++e) {
@@ -817,7 +951,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   unsigned lb;
   flux_block(b, nbs, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
-  flux_hex_face(H, coef, geo, mask, face, gp, dt, idt, N, lb, D);
+  __shared__ double stash[18][kBlock];
+  flux_hex_face(H, coef, geo, mask, face, gp, dt, idt, N, lb, D, stash);
 }
 
 // ---------------------------------------------------------------- K4
@@ -940,7 +1075,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_hex(HexGrid H, const TC* __
     face_corners(H, d, c[0], c[1], c[2], cx, cu);
     FacePoint P;
     face_point(cx, cu, (gp >> 1) ? kGaussNode : -kGaussNode, (gp & 1) ? kGaussNode : -kGaussNode, P);
-    double val[5], grad[5][3];
+    TC val[5], grad[5][3];
     eval_hex(coef, geo, N, idx, zero, P.x, (mask[idx] >> bit) & 1u, val, grad);
     for (int v = 0; v < 5; ++v) {
       double* o = out + ((idx * 24 + bit) * 5 + v) * 4;

@@ -295,8 +295,10 @@ hgks_status hex_stage(hgks_ctx c, const double* qin, double dt, double alpha) {
   const WenoParams<double> P = weno_params<double>(c->cfg, dx);
   const GasParams<TC> gp = gas_params<TC>(c->cfg);
   prof_mark(c, HGKS_PHASE_RECON, true);
-  hipLaunchKernelGGL((k_recon_hex<TC>), dim3(blocks_for(N)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
-                     (TC*)c->coef(), c->mask(), P, c->cfg.gamma - 1.0, N);
+  const unsigned ntx = (unsigned)((c->D.n[0] + kTX - 1) / kTX), nty = (unsigned)((c->D.n[1] + kTY - 1) / kTY);
+  const unsigned ntiles = ntx * nty * (unsigned)((c->D.n[2] + kTZ - 1) / kTZ);
+  hipLaunchKernelGGL((k_recon_hex<TC>), dim3(pad8(ntiles)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                     (TC*)c->coef(), c->mask(), P, c->cfg.gamma - 1.0, N, ntx, nty, ntiles);
   prof_mark(c, HGKS_PHASE_RECON, false);
   if (hgks_status s = launched(c, "recon")) return s;
   prof_mark(c, HGKS_PHASE_FALLBACK, true);
