@@ -50,18 +50,31 @@ class Params:
     tau_C: float = 1.0
 
 
+BOUNDARIES = ("periodic", "outflow", "symmetric")
+
+
 class Problem:
     """Grid description for the oracle.
 
-    ``kind`` is 'uniform' (origin, length, per-axis 'periodic'/'outflow')
-    or 'vertices' (periodic hexahedral grid given by its vertices, library
+    ``kind`` is 'uniform' (origin, length, per-axis boundaries) or
+    'vertices' (periodic hexahedral grid given by its vertices, library
     layout [3][nz][ny][nx], optional next vertices for a moving mesh).
+    A per-axis boundary is 'periodic', 'outflow' (zero-gradient ghosts:
+    the non-reflecting condition of Sec. 4), 'symmetric' (mirror ghosts with
+    the normal momentum reversed: the symmetric condition of Sec. 4) or a
+    pair (low end, high end) of the last two.
     """
 
     def __init__(self, n, bc, params, kind, origin=None, length=None,
                  verts=None, period=None, verts_next=None):
         self.n = tuple(int(x) for x in n)
         self.bc = tuple(bc)
+        self.sides = []
+        for b in self.bc:
+            lo, hi = (b, b) if isinstance(b, str) else tuple(b)
+            assert lo in BOUNDARIES and hi in BOUNDARIES
+            assert (lo == "periodic") == (hi == "periodic"), "periodic at both ends or neither"
+            self.sides.append((lo, hi))
         self.params = params
         self.kind = kind
         self.origin, self.length = origin, length
@@ -69,7 +82,10 @@ class Problem:
         self.verts = None if verts is None else _to_ijk(np.asarray(verts, float))
         self.verts_next = None if verts_next is None else _to_ijk(np.asarray(verts_next, float))
         if kind == "vertices":
-            assert all(b == "periodic" for b in self.bc)
+            assert all(self.periodic(d) for d in range(3))
+
+    def periodic(self, d):
+        return self.sides[d][0] == "periodic"
 
     @property
     def moving(self):
@@ -92,16 +108,34 @@ class Problem:
         return geo.padded_vertices_periodic((self.verts_next - self.verts) / dt, (0.0, 0.0, 0.0))
 
     def pad_state(self, Q):
-        """Ghost cells: periodic wrap or zero-gradient copy of the nearest
-        interior cell, axis by axis."""
+        """Ghost cells, axis by axis: periodic wrap; zero-gradient copy of
+        the nearest interior cell (outflow); or the mirror image across the
+        boundary face, ghost g outside <-> interior cell g inside, with the
+        momentum component normal to that face reversed (symmetric)."""
         out = Q
         for d in range(3):
-            idx = np.arange(-PAD, self.n[d] + PAD)
-            if self.bc[d] == "periodic":
-                idx = idx % self.n[d]
+            n = self.n[d]
+            idx = np.arange(-PAD, n + PAD)
+            src = idx.copy()
+            sign = np.ones(idx.size)
+            lo, hi = self.sides[d]
+            if lo == "periodic":
+                src = idx % n
             else:
-                idx = np.clip(idx, 0, self.n[d] - 1)
-            out = np.take(out, idx, axis=1 + d)
+                below, above = idx < 0, idx >= n
+                src = np.clip(idx, 0, n - 1)
+                if lo == "symmetric":
+                    src[below] = -1 - idx[below]
+                    sign[below] = -1.0
+                if hi == "symmetric":
+                    src[above] = 2 * n - 1 - idx[above]
+                    sign[above] = -1.0
+            out = np.take(out, src, axis=1 + d)
+            if np.any(sign < 0):
+                shape = [1, 1, 1]
+                shape[d] = idx.size
+                out = out.copy()
+                out[1 + d] *= sign.reshape(shape)
         return out
 
 
@@ -128,13 +162,13 @@ def _faces(prob, rec, vp, vdot, d, dt, chunk=2048):
     """Fluxes of every face normal to axis d that the real cells need.
 
     Face f (0 <= f < nf) lies between real cells f-1 and f along d.
-    Periodic axes have nf = n_d faces (face n_d is face 0); outflow axes
+    Periodic axes have nf = n_d faces (face n_d is face 0); other axes
     have nf = n_d + 1.
     """
     P = prob.params
     n = prob.n
     a_ax, b_ax = geo.face_axes(d)
-    nf = n[d] if prob.bc[d] == "periodic" else n[d] + 1
+    nf = n[d] if prob.periodic(d) else n[d] + 1
     order = [d, a_ax, b_ax]
     inv = list(np.argsort(order))
 
@@ -280,7 +314,7 @@ def residual(prob, Q, dt, alpha=0.0, keep_faces=False):
         lo = [slice(None)] * 3
         hi = [slice(None)] * 3
         lo[d] = slice(0, n[d])
-        if prob.bc[d] == "periodic":
+        if prob.periodic(d):
             hi_idx = (np.arange(n[d]) + 1) % n[d]
         else:
             hi_idx = np.arange(n[d]) + 1
@@ -392,7 +426,7 @@ def gp_states(prob, Q_lib, dt, alpha=0.0):
         sL = fd["stateL"]
         lo = [slice(None)] * 3
         lo[d] = slice(0, n[d])
-        hi_idx = (np.arange(n[d]) + 1) % n[d] if prob.bc[d] == "periodic" else np.arange(n[d]) + 1
+        hi_idx = (np.arange(n[d]) + 1) % n[d] if prob.periodic(d) else np.arange(n[d]) + 1
         minus = sR[(Ellipsis,) + tuple(lo)]
         plus = np.take(sL, hi_idx, axis=3 + d)
         for face, arr in ((2 * d, minus), (2 * d + 1, plus)):
@@ -412,7 +446,7 @@ def fallback_mask(prob, Q_lib, dt, alpha=0.0):
         fd = r["faces"][d]
         lo = [slice(None)] * 3
         lo[d] = slice(0, n[d])
-        hi_idx = (np.arange(n[d]) + 1) % n[d] if prob.bc[d] == "periodic" else np.arange(n[d]) + 1
+        hi_idx = (np.arange(n[d]) + 1) % n[d] if prob.periodic(d) else np.arange(n[d]) + 1
         minus = fd["trigR"][(slice(None),) + tuple(lo)]          # (4gp, i, j, k)
         plus = np.take(fd["trigL"], hi_idx, axis=1 + d)
         for face, arr in ((2 * d, minus), (2 * d + 1, plus)):
