@@ -51,7 +51,19 @@ typedef enum {
   HGKS_EUNSUPPORTED = 6   /* valid request this build does not provide      */
 } hgks_status;
 
-typedef enum { HGKS_BC_PERIODIC = 0, HGKS_BC_OUTFLOW = 1 } hgks_bc;
+/* Boundary conditions of Sec. 4.  OUTFLOW is the non-reflecting condition:
+ * zero-gradient ghost cells (each ghost a copy of the nearest interior cell,
+ * axis by axis).  SYMMETRIC is the symmetric condition of the octant
+ * problems: ghost cell g outside the boundary face is the mirror image of
+ * interior cell g inside, with the momentum component normal to that face
+ * reversed.  A periodic axis is periodic at both ends.  SAME is only for
+ * bc_hi: the high end takes the low end's condition. */
+typedef enum {
+  HGKS_BC_SAME = -1,
+  HGKS_BC_PERIODIC = 0,
+  HGKS_BC_OUTFLOW = 1,
+  HGKS_BC_SYMMETRIC = 2
+} hgks_bc;
 
 typedef enum {
   HGKS_FP64 = 0,  /* every step of the stage in double                        */
@@ -63,7 +75,8 @@ typedef enum {
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 2, with
                              (nx+2)(ny+2)(nz+2) < 2^32                        */
-  int32_t bc[3];          /* hgks_bc per axis (x, y, z)                       */
+  int32_t bc[3];          /* hgks_bc per axis (x, y, z): the low end, and the
+                             high end too unless bc_hi says otherwise         */
   double gamma;           /* ratio of specific heats, 1 < gamma < 5/3 (1.4)   */
   double mu;              /* dynamic viscosity; 0 selects the inviscid
                              collision time (Sec. 4)                          */
@@ -79,10 +92,13 @@ typedef struct {
                              hgks_set_vertices (all axes periodic); 0: uniform
                              box grid from hgks_set_uniform_grid              */
   void* stream;           /* hipStream_t, NULL for the default stream         */
+  int32_t bc_hi[3];       /* hgks_bc at the high end of each axis, or
+                             HGKS_BC_SAME (the default): as bc[d]             */
 } hgks_config;
 
 /* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,
- * tau_eps 0.01, tau_C 1, FP64, periodic, inviscid) for an n^3 grid. */
+ * tau_eps 0.01, tau_C 1, FP64, periodic, inviscid; bc_hi = HGKS_BC_SAME)
+ * for an nx x ny x nz grid. */
 hgks_status hgks_default_config(hgks_config* cfg, int32_t nx, int32_t ny, int32_t nz);
 
 /* Device bytes of the workspace a context with this configuration needs. */

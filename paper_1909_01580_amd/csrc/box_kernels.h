@@ -33,6 +33,7 @@ struct BoxGrid {
   int g[3];     // ghost layer of the reconstruction box
   int nr[3];    // reconstruction box
   int per[3];   // periodic axis
+  int sym[3][2];  // symmetric (mirror) low / high end of a non-periodic axis; else outflow
   int nf[3][3]; // face grid per direction
   double inv_dx[3];
   double wface[3];  // Gauss weight 1/4 times the face area, faces normal to d
@@ -175,11 +176,29 @@ constexpr size_t coef_elems(size_t NR, size_t elem_bytes) {
   return 50 * ((NR + cb - 1) / cb) * cb;
 }
 
-__device__ __forceinline__ int bc_index(const BoxGrid& G, int ax, int i) {
-  // Real index after the boundary rule: periodic wrap or zero-gradient clamp.
+// Real index of cell i (within one layer of the grid) along axis ax after
+// the boundary rule -- periodic wrap, zero-gradient clamp (outflow) or
+// mirror (symmetric) -- and the sign (+1 or -1) of the momentum component
+// along ax in that cell's value: -1 for a mirror image.
+__device__ __forceinline__ int bc_index(const BoxGrid& G, int ax, int i, double& sign) {
   const int n = G.n[ax];
+  sign = 1.0;
   if (G.per[ax]) return i < 0 ? i + n : (i >= n ? i - n : i);
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+  if (i < 0) {
+    if (G.sym[ax][0]) {
+      sign = -1.0;
+      return -1 - i;
+    }
+    return 0;
+  }
+  if (i >= n) {
+    if (G.sym[ax][1]) {
+      sign = -1.0;
+      return 2 * n - 1 - i;
+    }
+    return n - 1;
+  }
+  return i;
 }
 
 __device__ __forceinline__ int rec_index(const BoxGrid& G, int ax, int i) {
@@ -199,18 +218,24 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
   split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
   const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
   int ix[3], iy[3], iz[3];
+  double sx[3], sy[3], sz[3];  // momentum signs of mirror images
 #pragma unroll
   for (int o = 0; o < 3; ++o) {
-    ix[o] = bc_index(G, 0, i + o - 1);
-    iy[o] = bc_index(G, 1, j + o - 1);
-    iz[o] = bc_index(G, 2, k + o - 1);
+    ix[o] = bc_index(G, 0, i + o - 1, sx[o]);
+    iy[o] = bc_index(G, 1, j + o - 1, sy[o]);
+    iz[o] = bc_index(G, 2, k + o - 1, sz[o]);
   }
   const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
   TC qc[5], bnd[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const double* qv = q + v * N;
-    const double c = qv[iz[1] * nxy + iy[1] * nx + ix[1]];
+    // sign of variable v in the cell at offset o: the momentum component
+    // along an axis flips in a mirror image across that axis
+    auto sg = [&](int ox, int oy, int oz) -> double {
+      return v == 1 ? sx[ox + 1] : (v == 2 ? sy[oy + 1] : (v == 3 ? sz[oz + 1] : 1.0));
+    };
+    const double c = sg(0, 0, 0) * qv[iz[1] * nxy + iy[1] * nx + ix[1]];
     TC d[27];
 #pragma unroll
     for (int oz = -1; oz <= 1; ++oz)
@@ -222,7 +247,8 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
           if (nz == 0 || nz == 3) {
             d[sidx(ox, oy, oz)] = TC(0);
           } else {
-            d[sidx(ox, oy, oz)] = TC(qv[iz[oz + 1] * nxy + iy[oy + 1] * nx + ix[ox + 1]] - c);
+            d[sidx(ox, oy, oz)] =
+                TC(sg(ox, oy, oz) * qv[iz[oz + 1] * nxy + iy[oy + 1] * nx + ix[ox + 1]] - c);
           }
         }
     BoxRecon<TC> r;
@@ -273,14 +299,15 @@ __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__
 template <typename TC>
 __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ q, uint32_t* __restrict__ mask,
                                                      const BoxGrid& G, TC gm1, size_t idx) {
-  const int ri = (int)(idx % G.nr[0]);
-  const int rj = (int)((idx / G.nr[0]) % G.nr[1]);
-  const int rk = (int)(idx / ((size_t)G.nr[0] * G.nr[1]));
+  int ri, rj, rk;
+  split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
   const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
   const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
   auto at = [&](int v, int ox, int oy, int oz) -> double {
-    const int a = bc_index(G, 0, i + ox), bb = bc_index(G, 1, j + oy), c = bc_index(G, 2, k + oz);
-    return q[v * N + c * nxy + bb * nx + a];
+    double s[3];
+    const int a = bc_index(G, 0, i + ox, s[0]), bb = bc_index(G, 1, j + oy, s[1]), c = bc_index(G, 2, k + oz, s[2]);
+    const double val = q[v * N + c * nxy + bb * nx + a];
+    return (v >= 1 && v <= 3) ? s[v - 1] * val : val;
   };
   uint32_t bits = 0;
   for (int m = 0; m < 25; ++m) {

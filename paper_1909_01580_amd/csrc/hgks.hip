@@ -42,16 +42,23 @@ struct Layout {
 };
 
 struct Dims {
-  int n[3], g[3], nr[3], per[3], nf[3][3];
+  int n[3], g[3], nr[3], per[3], sym[3][2], nf[3][3];
   size_t N, NR, NF[3];
   size_t nred;  // doubles of reduction scratch
 };
 
+// Boundary at the high end of axis d (bc_hi may say "the same as the low end").
+int bc_high(const hgks_config* c, int d) { return c->bc_hi[d] == HGKS_BC_SAME ? c->bc[d] : c->bc_hi[d]; }
+
+bool valid_bc(int b) { return b == HGKS_BC_PERIODIC || b == HGKS_BC_OUTFLOW || b == HGKS_BC_SYMMETRIC; }
+
 bool valid_config(const hgks_config* c) {
   if (!c) return false;
   if (c->nx < 2 || c->ny < 2 || c->nz < 2) return false;
-  for (int d = 0; d < 3; ++d)
-    if (c->bc[d] != HGKS_BC_PERIODIC && c->bc[d] != HGKS_BC_OUTFLOW) return false;
+  for (int d = 0; d < 3; ++d) {
+    if (!valid_bc(c->bc[d]) || !valid_bc(bc_high(c, d))) return false;
+    if ((c->bc[d] == HGKS_BC_PERIODIC) != (bc_high(c, d) == HGKS_BC_PERIODIC)) return false;
+  }
   if (!(c->gamma > 1.0 && c->gamma < 5.0 / 3.0)) return false;
   if (!(c->mu >= 0.0) || !(c->weno_Gamma > 0.0 && c->weno_Gamma < 1.0 / 24.0)) return false;
   if (!(c->weno_eps > 0.0) || !(c->tau_eps >= 0.0) || !(c->tau_C >= 0.0)) return false;
@@ -73,6 +80,8 @@ Dims make_dims(const hgks_config* c) {
   for (int d = 0; d < 3; ++d) {
     D.n[d] = n[d];
     D.per[d] = c->bc[d] == HGKS_BC_PERIODIC;
+    D.sym[d][0] = c->bc[d] == HGKS_BC_SYMMETRIC;
+    D.sym[d][1] = bc_high(c, d) == HGKS_BC_SYMMETRIC;
     D.g[d] = D.per[d] ? 0 : 1;
     D.nr[d] = n[d] + 2 * D.g[d];
     D.N *= (size_t)n[d];
@@ -409,6 +418,7 @@ hgks_status hgks_default_config(hgks_config* cfg, int32_t nx, int32_t ny, int32_
   cfg->tau_eps = 0.01;
   cfg->tau_C = 1.0;
   cfg->precision = HGKS_FP64;
+  for (int d = 0; d < 3; ++d) cfg->bc_hi[d] = HGKS_BC_SAME;
   return HGKS_OK;
 }
 
@@ -441,6 +451,8 @@ hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t byte
     c->G.g[d] = c->D.g[d];
     c->G.nr[d] = c->D.nr[d];
     c->G.per[d] = c->D.per[d];
+    c->G.sym[d][0] = c->D.sym[d][0];
+    c->G.sym[d][1] = c->D.sym[d][1];
     for (int e = 0; e < 3; ++e) c->G.nf[d][e] = c->D.nf[d][e];
   }
   set_index_split(c->G);

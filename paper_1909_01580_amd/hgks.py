@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgks.so")
 
 HGKS_OK, HGKS_EINVAL, HGKS_ENOMEM, HGKS_EDEVICE, HGKS_ESTATE, HGKS_ENONPHYS, HGKS_EUNSUPPORTED = range(7)
-BC = {"periodic": 0, "outflow": 1}
+BC = {"same": -1, "periodic": 0, "outflow": 1, "symmetric": 2}
 PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTS = [
@@ -44,6 +44,7 @@ class hgks_config(ctypes.Structure):
         ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double),
         ("precision", ctypes.c_int32), ("moving", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("bc_hi", ctypes.c_int32 * 3),
     ]
 
 
@@ -219,7 +220,10 @@ def hgks_profile_end(h):
 
 # ------------------------------------------------------------ wrapper
 class Context:
-    """One HGKS context with its workspace held as a torch tensor."""
+    """One HGKS context with its workspace held as a torch tensor.
+
+    ``bc`` gives per axis one of 'periodic', 'outflow', 'symmetric', or a
+    pair (low end, high end) of the last two."""
 
     def __init__(self, n, bc=("periodic",) * 3, gamma=1.4, mu=0.0, weno_Gamma=0.0025,
                  weno_eps=1e-8, tau_eps=0.01, tau_C=1.0, precision="fp64", moving=False,
@@ -228,7 +232,10 @@ class Context:
         self.device = torch.device(device)
         cfg = hgks_default_config(*self.n)
         for d in range(3):
-            cfg.bc[d] = BC[bc[d]]
+            # one condition for the axis, or (low end, high end)
+            lo, hi = (bc[d], "same") if isinstance(bc[d], str) else bc[d]
+            cfg.bc[d] = BC[lo]
+            cfg.bc_hi[d] = BC[hi]
         cfg.gamma, cfg.mu = gamma, mu
         cfg.weno_Gamma, cfg.weno_eps = weno_Gamma, weno_eps
         cfg.tau_eps, cfg.tau_C = tau_eps, tau_C

@@ -60,6 +60,27 @@ def test_invalid_configurations_rejected(lib, field, value):
     assert e.value.status == hgks.HGKS_EINVAL
 
 
+def test_boundary_ends(lib):
+    """bc_hi defaults to "as the low end"; symmetric and mixed ends are
+    accepted; a periodic end needs a periodic partner; unknown codes fail."""
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(8, 8, 8)
+    assert list(cfg.bc_hi) == [hgks.BC["same"]] * 3
+    cfg.bc[0] = hgks.BC["symmetric"]
+    cfg.bc_hi[0] = hgks.BC["outflow"]
+    cfg.bc[1] = hgks.BC["symmetric"]
+    assert hgks.hgks_workspace_size(cfg) > 0
+    for lo, hi in (("periodic", "outflow"), ("symmetric", "periodic")):
+        bad = hgks.hgks_default_config(8, 8, 8)
+        bad.bc[2], bad.bc_hi[2] = hgks.BC[lo], hgks.BC[hi]
+        with pytest.raises(hgks.HGKSError):
+            hgks.hgks_workspace_size(bad)
+    bad = hgks.hgks_default_config(8, 8, 8)
+    bad.bc_hi[1] = 5
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_workspace_size(bad)
+
+
 def test_moving_requires_periodic(lib):
     from paper_1909_01580_amd import hgks
     cfg = hgks.hgks_default_config(8, 8, 8)
