@@ -18,7 +18,7 @@ cells and face Gauss points:
 * ``gks``       BGK gas-kinetic flux at one Gauss point, generic moment
                 algebra and 5x5 solves (Sec. 3, Eqs. (7)-(8), (13)-(16)).
 * ``scheme``    finite-volume operator, two-stage fourth-order stepping,
-                moving-mesh update, time step and totals
+                moving-mesh update, time step, step rejection and totals
                 (Sec. 3, Eq. (9) and Remark 2).
 
 Every function is pinned by CPU tests against what the paper or the
@@ -33,7 +33,11 @@ the oracle and the GPU agree on them by construction only:
   consequences (free stream to round-off, volume equal to the geometric
   volume) are pinned;
 * the smooth-flow collision time tau_eps * dt of the inviscid tau (Sec. 4),
-  whose printed value 0.01 matches only the coarsest row of Table 1.
+  whose printed value 0.01 matches only the coarsest row of Table 1;
+* the step-rejection rule ``checked_step`` (halve dt while the step gives a
+  non-physical state): a control rule the paper does not state, needed for
+  the singular start of its Sedov problem.  Pinned only to its own
+  definition (minimal halving, result equal to a plain step).
 
 Array convention inside the oracle: spatial axes are ordered (i, j, k) =
 (x, y, z).  The public helpers in ``scheme`` accept and return states in the
@@ -42,5 +46,5 @@ library layout ``[5][nz][ny][nx]`` and transpose at the edge.
 
 from .scheme import (  # noqa: F401
     Params, Problem, uniform_problem, vertex_problem, residual, step,
-    s2o4, max_dt, totals, gp_states, face_fluxes,
+    s2o4, max_dt, totals, gp_states, face_fluxes, physical, checked_step,
 )

@@ -374,6 +374,38 @@ def step(prob, Q_lib, dt, n_stages=2, return_volume=False):
     return Qn
 
 
+def physical(Q_lib, gamma):
+    """True when every cell has rho > 0 and p > 0 (NaN counts as not)."""
+    Q = np.asarray(Q_lib, float)
+    with np.errstate(all="ignore"):
+        p = (gamma - 1.0) * (Q[4] - 0.5 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2) / Q[0])
+        return bool(np.all(Q[0] > 0.0) and np.all(p > 0.0))
+
+
+def checked_step(prob, Q_lib, dt, n_stages=2, max_halvings=8):
+    """Step-rejection rule around ``step`` on a static grid: the step is
+    taken with dt / 2^k for the smallest k <= max_halvings whose result is
+    physical.  Returns (state, dt taken), or (None, None) when even
+    dt / 2^max_halvings fails.
+
+    Not part of the method: the paper prints only the CFL number, and for
+    the singular start of the Sedov problem (Sec. 4) a small CFL of 0.01.
+    At that CFL the two-stage step still drives the pressure of the cells
+    two faces away from the energy cell negative in the first step, through the
+    dt^2/3 dL(Q*) term of the second stage (the flux into those cells is
+    switched on only at the intermediate state, so the first stage gives it
+    no weight); halving the step removes it, since that term scales as
+    dt^2 while the cells' energy does not."""
+    assert not prob.moving
+    for _ in range(max_halvings + 1):
+        with np.errstate(all="ignore"):
+            Qn = step(prob, Q_lib, dt, n_stages)
+        if physical(Qn, prob.params.gamma):
+            return Qn, dt
+        dt = 0.5 * dt
+    return None, None
+
+
 def stage_volumes(prob, alpha=0.0):
     vp = prob.padded_vertices(alpha)
     xq, wj = geo.cell_quadrature(vp)

@@ -101,6 +101,31 @@ def explosion_state(n, radius=0.4, centre=(0.5, 0.5, 0.5), gamma=GAMMA):
     return np.ascontiguousarray(conservative(rho, zero, zero, zero, p, gamma))
 
 
+def spherical_sod_state(n, gamma=GAMMA):
+    """Spherically symmetric Sod problem in the octant [0,1]^3 (symmetric
+    planes x = y = z = 0, outflow at 1): rho = 1, p = 1 for r < 0.5,
+    rho = 0.125, p = 0.1 beyond, at rest; sampled at cell centres."""
+    return explosion_state(n, radius=0.5, centre=(0.0, 0.0, 0.0), gamma=gamma)
+
+
+SEDOV_ENERGY = 0.106384  # energy released in the octant
+
+
+def sedov_state(n, length=1.2, energy=SEDOV_ENERGY, p_background=1e-6, gamma=GAMMA):
+    """Sedov blast in the octant [0, length]^3 (symmetric planes x = y = z =
+    0, outflow at `length`): rho = 1 and p = 1e-6 everywhere except the cell
+    at the origin, whose pressure (gamma - 1) energy / V puts the released
+    energy into that one cell; at rest."""
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    shape = n[::-1]
+    rho = np.ones(shape)
+    p = np.full(shape, p_background)
+    vol = np.prod([length / n[d] for d in range(3)])
+    p[0, 0, 0] = (gamma - 1.0) * energy / vol
+    zero = np.zeros(shape)
+    return np.ascontiguousarray(conservative(rho, zero, zero, zero, p, gamma))
+
+
 # ------------------------------------------------------------ deformed grids
 def sine_mesh_vertices(n, t, amp=0.1, omega=np.pi, length=2.0, static=False):
     """Vertices x = xi + amp sin(pi xi) sin(pi eta) sin(pi zeta) s(t) (all
