@@ -142,6 +142,20 @@ hgks_status hgks_max_dt(hgks_ctx ctx, double cfl, double* dt_host);
  * Asynchronous. */
 hgks_status hgks_step(hgks_ctx ctx, double dt, int32_t n_stages);
 
+/* hgks_step with step rejection, for static grids: the step is taken with
+ * dt / 2^k for the smallest k <= max_halvings (0..60) after which every
+ * cell has positive density and pressure; *dt_taken_host receives that
+ * step.  The paper prints only the CFL number, and a small one (0.01) for
+ * the singular start of its Sedov problem (Sec. 4); at that CFL the
+ * two-stage step can still leave a negative pressure next to the energy
+ * cell, which a shorter step removes.  When dt / 2^max_halvings also
+ * fails the state is left as it was, *dt_taken_host = 0 and the call
+ * returns HGKS_ENONPHYS.  Keeps a copy of the state in the workspace;
+ * synchronises the stream once per attempt.  HGKS_EUNSUPPORTED on a
+ * moving mesh. */
+hgks_status hgks_step_checked(hgks_ctx ctx, double dt, int32_t n_stages, int32_t max_halvings,
+                              double* dt_taken_host);
+
 /* out[v] = sum over cells of |Omega| Q_v (deterministic order, double).
  * Synchronises the stream. */
 hgks_status hgks_totals(hgks_ctx ctx, double out_host[5]);

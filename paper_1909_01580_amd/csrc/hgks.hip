@@ -38,7 +38,7 @@ unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 unsigned pad8(unsigned nb) { return (nb + 7u) & ~7u; }
 
 struct Layout {
-  size_t q, qs, acc, coef, mask, face[3], red, geo, verts, vnext, vol, vacc, total;
+  size_t q, qs, acc, back, coef, mask, face[3], red, geo, verts, vnext, vol, vacc, total;
 };
 
 struct Dims {
@@ -108,6 +108,8 @@ Layout make_layout(const hgks_config* c, const Dims& D) {
   L.q = take(5 * D.N * sizeof(double));
   L.qs = take(5 * D.N * sizeof(double));
   L.acc = take(5 * D.N * sizeof(double));
+  // copy of the state for hgks_step_checked (static grids only)
+  L.back = c->moving ? 0 : take(5 * D.N * sizeof(double));
   L.coef = take(coef_elems(D.NR, tc) * tc);
   L.mask = take(D.NR * sizeof(uint32_t));
   const size_t nface = c->moving ? 12 : 10;
@@ -149,6 +151,7 @@ struct hgks_ctx_s {
   double* q() { return (double*)(ws + L.q); }
   double* qs() { return (double*)(ws + L.qs); }
   double* acc() { return (double*)(ws + L.acc); }
+  double* back() { return (double*)(ws + L.back); }
   void* coef() { return ws + L.coef; }
   uint32_t* mask() { return (uint32_t*)(ws + L.mask); }
   void* face(int d) { return ws + L.face[d]; }
@@ -552,6 +555,34 @@ hgks_status hgks_step(hgks_ctx c, double dt, int32_t n_stages) {
   else
     s = c->mixed() ? box_step<float>(c, dt, n_stages) : box_step<double>(c, dt, n_stages);
   return s;
+}
+
+hgks_status hgks_step_checked(hgks_ctx c, double dt, int32_t n_stages, int32_t max_halvings, double* dt_taken) {
+  if (hgks_status s = ready(c)) return s;
+  if (c->cfg.moving) return fail(HGKS_EUNSUPPORTED, "step_checked needs a static grid");
+  if (!dt_taken || max_halvings < 0 || max_halvings > 60) return fail(HGKS_EINVAL, "bad max_halvings or output");
+  *dt_taken = 0.0;
+  const size_t bytes = 5 * c->D.N * sizeof(double);
+  if (hgks_status s = check_hip(c, hipMemcpyAsync(c->back(), c->q(), bytes, hipMemcpyDeviceToDevice, c->stream),
+                                "save state"))
+    return s;
+  for (int k = 0;; ++k) {
+    if (hgks_status s = hgks_step(c, dt, n_stages)) return s;
+    int64_t bad = 0, fb = 0;
+    if (hgks_status s = hgks_check(c, &bad, &fb)) return s;
+    if (bad == 0) {
+      *dt_taken = dt;
+      return HGKS_OK;
+    }
+    if (hgks_status s = check_hip(c, hipMemcpyAsync(c->q(), c->back(), bytes, hipMemcpyDeviceToDevice, c->stream),
+                                  "restore state"))
+      return s;
+    if (k == max_halvings) {
+      if (hgks_status s = check_hip(c, hipStreamSynchronize(c->stream), "restore state")) return s;
+      return fail(HGKS_ENONPHYS, "non-physical state after %d halvings of the step", k);
+    }
+    dt *= 0.5;
+  }
 }
 
 hgks_status hgks_max_dt(hgks_ctx c, double cfl, double* dt_host) {

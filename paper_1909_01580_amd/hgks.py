@@ -24,7 +24,7 @@ PREC = {"fp64": 0, "mixed": 1}
 EXPORTS = [
     "hgks_default_config", "hgks_workspace_size", "hgks_create", "hgks_destroy",
     "hgks_set_uniform_grid", "hgks_set_vertices", "hgks_set_next_vertices",
-    "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_totals",
+    "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_step_checked", "hgks_totals",
     "hgks_check", "hgks_debug_gp_states", "hgks_debug_face_flux", "hgks_sync",
     "hgks_last_error", "hgks_profile_begin", "hgks_profile_end",
     "hgks_batch_workspace_size", "hgks_batch_create", "hgks_batch_destroy",
@@ -79,6 +79,7 @@ def load():
         "hgks_get_state": [P, P],
         "hgks_max_dt": [P, D, DP],
         "hgks_step": [P, D, I32],
+        "hgks_step_checked": [P, D, I32, I32, DP],
         "hgks_totals": [P, DP],
         "hgks_check": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "hgks_debug_gp_states": [P, D, P],
@@ -180,6 +181,12 @@ def hgks_max_dt(h, cfl):
 
 def hgks_step(h, dt, n_stages=2):
     _check(load().hgks_step(h, dt, n_stages))
+
+
+def hgks_step_checked(h, dt, n_stages=2, max_halvings=8):
+    taken = ctypes.c_double(0.0)
+    _check(load().hgks_step_checked(h, dt, n_stages, max_halvings, ctypes.byref(taken)))
+    return taken.value
 
 
 def hgks_totals(h):
@@ -286,6 +293,9 @@ class Context:
 
     def step(self, dt, n_stages=2):
         hgks_step(self.h, dt, n_stages)
+
+    def step_checked(self, dt, n_stages=2, max_halvings=8):
+        return hgks_step_checked(self.h, dt, n_stages, max_halvings)
 
     def totals(self):
         return hgks_totals(self.h)

@@ -81,6 +81,15 @@ def test_boundary_ends(lib):
         hgks.hgks_workspace_size(bad)
 
 
+def test_step_checked_workspace(lib):
+    """Static grids keep one more copy of the state for the step rejection
+    of hgks_step_checked; moving meshes do not offer it."""
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(16, 16, 16)
+    n_static = hgks.hgks_workspace_size(cfg)
+    assert n_static >= (20 + 50 + 30) * 8 * 16 ** 3
+
+
 def test_moving_requires_periodic(lib):
     from paper_1909_01580_amd import hgks
     cfg = hgks.hgks_default_config(8, 8, 8)
