@@ -203,6 +203,38 @@ def run_moving(n, steps, warmup, precision, v0, q0, cfl=0.35):
     return {"ms": ms, "prof": prof, "rho": ctx.get_state()[0].cpu().numpy(), "drift": drift}
 
 
+def run_octant(n, steps, warmup, precision):
+    """Sedov blast in the octant [0,1.2]^3 (Sec. 4): symmetric planes at
+    x, y, z = 0, outflow at 1.2, the released energy in the corner cell,
+    CFL 0.01 (the singular start), steps taken through the step-rejection
+    entry point, which checks every step and halves a rejected one."""
+    import torch
+    from paper_1909_01580_amd import hgks
+    from paper_1909_01580_amd import workloads as wl
+
+    ctx = hgks.Context((n, n, n), bc=(("symmetric", "outflow"),) * 3, precision=precision)
+    ctx.set_uniform_grid((0.0, 0.0, 0.0), (1.2, 1.2, 1.2))
+    ctx.set_state(torch.tensor(wl.sedov_state(n), device="cuda:0"))
+    tot0 = np.array(ctx.totals())
+    halved = 0
+    for _ in range(warmup):
+        dt = ctx.max_dt(0.01)
+        halved += ctx.step_checked(dt) < dt
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.profile_begin()
+    ev0.record()
+    for _ in range(steps):
+        dt = ctx.max_dt(0.01)
+        halved += ctx.step_checked(dt) < dt
+    ev1.record()
+    torch.cuda.synchronize()
+    prof = ctx.profile_end()
+    drift = np.abs(np.array(ctx.totals()) - tot0)[[0, 4]] / np.abs(tot0)[[0, 4]]
+    return {"ms": ev0.elapsed_time(ev1), "prof": prof, "halved": int(halved), "drift": float(drift.max()),
+            "nonphysical": ctx.check()[0]}
+
+
 def sampled_oracle_error(q0, first, n):
     """Error of the first GPU FP64 step against the oracle at sampled cells:
     the oracle advances a 13^3 periodic patch around each sampled cell (the
@@ -265,6 +297,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--no-moving", action="store_true")
     ap.add_argument("--moving-steps", type=int, default=10)
+    ap.add_argument("--no-octant", action="store_true")
+    ap.add_argument("--octant-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also copy this many MiB once (reference for HBM counters)")
     args = ap.parse_args()
@@ -367,6 +401,20 @@ def main():
             "mixed_phases_ms_per_step": {k: v[0] / args.moving_steps for k, v in mv["mixed"]["prof"].items()},
             "l1_rho_rel_error_mixed_vs_fp64": float(np.abs(mv["mixed"]["rho"] - r64).sum() / np.abs(r64).sum()),
             "conservation_rel_drift": max(mv["fp64"]["drift"], mv["mixed"]["drift"]),
+        }
+    if not args.no_octant:
+        oc = {p: run_octant(args.n, args.octant_steps, 2, p) for p in ("fp64", "mixed")}
+        out["octant"] = {
+            "workload": f"Sedov blast {n}^3 in the octant [0,1.2]^3, symmetric planes x,y,z = 0, outflow at 1.2, "
+                        "energy 0.106384 in the corner cell, CFL 0.01, every step checked for positivity",
+            "value": cells * 2 * args.octant_steps / (oc["fp64"]["ms"] / 1e3),
+            "unit": "cell-stage updates/s", "dtype": "f64",
+            "ms_per_step": oc["fp64"]["ms"] / args.octant_steps,
+            "phases_ms_per_step": {k: v[0] / args.octant_steps for k, v in oc["fp64"]["prof"].items()},
+            "mixed_value": cells * 2 * args.octant_steps / (oc["mixed"]["ms"] / 1e3),
+            "steps_halved": {p: oc[p]["halved"] for p in oc},
+            "nonphysical_cells": {p: oc[p]["nonphysical"] for p in oc},
+            "mass_energy_rel_drift": max(oc["fp64"]["drift"], oc["mixed"]["drift"]),
         }
     if head.get("first") is not None and not args.no_oracle_check:
         err, ns = sampled_oracle_error(head["q0"], head["first"], n)
