@@ -17,6 +17,9 @@ cells and face Gauss points:
                 positivity fallback (Sec. 2, Eqs. (1)-(5); Sec. 4 limiter).
 * ``gks``       BGK gas-kinetic flux at one Gauss point, generic moment
                 algebra and 5x5 solves (Sec. 3, Eqs. (7)-(8), (13)-(16)).
+* ``characteristic``  reconstruction in characteristic variables: Euler
+                eigenvectors along the face normal, projected polynomials,
+                indicators and weights per characteristic field (Sec. 4).
 * ``scheme``    finite-volume operator, two-stage fourth-order stepping,
                 moving-mesh update, time step, step rejection and totals
                 (Sec. 3, Eq. (9) and Remark 2).

@@ -34,6 +34,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import geometry as geo
+from . import characteristic
 from . import weno
 from .gks import gks_flux
 
@@ -48,6 +49,7 @@ class Params:
     weno_eps: float = 1e-8
     tau_eps: float = 0.01
     tau_C: float = 1.0
+    characteristic: bool = False   # reconstruct in characteristic variables (Sec. 4)
 
 
 BOUNDARIES = ("periodic", "outflow", "symmetric")
@@ -211,11 +213,19 @@ def _faces(prob, rec, vp, vdot, d, dt, chunk=2048):
     for s in range(0, nfaces, chunk):
         sl = slice(s, min(s + chunk, nfaces))
         x = xG[:, :, sl]
+        nx_, ny_, nz_ = geo.local_frame(aG[:, :, sl], xb[:, :, sl])
+        frame = (nx_, ny_, nz_)
+        sels = {side: weno.select(rec, idx[None, :]) for side, idx in (("L", IL[sl]), ("R", IR[sl]))}
+        if P.characteristic:
+            Qbar = 0.5 * (sels["L"]["Q"] + sels["R"]["Q"])
         states = []
-        for side, idx in (("L", IL[sl]), ("R", IR[sl])):
-            sel = weno.select(rec, idx[None, :])
+        for side in ("L", "R"):
+            sel = sels[side]
             vals, grads = weno.eval_polys(sel, x)
-            val, grad = weno.combine(sel, vals, grads)
+            if P.characteristic:
+                val, grad = characteristic.point_states(sel, x, Qbar, frame, P.weno_Gamma, P.weno_eps, P.gamma)
+            else:
+                val, grad = weno.combine(sel, vals, grads)
             trig = weno.positivity_trigger(vals, P.gamma)
             Qc = np.broadcast_to(sel["Q"], val.shape)
             val = np.where(trig[None], Qc, val)
@@ -223,8 +233,6 @@ def _faces(prob, rec, vp, vdot, d, dt, chunk=2048):
             out["state" + side][:, :, :, sl] = np.concatenate([val[None], grad], axis=0)
             out["trig" + side][:, sl] = trig
             states.append((val, grad))
-        nx_, ny_, nz_ = geo.local_frame(aG[:, :, sl], xb[:, :, sl])
-        frame = (nx_, ny_, nz_)
         u_g = None if ug is None else ug[:, :, sl]
 
         loc = []

@@ -200,6 +200,7 @@ def reconstruct(xq, wj, V, c, h, Qp, Gamma, eps):
     return {
         "shape": shp,
         "c": ci.reshape(3, nr), "h": hf, "V": Vi,
+        "xg": X, "wg": wo,
         "avg": avg_i.reshape(9, nr),
         "Q": Qi.reshape(5, nr),
         "a": a, "b": b,
@@ -217,6 +218,8 @@ def select(rec, index):
         out[key] = rec[key][:, flat].reshape(rec[key].shape[:1] + shp)
     for key in ("h", "V"):
         out[key] = rec[key][flat].reshape(shp)
+    out["xg"] = rec["xg"][:, :, flat].reshape((3, 8) + shp)
+    out["wg"] = rec["wg"][:, flat].reshape((8,) + shp)
     out["a"] = np.moveaxis(rec["a"][flat], 0, -1).reshape((9, 5) + shp)
     out["b"] = np.moveaxis(rec["b"][flat], 0, -1).reshape((24, 3, 5) + shp)
     out["wbar"] = rec["wbar"][:, :, flat].reshape((25, 5) + shp)

@@ -1,0 +1,138 @@
+"""Pins of the oracle's characteristic-variable reconstruction (Sec. 4).
+
+* The eigenvectors diagonalise the Euler Jacobian along the normal: checked
+  against a central-difference Jacobian of the Euler flux n.(F, G, H) written
+  from its definition, with eigenvalues u_n - c, u_n (three times), u_n + c.
+* The indicators recomputed from projected coefficients are those of Eq. (4):
+  on unprojected coefficients they reproduce the reconstruction's own.
+* With the weights forced linear (huge epsilon) the characteristic and the
+  component-wise schemes coincide: the polynomials are linear in the data,
+  so projecting and projecting back is the identity.
+* An entropy wave (density varies, velocity and pressure constant) excites
+  only the entropy field, because (1, u, v, w, |u|^2/2) is an eigenvector at
+  every state with that velocity: the characteristic reconstruction keeps
+  velocity and pressure constant at every Gauss point, with gradients
+  proportional to the density gradient, while the component-wise one does
+  not (its weights depend on each variable's scale through epsilon).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import characteristic as ch
+from oracle import geometry as geo
+from oracle import weno
+
+GAMMA = 1.4
+
+
+def cons(rho, V, p):
+    return np.concatenate([rho[None], rho * V, (p / (GAMMA - 1) + 0.5 * rho * (V ** 2).sum(axis=0))[None]])
+
+
+def test_eigensystem_diagonalises_jacobian():
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        rho, p = rng.uniform(0.2, 3.0, 2)
+        V = rng.normal(size=3) * 2
+        Q = np.array([rho, *(rho * V), p / (GAMMA - 1) + 0.5 * rho * V @ V])
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        t1 = np.cross(n, rng.normal(size=3))
+        t1 /= np.linalg.norm(t1)
+        t2 = np.cross(n, t1)
+        R, L, lam = ch.eigensystem(Q, n, t1, t2, GAMMA)
+        J = np.empty((5, 5))
+        h = 1e-6 * max(1.0, np.abs(Q).max())
+        for j in range(5):
+            e = np.zeros(5)
+            e[j] = h
+            J[:, j] = (ch.euler_flux_n(Q + e, n, GAMMA) - ch.euler_flux_n(Q - e, n, GAMMA)) / (2 * h)
+        scale = np.abs(J).max() * np.abs(R).max()
+        assert np.abs(J @ R - R * lam[None]).max() < 1e-6 * scale
+        assert np.abs(L @ R - np.eye(5)).max() < 1e-12
+        un, c = V @ n, np.sqrt(GAMMA * p / rho)
+        np.testing.assert_allclose(lam, [un - c, un, un, un, un + c], rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("deformed", [False, True])
+def test_indicators_reproduce_eq4(deformed):
+    rng = np.random.default_rng(5)
+    n = (5, 4, 4)
+    if deformed:
+        import paper_1909_01580_amd.workloads as wl
+        prob = oracle.vertex_problem(n, wl.sine_mesh_vertices(n, 0.0, amp=0.1, static=True, length=2.0),
+                                     (2.0, 2.0, 2.0))
+    else:
+        prob = oracle.uniform_problem(n, (0, 0, 0), (1.0, 0.8, 0.8))
+    vp = prob.padded_vertices(0.0)
+    xq, wj = geo.cell_quadrature(vp)
+    V, c, h = geo.cell_volume_centroid(xq, wj)
+    Qp = 1.0 + 0.3 * rng.random((5,) + V.shape)
+    rec = weno.reconstruct(xq, wj, V, c, h, Qp, 0.0025, 1e-8)
+    a = np.moveaxis(rec["a"], 0, -1)                  # (9,5,nr)
+    b = np.moveaxis(rec["b"], 0, -1)                  # (24,3,5,nr)
+    beta = ch.indicators(a, b, rec["xg"], rec["wg"], rec["h"], rec["V"])
+    np.testing.assert_allclose(beta, rec["beta"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(ch.nonlinear_weights(beta, 0.0025, 1e-8), rec["wbar"], rtol=1e-12, atol=1e-15)
+
+
+def random_state(rng, n):
+    shp = n[::-1]
+    return cons(1 + 0.4 * rng.random(shp), 0.5 * rng.normal(size=(3,) + shp), 1 + 0.4 * rng.random(shp))
+
+
+def test_linear_weights_commute():
+    rng = np.random.default_rng(9)
+    n = (6, 5, 4)
+    Q = random_state(rng, n)
+    out = {}
+    for charv in (False, True):
+        prob = oracle.uniform_problem(n, (0, 0, 0), (1, 1, 1), bc=("periodic", "outflow", ("symmetric", "outflow")),
+                                      params=oracle.Params(characteristic=charv, weno_eps=1e30))
+        out[charv] = oracle.step(prob, Q, 0.01)
+    assert np.abs(out[True] - out[False]).max() < 1e-13 * np.abs(Q).max()
+    # with the ordinary epsilon the two differ on rough data
+    prob = oracle.uniform_problem(n, (0, 0, 0), (1, 1, 1), bc=("periodic", "outflow", ("symmetric", "outflow")),
+                                  params=oracle.Params(characteristic=True))
+    assert np.abs(oracle.step(prob, Q, 0.01) - out[False]).max() > 1e-4
+
+
+def gp_primitives(gp):
+    """Velocity, pressure and their gradients at Gauss points from the
+    [..., 5, 4] (value, d/dx, d/dy, d/dz) arrays of gp_states."""
+    W = gp[..., 0]
+    rho = W[..., 0]
+    V = W[..., 1:4] / rho[..., None]
+    p = (GAMMA - 1) * (W[..., 4] - 0.5 * (W[..., 1:4] ** 2).sum(axis=-1) / rho)
+    return rho, V, p
+
+
+@pytest.mark.parametrize("charv", [True, False])
+def test_entropy_wave_stays_in_its_field(charv):
+    n = (9, 6, 5)
+    x = (np.arange(n[0]) + 0.5) / n[0]
+    y = (np.arange(n[1]) + 0.5) / n[1]
+    Z, Y, X = np.meshgrid(np.arange(n[2]), y, x, indexing="ij")
+    rho = 1.0 + 0.8 * (X > 0.45) + 0.1 * np.sin(2 * np.pi * Y)
+    u = np.array([0.7, -0.3, 0.2])
+    Q = cons(rho, np.broadcast_to(u[:, None, None, None], (3,) + rho.shape), np.ones_like(rho))
+    prob = oracle.uniform_problem(n, (0, 0, 0), (1, 1, 1),
+                                  params=oracle.Params(characteristic=charv, weno_eps=1e-3))
+    gp = oracle.gp_states(prob, Q, 0.01)             # [nz][ny][nx][24][5][4]
+    r, V, p = gp_primitives(gp)
+    dev_v = np.abs(V - u).max()
+    dev_p = np.abs(p - 1.0).max()
+    if charv:
+        assert dev_v < 1e-13 and dev_p < 1e-13, (dev_v, dev_p)
+        # gradients: d(rho u) = u d(rho), dE = |u|^2/2 d(rho)
+        g = gp[..., 1:]                               # (..., 5, 3)
+        np.testing.assert_allclose(g[..., 1:4, :], u[:, None] * g[..., 0:1, :], atol=1e-12)
+        np.testing.assert_allclose(g[..., 4, :], 0.5 * (u @ u) * g[..., 0, :], atol=1e-12)
+        # the density itself is the component-wise density (same data, same weights)
+        prob_c = oracle.uniform_problem(n, (0, 0, 0), (1, 1, 1), params=oracle.Params(weno_eps=1e-3))
+        rc = oracle.gp_states(prob_c, Q, 0.01)[..., 0, 0]
+        assert np.abs(r - rc).max() < 1e-13
+    else:
+        assert max(dev_v, dev_p) > 1e-6, (dev_v, dev_p)
