@@ -94,6 +94,11 @@ typedef struct {
   void* stream;           /* hipStream_t, NULL for the default stream         */
   int32_t bc_hi[3];       /* hgks_bc at the high end of each axis, or
                              HGKS_BC_SAME (the default): as bc[d]             */
+  int32_t characteristic; /* 1: reconstruct in characteristic variables (Sec.
+                             4): per face, Euler eigenvectors along the normal
+                             at the mean of the two cell averages; box grids
+                             (moving = 0) only, not in batches.  0: the
+                             conservative variables component-wise (default) */
 } hgks_config;
 
 /* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,

@@ -45,6 +45,11 @@ struct BoxGrid {
   // rows along y; reciprocals of n0 band n2, n0 band and n0 (tail height).
   int band, band_full, band_tail;
   double inv_band[3];
+  // Elements between the six per-face coefficient arrays of a cell
+  // (reconstruction in characteristic variables: array 2 d + s holds the
+  // quadratic for the cell's face normal to d on side s); 0 when one
+  // reconstruction serves all faces.
+  size_t fs_stride;
 };
 
 // floor(k / d) for k < 2^32 from inv = (1 + 2^-40) / d: the double product
@@ -466,17 +471,21 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   const bool fbL = (mask[iL] >> (4 * (2 * D + 1) + gpi)) & 1u;
   const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
 
+  // the left cell's quadratic for its high face, the right cell's for its
+  // low face (the same array unless the faces have their own)
+  const TC* coefL = coef + (size_t)(2 * D + 1) * G.fs_stride;
+  const TC* coefR = coef + (size_t)(2 * D) * G.fs_stride;
   FluxAcc<TC> acc;
   acc_zero(acc);
   {
     TC W[5], dW[3][5];
-    eval_box_gp_dir(D, coef, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
+    eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
     side_terms<+1>(W, dW, gp, acc);
   }
   after_left_side(iR, acc);
   {
     TC W[5], dW[3][5];
-    eval_box_gp_dir(D, coef, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
+    eval_box_gp_dir(D, coefR, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
     side_terms<-1>(W, dW, gp, acc);
   }
   TC F[5], dF[5];
@@ -712,7 +721,7 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_box(const TC* __restrict__ 
     xi[(d + 2) % 3] = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
     const bool fb = (mk >> bit) & 1u;
     for (int v = 0; v < 5; ++v) {
-      const TC* cv = coef + coef_cell<TC>(r) + v * 10 * kCB<TC>;
+      const TC* cv = coef + (size_t)f * G.fs_stride + coef_cell<TC>(r) + v * 10 * kCB<TC>;
       TC c[9];
       for (int m = 0; m < 9; ++m) c[m] = cv[(m + 1) * kCB<TC>];
       TC val, g[3];

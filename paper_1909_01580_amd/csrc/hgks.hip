@@ -15,6 +15,7 @@
 #include "box_kernels.h"
 #include "hex_kernels.h"
 #include "batch_kernels.h"
+#include "char_box.h"
 
 using namespace hgks;
 
@@ -64,6 +65,8 @@ bool valid_config(const hgks_config* c) {
   if (!(c->weno_eps > 0.0) || !(c->tau_eps >= 0.0) || !(c->tau_C >= 0.0)) return false;
   if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED) return false;
   if (c->moving != 0 && c->moving != 1) return false;
+  if (c->characteristic != 0 && c->characteristic != 1) return false;
+  if (c->characteristic && c->moving) return false;
   if (c->moving)
     for (int d = 0; d < 3; ++d)
       if (c->bc[d] != HGKS_BC_PERIODIC) return false;
@@ -110,7 +113,8 @@ Layout make_layout(const hgks_config* c, const Dims& D) {
   L.acc = take(5 * D.N * sizeof(double));
   // copy of the state for hgks_step_checked (static grids only)
   L.back = c->moving ? 0 : take(5 * D.N * sizeof(double));
-  L.coef = take(coef_elems(D.NR, tc) * tc);
+  // one coefficient array, plus six per-face arrays in characteristic mode
+  L.coef = take(coef_elems(D.NR, tc) * tc * (c->characteristic ? 7 : 1));
   L.mask = take(D.NR * sizeof(uint32_t));
   const size_t nface = c->moving ? 12 : 10;
   for (int d = 0; d < 3; ++d) L.face[d] = take(nface * D.NF[d] * tc);
@@ -230,6 +234,14 @@ GasParams<T> gas_params(const hgks_config& cfg) {
   return g;
 }
 
+// Coefficients the face flux reads: the cell quadratics, or in characteristic
+// mode the six per-face arrays that follow them.
+template <typename TC>
+TC* face_coef(hgks_ctx c) {
+  TC* coef = (TC*)c->coef();
+  return c->cfg.characteristic ? coef + c->G.fs_stride : coef;
+}
+
 // Reconstruction (with the fallback mask) and face fluxes of the state qin.
 template <typename TC>
 hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
@@ -251,12 +263,19 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
                        TC(c->cfg.gamma - 1.0), D.NR);
     prof_mark(c, HGKS_PHASE_FALLBACK, false);
     if (hgks_status s = launched(c, "positivity")) return s;
+    if (c->cfg.characteristic) {
+      prof_mark(c, HGKS_PHASE_RECON, true);
+      hipLaunchKernelGGL((k_char_recon_box<TC>), dim3(pad8(nb), 6), dim3(kBlock), 0, c->stream, qin,
+                         face_coef<TC>(c), c->G, P, c->cfg.gamma, D.NR, nb);
+      prof_mark(c, HGKS_PHASE_RECON, false);
+      if (hgks_status s = launched(c, "characteristic recon")) return s;
+    }
   }
   unsigned nb[3];
   flux_block_counts(c->G, nb);
   prof_mark(c, HGKS_PHASE_FLUX, true);
-  hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nb[0] + nb[1] + nb[2])), dim3(kBlock), 0, c->stream, coef,
-                     c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), TC(1.0 / dt),
+  hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nb[0] + nb[1] + nb[2])), dim3(kBlock), 0, c->stream,
+                     (const TC*)face_coef<TC>(c), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), TC(1.0 / dt),
                      nb[0], nb[1], nb[2]);
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
@@ -459,6 +478,7 @@ hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t byte
     for (int e = 0; e < 3; ++e) c->G.nf[d][e] = c->D.nf[d][e];
   }
   set_index_split(c->G);
+  if (cfg->characteristic) c->G.fs_stride = coef_elems(c->D.NR, c->mixed() ? sizeof(float) : sizeof(double));
   std::memset(&c->H, 0, sizeof c->H);
   *out = c;
   return HGKS_OK;
@@ -645,10 +665,10 @@ hgks_status hgks_debug_gp_states(hgks_ctx c, double dt, double* out) {
   if (s) return s;
   if (c->mixed())
     hipLaunchKernelGGL((k_debug_gp_box<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
-                       (const float*)c->coef(), c->mask(), c->G, c->D.NR, c->D.N, out);
+                       (const float*)face_coef<float>(c), c->mask(), c->G, c->D.NR, c->D.N, out);
   else
     hipLaunchKernelGGL((k_debug_gp_box<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
-                       (const double*)c->coef(), c->mask(), c->G, c->D.NR, c->D.N, out);
+                       (const double*)face_coef<double>(c), c->mask(), c->G, c->D.NR, c->D.N, out);
   return launched(c, "debug gp");
 }
 
@@ -750,7 +770,7 @@ hgks_status busable(hgks_batch b) {
 }
 
 bool batch_compatible(const hgks_config& a, const hgks_config& c) {
-  if (!valid_config(&c) || c.moving) return false;
+  if (!valid_config(&c) || c.moving || c.characteristic) return false;
   for (int d = 0; d < 3; ++d)
     if (c.bc[d] != HGKS_BC_PERIODIC) return false;
   return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&

@@ -45,6 +45,7 @@ class hgks_config(ctypes.Structure):
         ("precision", ctypes.c_int32), ("moving", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("bc_hi", ctypes.c_int32 * 3),
+        ("characteristic", ctypes.c_int32),
     ]
 
 
@@ -234,7 +235,7 @@ class Context:
 
     def __init__(self, n, bc=("periodic",) * 3, gamma=1.4, mu=0.0, weno_Gamma=0.0025,
                  weno_eps=1e-8, tau_eps=0.01, tau_C=1.0, precision="fp64", moving=False,
-                 device="cuda:0", stream=None):
+                 characteristic=False, device="cuda:0", stream=None):
         self.n = tuple(int(x) for x in n)
         self.device = torch.device(device)
         cfg = hgks_default_config(*self.n)
@@ -248,6 +249,7 @@ class Context:
         cfg.tau_eps, cfg.tau_C = tau_eps, tau_C
         cfg.precision = PREC[precision]
         cfg.moving = 1 if moving else 0
+        cfg.characteristic = 1 if characteristic else 0
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

@@ -7,14 +7,19 @@ from paper_1909_01580_amd import workloads as wl
 GAMMA = 1.4
 
 
-def nerr(a, b, axis_var=0):
+def nerr(a, b, axis_var=0, mom_scale=False):
     """Normalised max-norm error per conservative variable: max |a - b| over
     cells divided by max |b|; momentum components share one denominator
-    (the largest momentum magnitude)."""
+    (the largest momentum magnitude).  With mom_scale the momentum
+    denominator is at least sqrt(max rho * max rho E), the momentum a flow
+    at its sound speed would carry, for states (near) at rest where the
+    momentum is zero up to rounding."""
     a = np.moveaxis(np.asarray(a), axis_var, 0)
     b = np.moveaxis(np.asarray(b), axis_var, 0)
     den = [np.abs(b[v]).max() for v in range(5)]
     mom = max(den[1:4])
+    if mom_scale:
+        mom = max(mom, np.sqrt(den[0] * den[4]))
     out = []
     for v in range(5):
         d = den[v] if v in (0, 4) else mom
