@@ -61,13 +61,13 @@ def measured_traffic(precision):
     return entry["bytes_per_launch"]
 
 
-def run_gpu(n, steps, warmup, precision, cfl=0.35, record_first=False):
+def run_gpu(n, steps, warmup, precision, cfl=0.35, record_first=False, characteristic=False):
     import torch
     from paper_1909_01580_amd import hgks
     from paper_1909_01580_amd import workloads as wl
 
     q0 = torch.tensor(wl.tgv_state(n), device="cuda:0")
-    ctx = hgks.Context((n, n, n), mu=wl.TGV_MU, precision=precision)
+    ctx = hgks.Context((n, n, n), mu=wl.TGV_MU, precision=precision, characteristic=characteristic)
     ctx.set_uniform_grid((-np.pi,) * 3, (2 * np.pi,) * 3)
     ctx.set_state(q0)
     first = None
@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--no-moving", action="store_true")
     ap.add_argument("--moving-steps", type=int, default=10)
     ap.add_argument("--no-octant", action="store_true")
+    ap.add_argument("--no-characteristic", action="store_true")
+    ap.add_argument("--characteristic-steps", type=int, default=5)
     ap.add_argument("--octant-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also copy this many MiB once (reference for HBM counters)")
@@ -415,6 +417,19 @@ def main():
             "steps_halved": {p: oc[p]["halved"] for p in oc},
             "nonphysical_cells": {p: oc[p]["nonphysical"] for p in oc},
             "mass_energy_rel_drift": max(oc["fp64"]["drift"], oc["mixed"]["drift"]),
+        }
+    if not args.no_characteristic:
+        cr = {p: run_gpu(n, args.characteristic_steps, 1, p, characteristic=True) for p in ("fp64", "mixed")}
+        cs = args.characteristic_steps
+        out["characteristic"] = {
+            "workload": f"the same {n}^3 Taylor-Green steps with reconstruction in characteristic variables "
+                        "(six per-face quadratics per cell)",
+            "value": cells * 2 * cs / (cr["fp64"]["ms"] / 1e3), "unit": "cell-stage updates/s", "dtype": "f64",
+            "ms_per_step": cr["fp64"]["ms"] / cs,
+            "phases_ms_per_step": {k: v[0] / cs for k, v in cr["fp64"]["prof"].items()},
+            "mixed_value": cells * 2 * cs / (cr["mixed"]["ms"] / 1e3),
+            "mixed_phases_ms_per_step": {k: v[0] / cs for k, v in cr["mixed"]["prof"].items()},
+            "cost_vs_componentwise_fp64": (cr["fp64"]["ms"] / cs) / ms_step,
         }
     if head.get("first") is not None and not args.no_oracle_check:
         err, ns = sampled_oracle_error(head["q0"], head["first"], n)
