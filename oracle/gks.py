@@ -153,8 +153,26 @@ def time_fit(Ffull, Fhalf, dt):
     return sol[0].reshape(np.shape(Ffull)), sol[1].reshape(np.shape(Ffull))
 
 
+def padd(*Ps):
+    out = {}
+    for P in Ps:
+        for e, cf in P.items():
+            out[e] = out.get(e, 0.0) + cf
+    return out
+
+
+def heat_flux_poly(U, V, W):
+    """(u - U)((u - U)^2 + (v - V)^2 + (w - W)^2 + xi^2) / 2: the normal heat
+    flux carried by a particle, relative to the velocity (U, V, W)."""
+    cx = {(1, 0, 0, 0): 1.0, (0, 0, 0, 0): -U}
+    cy = {(0, 1, 0, 0): 1.0, (0, 0, 0, 0): -V}
+    cz = {(0, 0, 1, 0): 1.0, (0, 0, 0, 0): -W}
+    c2 = padd(pmul(cx, cx), pmul(cy, cy), pmul(cz, cz), {(0, 0, 0, 1): 1.0})
+    return {e: 0.5 * cf for e, cf in pmul(cx, c2).items()}
+
+
 def gks_flux(Wl, dWl, Wr, dWr, dt, gamma, mu=0.0, tau_eps=0.01, tau_C=1.0,
-             return_parts=False):
+             return_parts=False, mu_T0=1.0, mu_exponent=0.0, prandtl=1.0):
     """Gas-kinetic flux F and its time derivative dF at Gauss points.
 
     Wl, Wr:   conservative variables (5, ...) in the local frame.
@@ -190,10 +208,13 @@ def gks_flux(Wl, dWl, Wr, dWr, dt, gamma, mu=0.0, tau_eps=0.01, tau_C=1.0,
     ab = [solve5(M0, dQ0[j] / r0) for j in range(3)]
     Ab = solve5(M0, -sum(psi_moments(pmul(slope_poly(ab[j]), UJ[j]), m0) for j in range(3)))
 
-    # Collision time (Sec. 4).
+    # Collision time (Sec. 4); on the viscous branch mu may follow the power
+    # law mu (T / T0)^omega of the isotropic-turbulence test (Sec. 4), with
+    # T = p_0 / rho_0 the temperature of g_0.
     jump = np.abs((pl - pr) / (pl + pr)) * dt
     if mu > 0.0:
-        tau = mu / p0 + tau_C * jump
+        mu_g = mu * ((p0 / r0) / mu_T0) ** mu_exponent if mu_exponent != 0.0 else mu
+        tau = mu_g / p0 + tau_C * jump
     else:
         tau = tau_eps * dt + tau_C * jump
 
@@ -210,6 +231,29 @@ def gks_flux(Wl, dWl, Wr, dWr, dt, gamma, mu=0.0, tau_eps=0.01, tau_C=1.0,
     def Fhat(delta):
         T1, T2, T3, T4, T5 = time_coefficients(delta, tau)
         return T1 * X1 + T2 * X2 + T3 * X3 + T4 * X4 - T5 * X5 - tau * T4 * X6
+
+    # Prandtl number (Pr = 0.71 for the viscous tests of Sec. 4; the BGK
+    # flux has Pr = 1): the time-integrated energy flux gains (1/Pr - 1) times
+    # the time-integrated heat flux, the moment of the heat-flux polynomial
+    # relative to the velocity of g_0 against the same time-dependent
+    # distribution, term by term.
+    if prandtl != 1.0:
+        hq = heat_flux_poly(U0, V0, W0)
+        Y1 = r0 * expect(hq, m0)
+        Y2 = r0 * sum(expect(pmul(hq, pmul(slope_poly(ab[j]), UJ[j])), m0) for j in range(3))
+        Y3 = r0 * expect(pmul(hq, slope_poly(Ab)), m0)
+        Y4 = rl * expect(hq, mlp) + rr * expect(hq, mrn)
+        Y5 = rl * sum(expect(pmul(hq, pmul(slope_poly(al[j]), UJ[j])), mlp) for j in range(3)) \
+            + rr * sum(expect(pmul(hq, pmul(slope_poly(ar[j]), UJ[j])), mrn) for j in range(3))
+        Y6 = rl * expect(pmul(hq, slope_poly(Al)), mlp) + rr * expect(pmul(hq, slope_poly(Ar)), mrn)
+        Fplain = Fhat
+
+        def Fhat(delta):
+            T1, T2, T3, T4, T5 = time_coefficients(delta, tau)
+            q = T1 * Y1 + T2 * Y2 + T3 * Y3 + T4 * Y4 - T5 * Y5 - tau * T4 * Y6
+            out = Fplain(delta).copy()
+            out[4] = out[4] + (1.0 / prandtl - 1.0) * q
+            return out
 
     # Linear-in-time flux fitted to its integrals over [0, dt] and
     # [0, dt/2] (Eq. (16) and the two equations after it).

@@ -50,6 +50,9 @@ class Params:
     tau_eps: float = 0.01
     tau_C: float = 1.0
     characteristic: bool = False   # reconstruct in characteristic variables (Sec. 4)
+    mu_T0: float = 1.0             # viscosity law mu (T / mu_T0)^mu_exponent (Sec. 4)
+    mu_exponent: float = 0.0       # 0: constant mu
+    prandtl: float = 1.0           # 1: the BGK flux as it stands
 
 
 BOUNDARIES = ("periodic", "outflow", "symmetric")
@@ -244,7 +247,8 @@ def _faces(prob, rec, vp, vdot, d, dt, chunk=2048):
                            for j in range(3)])
             loc.append((W, dW))
         F, dF, Q0 = gks_flux(loc[0][0], loc[0][1], loc[1][0], loc[1][1], dt,
-                             P.gamma, P.mu, P.tau_eps, P.tau_C)
+                             P.gamma, P.mu, P.tau_eps, P.tau_C, mu_T0=P.mu_T0,
+                             mu_exponent=P.mu_exponent, prandtl=P.prandtl)
         F, dF, Q0 = (_unrotate(v, frame) for v in (F, dF, Q0))
         if u_g is not None:
             F, dF, Q0 = (_galilean_back(v, u_g) for v in (F, dF, Q0))

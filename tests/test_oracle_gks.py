@@ -116,6 +116,10 @@ class Quad:
         """int psi * weight * g  -> (5,)."""
         return (self.psi() * weight * self.wt).sum(axis=1)
 
+    def integral(self, weight):
+        """int weight * g (scalar)."""
+        return (weight * self.wt).sum()
+
 
 def prim(Wc):
     rho = Wc[0]
@@ -124,7 +128,7 @@ def prim(Wc):
     return rho, U, V, W, p, rho / (2 * p)
 
 
-def brute_flux(Wl, dWl, Wr, dWr, dt, mu, tau_eps=0.01, tau_C=1.0):
+def brute_flux(Wl, dWl, Wr, dWr, dt, mu, tau_eps=0.01, tau_C=1.0, prandtl=1.0, mu_T0=1.0, mu_exponent=0.0):
     sides = []
     for Wc, dWc, half in ((Wl, dWl, "+"), (Wr, dWr, "-")):
         rho, U, V, W, p, lam = prim(Wc)
@@ -146,7 +150,8 @@ def brute_flux(Wl, dWl, Wr, dWr, dt, mu, tau_eps=0.01, tau_C=1.0):
     Ab = np.linalg.solve(M0, -sum(g0.moments((ab[j] @ psi0) * g0.vel(j)) for j in range(3)))
     pl, pr = sides[0]["p"], sides[1]["p"]
     jump = abs((pl - pr) / (pl + pr)) * dt
-    tau = mu / p0 + tau_C * jump if mu > 0 else tau_eps * dt + tau_C * jump
+    mu_g = mu * ((p0 / r0) / mu_T0) ** mu_exponent
+    tau = mu_g / p0 + tau_C * jump if mu > 0 else tau_eps * dt + tau_C * jump
 
     u0 = g0.u
     m_eq = g0.moments(u0)
@@ -156,6 +161,21 @@ def brute_flux(Wl, dWl, Wr, dWr, dt, mu, tau_eps=0.01, tau_C=1.0):
     m_nea = sum(s["part"].moments(s["part"].u * sum((s["a"][j] @ s["part"].psi()) * s["part"].vel(j)
                                                       for j in range(3))) for s in sides)
     m_neA = sum(s["part"].moments(s["part"].u * (s["A"] @ s["part"].psi())) for s in sides)
+
+    # heat flux carried by each particle, relative to the velocity of g_0
+    def hq(qd):
+        return 0.5 * (qd.u - U0) * ((qd.u - U0) ** 2 + (qd.v - V0) ** 2 + (qd.w - W0) ** 2 + qd.xi2)
+    y = [g0.integral(hq(g0)),
+         g0.integral(hq(g0) * sum((ab[j] @ psi0) * g0.vel(j) for j in range(3))),
+         g0.integral(hq(g0) * (Ab @ psi0)),
+         sum(s["part"].integral(hq(s["part"])) for s in sides),
+         sum(s["part"].integral(hq(s["part"]) * sum((s["a"][j] @ s["part"].psi()) * s["part"].vel(j)
+                                                     for j in range(3))) for s in sides),
+         sum(s["part"].integral(hq(s["part"]) * (s["A"] @ s["part"].psi())) for s in sides)]
+    heat = np.zeros(5)
+    heat[4] = 1.0 / prandtl - 1.0
+    m_eq, m_ab, m_Ab, m_ne, m_nea, m_neA = (m + heat * yk for m, yk in
+                                            zip((m_eq, m_ab, m_Ab, m_ne, m_nea, m_neA), y))
 
     def tint(fn, delta):
         return integrate.quad(fn, 0.0, delta, epsabs=0.0, epsrel=1e-13, limit=200,
@@ -183,7 +203,7 @@ def random_state(rng, rho=1.0, p=1.0, umag=0.6):
     return np.array([r, r * U[0], r * U[1], r * U[2], pp / (GAMMA - 1) + 0.5 * r * U @ U])
 
 
-@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("case", [0, 1, 2, 3])
 def test_flux_against_brute_force(case):
     rng = np.random.default_rng(30 + case)
     Wl, Wr = random_state(rng), random_state(rng)
@@ -192,9 +212,12 @@ def test_flux_against_brute_force(case):
     dWl = 0.5 * rng.standard_normal((3, 5))
     dWr = 0.5 * rng.standard_normal((3, 5))
     dt = 0.01
-    mu = 0.0 if case != 1 else 2e-4
-    F, dF, Q0 = gks.gks_flux(Wl[:, None], dWl[:, :, None], Wr[:, None], dWr[:, :, None], dt, GAMMA, mu)
-    Fb, dFb, Q0b = brute_flux(Wl, dWl, Wr, dWr, dt, mu)
+    mu = 0.0 if case not in (1, 3) else 2e-4
+    # case 3: the viscosity law and Prandtl number of the isotropic-turbulence
+    # test (mu (T/T0)^0.76, Pr 0.71): the heat-flux moments by quadrature
+    extra = dict(prandtl=0.71, mu_T0=0.8, mu_exponent=0.76) if case == 3 else {}
+    F, dF, Q0 = gks.gks_flux(Wl[:, None], dWl[:, :, None], Wr[:, None], dWr[:, :, None], dt, GAMMA, mu, **extra)
+    Fb, dFb, Q0b = brute_flux(Wl, dWl, Wr, dWr, dt, mu, **extra)
     assert np.allclose(Q0[:, 0], Q0b, rtol=1e-11, atol=1e-12)
     assert np.allclose(F[:, 0], Fb, rtol=1e-9, atol=1e-10)
     scale = np.abs(dFb).max()
@@ -243,6 +266,25 @@ def test_shear_stress_navier_stokes_limit():
     mu, dt = 1e-5, 1e-2                   # tau = mu/p << dt
     F, _, _ = gks.gks_flux(Wc[:, None], dW[:, :, None], Wc[:, None], dW[:, :, None], dt, GAMMA, mu)
     assert abs(F[2, 0] - (-mu * s)) < 1e-3 * mu * s
+
+
+@pytest.mark.parametrize("prandtl", [1.0, 0.71])
+@pytest.mark.parametrize("T", [1.0, 2.5])
+def test_heat_flux_navier_stokes_limit(prandtl, T):
+    """At rest with uniform pressure and a linear temperature profile along
+    the normal the energy flux is Fourier's -kappa dT/dx with
+    kappa = c_p mu / Pr, c_p = gamma / (gamma - 1) (unit gas constant), mu from
+    the power law mu0 (T/T0)^0.76 (Chapman-Enskog of the BGK model, with
+    the Prandtl correction)."""
+    s, p, T0, mu0 = 0.2, 1.0, 0.6, 1e-5
+    Wc = np.array([p / T, 0.0, 0.0, 0.0, p / (GAMMA - 1)])
+    dW = np.zeros((3, 5))
+    dW[0, 0] = -p / T ** 2 * s                  # d rho / dn_x with p fixed
+    F, _, _ = gks.gks_flux(Wc[:, None], dW[:, :, None], Wc[:, None], dW[:, :, None], 1e-2, GAMMA, mu0,
+                           prandtl=prandtl, mu_T0=T0, mu_exponent=0.76)
+    kappa = GAMMA / (GAMMA - 1) * mu0 * (T / T0) ** 0.76 / prandtl
+    assert abs(F[4, 0] - (-kappa * s)) < 1e-6 * kappa * s
+    assert np.abs(F[1:4, 0] - np.array([p, 0.0, 0.0])).max() < 1e-12
 
 
 def mirror(Wc, dW):
