@@ -99,10 +99,21 @@ typedef struct {
                              at the mean of the two cell averages; box grids
                              (moving = 0) only, not in batches.  0: the
                              conservative variables component-wise (default) */
+  double mu_T0;           /* viscosity law mu (T / mu_T0)^mu_exponent with T =
+                             p / rho of the interface equilibrium state, as in
+                             the isotropic-turbulence test of Sec. 4 (0.76);  */
+  double mu_exponent;     /* exponent 0 (default): constant mu; mu_T0 > 0     */
+  double prandtl;         /* Prandtl number of the viscous flux: 1 (default)
+                             is the BGK flux as it stands; otherwise (1/Pr - 1)
+                             times the heat flux relative to the interface
+                             velocity is added to the energy flux (Sec. 4
+                             gives Pr = 0.71).  Both on box grids only, not
+                             in batches                                      */
 } hgks_config;
 
 /* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,
- * tau_eps 0.01, tau_C 1, FP64, periodic, inviscid; bc_hi = HGKS_BC_SAME)
+ * tau_eps 0.01, tau_C 1, FP64, periodic, inviscid; bc_hi = HGKS_BC_SAME;
+ * component-wise reconstruction; constant mu, Prandtl number 1)
  * for an nx x ny x nz grid. */
 hgks_status hgks_default_config(hgks_config* cfg, int32_t nx, int32_t ny, int32_t nz);
 

@@ -448,7 +448,8 @@ HGKS_FN void eval_box_gp_dir(int D, const TC* __restrict__ coef, size_t cell, TC
 // a face sum their weighted fluxes with lane shuffles.  Lane l of the
 // 256-lane block lb of direction D takes Gauss point l % 4 of face slot
 // l / 4 (face_of_block).
-template <typename TC>
+// PR: with the Prandtl correction of the energy flux.
+template <typename TC, bool PR = false>
 __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
                                               TC dt, TC idt, unsigned lb, int D) {
@@ -480,16 +481,16 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   {
     TC W[5], dW[3][5];
     eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
-    side_terms<+1>(W, dW, gp, acc);
+    side_terms<+1, PR>(W, dW, gp, acc);
   }
   after_left_side(iR, acc);
   {
     TC W[5], dW[3][5];
     eval_box_gp_dir(D, coefR, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
-    side_terms<-1>(W, dW, gp, acc);
+    side_terms<-1, PR>(W, dW, gp, acc);
   }
   TC F[5], dF[5];
-  finish_flux(acc, gp, dt, idt, F, dF);
+  finish_flux<PR>(acc, gp, dt, idt, F, dF);
   // Face weight of Eq. (11): Gauss weight 1/4 times the area element.
   const TC w = TC(G.wface[D]);
 #pragma unroll
@@ -535,7 +536,7 @@ HGKS_FN void flux_block(unsigned b, const unsigned (&nb)[3], int& D, unsigned& l
 }
 
 // All faces of the three directions in one launch (see flux_block).
-template <typename TC>
+template <typename TC, bool PR = false>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
     const TC* __restrict__ coef, const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy,
     TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, unsigned nb0, unsigned nb1, unsigned nb2) {
@@ -546,7 +547,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
   unsigned lb;
   flux_block(b, nb, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
-  flux_box_face(coef, mask, face, G, gp, dt, idt, lb, D);
+  flux_box_face<TC, PR>(coef, mask, face, G, gp, dt, idt, lb, D);
 }
 
 // ---------------------------------------------------------------- update

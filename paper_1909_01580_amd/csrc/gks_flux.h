@@ -59,6 +59,9 @@ struct GasParams {
   T mu;       // viscosity (0: inviscid collision time)
   T tau_eps, tau_C;
   int viscous;
+  T mu_exp;   // viscosity law mu (T / T0)^mu_exp on the viscous branch (0: constant)
+  T mu_iT0;   // 1 / T0
+  T pr_fix;   // 1 / Pr - 1: weight of the heat flux added to the energy flux
 };
 
 // Gaussian moments of the tangential and internal velocities of one state.
@@ -206,6 +209,10 @@ struct FluxAcc {
   T dQ0[3][5];
   T X4[5], X5[5], X6[5];
   T p[2];
+  // Prandtl correction only: the state moments of the slope and time
+  // derivative terms of the initial distribution (X5, X6 without the
+  // factor u), which the heat flux needs.
+  T S5[5], S6[5];
 };
 
 template <typename T>
@@ -214,6 +221,7 @@ HGKS_FN void acc_zero(FluxAcc<T>& A) {
   for (int i = 0; i < 5; ++i) {
     A.Q0[i] = T(0); A.X4[i] = T(0); A.X5[i] = T(0); A.X6[i] = T(0);
     A.dQ0[0][i] = T(0); A.dQ0[1][i] = T(0); A.dQ0[2][i] = T(0);
+    A.S5[i] = T(0); A.S6[i] = T(0);
   }
 }
 
@@ -255,7 +263,7 @@ HGKS_FN void primitives(const T (&Q)[5], const GasParams<T>& g, Prim<T>& s) {
   s.c5 = s.il * s.il * g.inv_K3;             // 4 lambda^2 / (K + 3)
 }
 
-template <int SIDE, typename T>
+template <int SIDE, bool PR = false, typename T>
 HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>& g, FluxAcc<T>& A) {
   Prim<T> P;
   primitives(W, g, P);
@@ -276,6 +284,7 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
     mom_a<1, false>(s, t, mf, r);
     mom_a<0, true>(s, t, mh, A.dQ0[0]);
     mom_a<2, true>(s, t, mh, A.X5);
+    if constexpr (PR) mom_a<1, true>(s, t, mh, A.S5);
   }
   {
     T a[5];
@@ -285,6 +294,7 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
     mom_av<0, true>(s, t, mf, r);
     mom_a<0, true>(s, t, mh, A.dQ0[1]);
     mom_av<1, true>(s, t, mh, A.X5);
+    if constexpr (PR) mom_av<0, true>(s, t, mh, A.S5);
   }
   {
     T a[5];
@@ -294,6 +304,7 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
     mom_aw<0, true>(s, t, mf, r);
     mom_a<0, true>(s, t, mh, A.dQ0[2]);
     mom_aw<1, true>(s, t, mh, A.X5);
+    if constexpr (PR) mom_aw<0, true>(s, t, mh, A.S5);
   }
 #pragma unroll
   for (int i = 0; i < 5; ++i) r[i] = -r[i];
@@ -303,6 +314,7 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
     micro_slope(r, U, V, Wv, il, q, c5, a);
     slope_prep(a, t, s);
     mom_a<1, true>(s, t, mh, A.X6);
+    if constexpr (PR) mom_a<0, true>(s, t, mh, A.S6);
   }
   T v5[5];
   mom_psi<0>(t, mh, v5);
@@ -345,15 +357,18 @@ HGKS_FN void time_integrals(T delta, T tau, T itau, T (&Tc)[5]) {
 // conservative variables of g_0.  The collision time and the coefficients
 // of the time fit come first, so that every moment is folded into F and dF
 // as soon as it is formed.
-template <typename T>
+template <bool PR = false, typename T>
 HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&F)[5], T (&dF)[5]) {
   Prim<T> P;
   primitives(A.Q0, g, P);
   const T r0 = P.rho, U = P.U, V = P.V, W = P.W, h = P.h, il = P.il, q = P.q, c5 = P.c5;
 
   const T jump = d_abs(A.p[0] - A.p[1]) * d_rcp(A.p[0] + A.p[1]) * dt;
-  // mu / p_0 = mu (rho_0 / p_0) (1 / rho_0)
-  const T tau = g.viscous ? g.mu * il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
+  // mu / p_0 = mu (rho_0 / p_0) (1 / rho_0); mu = mu0 (T / T0)^omega with
+  // T = p_0 / rho_0 when a viscosity law is set
+  T mu = g.mu;
+  if (g.mu_exp != T(0)) mu *= exp(g.mu_exp * log(P.h * g.mu_iT0));
+  const T tau = g.viscous ? mu * il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
   const T itau = T(1) / tau;
   T c[5], d[5];
   {
@@ -434,6 +449,30 @@ HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&
     mom_a<1, false>(s, t, m, v5);
     axpy5(c[2], v5, F);
     axpy5(d[2], v5, dF);
+  }
+  if constexpr (PR) {
+    // Prandtl correction: the heat flux relative to the velocity (U, V, W)
+    // of g_0 is the moment of (u - U)(|c|^2 + xi^2)/2, which expands into the
+    // fluxes F and the state moments S of the same distribution:
+    //   q = F_E - U.F_M + |U|^2/2 F_rho - U (S_E - U.S_M + |U|^2/2 S_rho).
+    // S over time: g_0's moments Q0 (T1 and T4 terms), rho_0 <Abar psi> = r
+    // (T3 - T2) and the initial slopes and time derivatives (-T5 S5,
+    // -tau T4 S6); fitted with the same coefficients as the flux.
+    const T u2 = T(0.5) * (U * U + V * V + W * W);
+    T S[5], dS[5];
+    const T ce = c[0] + c[3], de = d[0] + d[3], cr = c[2] - c[1], dr = d[2] - d[1];
+    const T c6 = tau * c[3], d6 = tau * d[3];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      S[i] = ce * A.Q0[i] + cr * r[i] - c[4] * A.S5[i] - c6 * A.S6[i];
+      dS[i] = de * A.Q0[i] + dr * r[i] - d[4] * A.S5[i] - d6 * A.S6[i];
+    }
+    const T B = S[4] - (U * S[1] + V * S[2] + W * S[3]) + u2 * S[0];
+    const T dB = dS[4] - (U * dS[1] + V * dS[2] + W * dS[3]) + u2 * dS[0];
+    const T qf = F[4] - (U * F[1] + V * F[2] + W * F[3]) + u2 * F[0] - U * B;
+    const T dq = dF[4] - (U * dF[1] + V * dF[2] + W * dF[3]) + u2 * dF[0] - U * dB;
+    F[4] += g.pr_fix * qf;
+    dF[4] += g.pr_fix * dq;
   }
 }
 

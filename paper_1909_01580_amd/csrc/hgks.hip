@@ -67,6 +67,10 @@ bool valid_config(const hgks_config* c) {
   if (c->moving != 0 && c->moving != 1) return false;
   if (c->characteristic != 0 && c->characteristic != 1) return false;
   if (c->characteristic && c->moving) return false;
+  if (!(c->mu_T0 > 0.0) || !std::isfinite(c->mu_exponent) || !(c->prandtl > 0.0) || !std::isfinite(c->prandtl))
+    return false;
+  // the viscosity law and the Prandtl correction are offered on box grids
+  if (c->moving && (c->mu_exponent != 0.0 || c->prandtl != 1.0)) return false;
   if (c->moving)
     for (int d = 0; d < 3; ++d)
       if (c->bc[d] != HGKS_BC_PERIODIC) return false;
@@ -231,6 +235,9 @@ GasParams<T> gas_params(const hgks_config& cfg) {
   g.tau_eps = T(cfg.tau_eps);
   g.tau_C = T(cfg.tau_C);
   g.viscous = cfg.mu > 0.0;
+  g.mu_exp = T(cfg.mu_exponent);
+  g.mu_iT0 = T(1.0 / cfg.mu_T0);
+  g.pr_fix = T(1.0 / cfg.prandtl - 1.0);
   return g;
 }
 
@@ -274,9 +281,15 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
   unsigned nb[3];
   flux_block_counts(c->G, nb);
   prof_mark(c, HGKS_PHASE_FLUX, true);
-  hipLaunchKernelGGL((k_flux_box<TC>), dim3(pad8(nb[0] + nb[1] + nb[2])), dim3(kBlock), 0, c->stream,
-                     (const TC*)face_coef<TC>(c), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->G, gp, TC(dt), TC(1.0 / dt),
-                     nb[0], nb[1], nb[2]);
+  const dim3 grid(pad8(nb[0] + nb[1] + nb[2]));
+  const TC* fc = face_coef<TC>(c);
+  TC* f[3] = {(TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2)};
+  if (c->cfg.prandtl != 1.0)
+    hipLaunchKernelGGL((k_flux_box<TC, true>), grid, dim3(kBlock), 0, c->stream, fc, c->mask(), f[0], f[1], f[2],
+                       c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2]);
+  else
+    hipLaunchKernelGGL((k_flux_box<TC, false>), grid, dim3(kBlock), 0, c->stream, fc, c->mask(), f[0], f[1], f[2],
+                       c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2]);
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
@@ -441,6 +454,9 @@ hgks_status hgks_default_config(hgks_config* cfg, int32_t nx, int32_t ny, int32_
   cfg->tau_C = 1.0;
   cfg->precision = HGKS_FP64;
   for (int d = 0; d < 3; ++d) cfg->bc_hi[d] = HGKS_BC_SAME;
+  cfg->mu_T0 = 1.0;
+  cfg->mu_exponent = 0.0;
+  cfg->prandtl = 1.0;
   return HGKS_OK;
 }
 
@@ -770,7 +786,7 @@ hgks_status busable(hgks_batch b) {
 }
 
 bool batch_compatible(const hgks_config& a, const hgks_config& c) {
-  if (!valid_config(&c) || c.moving || c.characteristic) return false;
+  if (!valid_config(&c) || c.moving || c.characteristic || c.mu_exponent != 0.0 || c.prandtl != 1.0) return false;
   for (int d = 0; d < 3; ++d)
     if (c.bc[d] != HGKS_BC_PERIODIC) return false;
   return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&

@@ -34,6 +34,9 @@ inline Cnt& operator-=(Cnt& a, Cnt b) { a = a - b; return a; }
 inline Cnt& operator*=(Cnt& a, Cnt b) { a = a * b; return a; }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
+inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
+inline Cnt exp(Cnt x) { ++cnt::tr; return Cnt(std::exp(x.v)); }
+inline Cnt log(Cnt x) { ++cnt::tr; return Cnt(std::log(x.v)); }
 
 namespace hgks {
 template <> HGKS_FN Cnt d_exp<Cnt>(Cnt x) { ++cnt::tr; return Cnt(std::exp(x.v)); }

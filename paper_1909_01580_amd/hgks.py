@@ -46,6 +46,7 @@ class hgks_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("bc_hi", ctypes.c_int32 * 3),
         ("characteristic", ctypes.c_int32),
+        ("mu_T0", ctypes.c_double), ("mu_exponent", ctypes.c_double), ("prandtl", ctypes.c_double),
     ]
 
 
@@ -235,7 +236,7 @@ class Context:
 
     def __init__(self, n, bc=("periodic",) * 3, gamma=1.4, mu=0.0, weno_Gamma=0.0025,
                  weno_eps=1e-8, tau_eps=0.01, tau_C=1.0, precision="fp64", moving=False,
-                 characteristic=False, device="cuda:0", stream=None):
+                 characteristic=False, mu_T0=1.0, mu_exponent=0.0, prandtl=1.0, device="cuda:0", stream=None):
         self.n = tuple(int(x) for x in n)
         self.device = torch.device(device)
         cfg = hgks_default_config(*self.n)
@@ -250,6 +251,7 @@ class Context:
         cfg.precision = PREC[precision]
         cfg.moving = 1 if moving else 0
         cfg.characteristic = 1 if characteristic else 0
+        cfg.mu_T0, cfg.mu_exponent, cfg.prandtl = mu_T0, mu_exponent, prandtl
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

@@ -126,6 +126,64 @@ def sedov_state(n, length=1.2, energy=SEDOV_ENERGY, p_background=1e-6, gamma=GAM
     return np.ascontiguousarray(conservative(rho, zero, zero, zero, p, gamma))
 
 
+# ------------------------------------------------ isotropic turbulence
+ISO_A0, ISO_K0, ISO_RE_LAMBDA = 1.3e-4, 8.0, 72.0
+ISO_PRANDTL, ISO_MU_EXPONENT = 0.71, 0.76
+
+
+def isotropic_turbulence_params(mach_t, A0=ISO_A0, k0=ISO_K0, re_lambda=ISO_RE_LAMBDA, gamma=GAMMA, rho0=1.0):
+    """Scales of the compressible isotropic turbulence of Sec. 4 from the
+    spectrum E(k) = A0 k^4 exp(-2 k^2 / k0^2): initial kinetic energy
+    K0 = 3 A0 sqrt(2 pi) k0^5 / 64, u_rms = sqrt(2 K0 / 3), the large-eddy
+    turnover time sqrt(32 / A0) (2 pi)^(1/4) k0^(-7/2); T0 from
+    Ma_t = sqrt(3) u_rms / sqrt(gamma T0) and mu0 from
+    Re_lambda = (2 pi)^(1/4) / 4 (rho0 / mu0) sqrt(2 A0) k0^(3/2) (unit gas
+    constant, so p = rho T)."""
+    K0 = 3.0 * A0 / 64.0 * np.sqrt(2 * np.pi) * k0 ** 5
+    u_rms = np.sqrt(2.0 * K0 / 3.0)
+    T0 = 3.0 * u_rms ** 2 / (gamma * mach_t ** 2)
+    mu0 = (2 * np.pi) ** 0.25 / 4.0 * rho0 * np.sqrt(2.0 * A0) * k0 ** 1.5 / re_lambda
+    tau_t0 = np.sqrt(32.0 / A0) * (2 * np.pi) ** 0.25 * k0 ** -3.5
+    return {"K0": K0, "u_rms": u_rms, "T0": T0, "p0": rho0 * T0, "rho0": rho0, "mu0": mu0,
+            "tau_t0": tau_t0, "mu_exponent": ISO_MU_EXPONENT, "prandtl": ISO_PRANDTL}
+
+
+def isotropic_turbulence_state(n, mach_t, seed=190901580, A0=ISO_A0, k0=ISO_K0, gamma=GAMMA):
+    """Seeded divergence-free random velocity on the periodic box
+    [-pi, pi]^3 with the spectrum A0 k^4 exp(-2 k^2 / k0^2) (each Fourier
+    mode: Gaussian random complex amplitude, projected normal to its wave
+    vector, scaled to the spectrum's energy per mode E(|k|) / (4 pi |k|^2);
+    no Nyquist modes), the real part sampled at cell centres and scaled to
+    the u_rms of the spectrum; uniform
+    density rho0 = 1 and temperature T0 from Ma_t.  Returns the conservative
+    state [5][n][n][n] and the parameters."""
+    P = isotropic_turbulence_params(mach_t, A0=A0, k0=k0, gamma=gamma)
+    rng = np.random.default_rng(seed)
+    k1 = np.fft.fftfreq(n, 1.0 / n)
+    KZ, KY, KX = np.meshgrid(k1, k1, k1, indexing="ij")
+    kk = np.stack([KX, KY, KZ])
+    k2 = (kk ** 2).sum(axis=0)
+    kmag = np.sqrt(k2)
+    a = rng.standard_normal((3, n, n, n)) + 1j * rng.standard_normal((3, n, n, n))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        a -= kk * (kk * a).sum(axis=0) / np.where(k2 > 0, k2, 1.0)
+        norm = np.sqrt((np.abs(a) ** 2).sum(axis=0))
+        E = A0 * kmag ** 4 * np.exp(-2.0 * k2 / k0 ** 2)
+        amp = np.where(k2 > 0, np.sqrt(E / (4 * np.pi * np.where(k2 > 0, k2, 1.0))) / np.where(norm > 0, norm, 1.0),
+                       0.0)
+    a *= amp
+    # no Nyquist modes: their partner -k is not on the grid
+    a[:, np.abs(kk).max(axis=0) >= n // 2] = 0.0
+    # the FFT nodes are taken as the cell centres (a translation of a
+    # statistically homogeneous field)
+    u = np.real(np.fft.ifftn(a, axes=(1, 2, 3))) * n ** 3
+    urms = np.sqrt((u ** 2).sum(axis=0).mean() / 3.0)
+    u *= P["u_rms"] / urms
+    rho = np.full((n, n, n), P["rho0"])
+    p = np.full((n, n, n), P["p0"])
+    return np.ascontiguousarray(conservative(rho, u[0], u[1], u[2], p, gamma)), P
+
+
 # ------------------------------------------------------------ deformed grids
 def sine_mesh_vertices(n, t, amp=0.1, omega=np.pi, length=2.0, static=False):
     """Vertices x = xi + amp sin(pi xi) sin(pi eta) sin(pi zeta) s(t) (all

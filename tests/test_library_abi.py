@@ -51,7 +51,7 @@ def test_defaults_and_workspace(lib):
 
 @pytest.mark.parametrize("field,value", [("nx", 1), ("gamma", 1.0), ("weno_Gamma", 0.05),
                                          ("weno_eps", 0.0), ("precision", 7), ("moving", 2),
-                                         ("characteristic", 2)])
+                                         ("characteristic", 2), ("mu_T0", 0.0), ("prandtl", 0.0)])
 def test_invalid_configurations_rejected(lib, field, value):
     from paper_1909_01580_amd import hgks
     cfg = hgks.hgks_default_config(8, 8, 8)
@@ -107,6 +107,21 @@ def test_characteristic_workspace_and_limits(lib):
     cfg.moving = 0
     with pytest.raises(hgks.HGKSError):
         hgks.hgks_batch_workspace_size([cfg])
+
+
+def test_viscosity_law_and_prandtl_limits(lib):
+    """Defaults: constant mu, Pr = 1; the law and the correction are offered
+    on box grids, not on moving meshes or in batches."""
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(8, 8, 8)
+    assert (cfg.mu_T0, cfg.mu_exponent, cfg.prandtl) == (1.0, 0.0, 1.0)
+    cfg.mu, cfg.mu_exponent, cfg.prandtl = 1e-3, 0.76, 0.71
+    assert hgks.hgks_workspace_size(cfg) > 0
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_batch_workspace_size([cfg])
+    cfg.moving = 1
+    with pytest.raises(hgks.HGKSError):
+        hgks.hgks_workspace_size(cfg)
 
 
 def test_moving_requires_periodic(lib):
