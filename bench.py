@@ -203,6 +203,35 @@ def run_moving(n, steps, warmup, precision, v0, q0, cfl=0.35):
     return {"ms": ms, "prof": prof, "rho": ctx.get_state()[0].cpu().numpy(), "drift": drift}
 
 
+def run_turbulence(n, steps, warmup, precision, mach_t):
+    """Compressible isotropic turbulence (Sec. 4) on [-pi, pi]^3, periodic:
+    seeded divergence-free field with the spectrum A0 k^4 exp(-2 k^2/k0^2)
+    (A0 1.3e-4, k0 8), Re_lambda 72, the given Ma_t, viscosity
+    mu0 (T/T0)^0.76 and Prandtl number 0.71, CFL 0.35."""
+    import torch
+    from paper_1909_01580_amd import hgks
+    from paper_1909_01580_amd import workloads as wl
+
+    q0, P = wl.isotropic_turbulence_state(n, mach_t)
+    ctx = hgks.Context((n, n, n), mu=P["mu0"], precision=precision, mu_T0=P["T0"],
+                       mu_exponent=P["mu_exponent"], prandtl=P["prandtl"])
+    ctx.set_uniform_grid((-np.pi,) * 3, (2 * np.pi,) * 3)
+    ctx.set_state(torch.tensor(q0, device="cuda:0"))
+    for _ in range(warmup):
+        ctx.step(ctx.max_dt(0.35), 2)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.profile_begin()
+    ev0.record()
+    for _ in range(steps):
+        ctx.step(ctx.max_dt(0.35), 2)
+    ev1.record()
+    torch.cuda.synchronize()
+    prof = ctx.profile_end()
+    return {"ms": ev0.elapsed_time(ev1), "prof": prof, "rho": ctx.get_state()[0].cpu().numpy(),
+            "nonphysical": ctx.check()[0]}
+
+
 def run_octant(n, steps, warmup, precision):
     """Sedov blast in the octant [0,1.2]^3 (Sec. 4): symmetric planes at
     x, y, z = 0, outflow at 1.2, the released energy in the corner cell,
@@ -299,6 +328,8 @@ def main():
     ap.add_argument("--moving-steps", type=int, default=10)
     ap.add_argument("--no-octant", action="store_true")
     ap.add_argument("--no-characteristic", action="store_true")
+    ap.add_argument("--no-turbulence", action="store_true")
+    ap.add_argument("--turbulence-steps", type=int, default=5)
     ap.add_argument("--characteristic-steps", type=int, default=5)
     ap.add_argument("--octant-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -430,6 +461,21 @@ def main():
             "mixed_value": cells * 2 * cs / (cr["mixed"]["ms"] / 1e3),
             "mixed_phases_ms_per_step": {k: v[0] / cs for k, v in cr["mixed"]["prof"].items()},
             "cost_vs_componentwise_fp64": (cr["fp64"]["ms"] / cs) / ms_step,
+        }
+    if not args.no_turbulence:
+        ts = args.turbulence_steps
+        tb = {p: run_turbulence(n, ts, 1, p, 0.5) for p in ("fp64", "mixed")}
+        r64 = tb["fp64"]["rho"]
+        out["turbulence"] = {
+            "workload": f"compressible isotropic turbulence {n}^3 periodic [-pi,pi]^3, Ma_t 0.5, Re_lambda 72, "
+                        "spectrum A0 k^4 exp(-2k^2/k0^2) (A0 1.3e-4, k0 8), mu0 (T/T0)^0.76, Pr 0.71 "
+                        "(heat-flux correction), CFL 0.35",
+            "value": cells * 2 * ts / (tb["fp64"]["ms"] / 1e3), "unit": "cell-stage updates/s", "dtype": "f64",
+            "ms_per_step": tb["fp64"]["ms"] / ts,
+            "phases_ms_per_step": {k: v[0] / ts for k, v in tb["fp64"]["prof"].items()},
+            "mixed_value": cells * 2 * ts / (tb["mixed"]["ms"] / 1e3),
+            "l1_rho_rel_error_mixed_vs_fp64": float(np.abs(tb["mixed"]["rho"] - r64).sum() / np.abs(r64).sum()),
+            "nonphysical_cells": {p: tb[p]["nonphysical"] for p in tb},
         }
     if head.get("first") is not None and not args.no_oracle_check:
         err, ns = sampled_oracle_error(head["q0"], head["first"], n)
