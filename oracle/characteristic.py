@@ -74,7 +74,7 @@ def indicators(a, b, X, wg, h, V):
     """Smoothness indicators (Eq. (4)) of P_0 with coefficients a (9,k,...)
     and of P_1..P_24 with coefficients b (24,3,k,...), over a cell with
     scaled Gauss points X (3,8,...), weights wg (8,...), scale h and
-    volume V.  Returns beta (25,k,...)."""
+    volume V.  Returns beta (M+1,k,...) for M sub-stencils."""
     G = weno.mono_grad(X)                                 # (9,3,8,...)
     Hs = weno.mono_hess()                                 # (9,6)
     ex = (slice(None),) * 3 + (None,)
@@ -82,19 +82,21 @@ def indicators(a, b, X, wg, h, V):
     d2 = np.einsum("ns,nk...->sk...", Hs, a) / h ** 2     # (6,k,...)
     int1 = (d1 ** 2 * wg[None, :, None]).sum(axis=(0, 1))
     int2 = (d2 ** 2).sum(axis=0) * V
-    beta = np.empty((25,) + int1.shape)
+    M = b.shape[0]
+    beta = np.empty((M + 1,) + int1.shape)
     beta[0] = V ** (2.0 / 3.0 - 1.0) * int1 + V ** (4.0 / 3.0 - 1.0) * int2
     wsum = wg.sum(axis=0)
-    for m in range(24):
+    for m in range(M):
         beta[1 + m] = V ** (2.0 / 3.0 - 1.0) * ((b[m] / h) ** 2).sum(axis=0) * wsum
     return beta
 
 
 def nonlinear_weights(beta, Gamma, eps):
     """Normalised weights of Eqs. (3) and (5) from the indicators."""
-    gam = weno.linear_weights(Gamma)
-    gshape = (25,) + (1,) * (beta.ndim - 1)
-    tau = np.abs(beta[0][None] - beta[1:]).sum(axis=0) / 24.0
+    M = beta.shape[0] - 1
+    gam = weno.linear_weights(Gamma, M)
+    gshape = (M + 1,) + (1,) * (beta.ndim - 1)
+    tau = np.abs(beta[0][None] - beta[1:]).sum(axis=0) / M
     omega = gam.reshape(gshape) * (1.0 + tau[None] / (beta + eps))
     return omega / omega.sum(axis=0)[None]
 

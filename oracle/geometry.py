@@ -22,7 +22,8 @@ GNODE = 0.5 / np.sqrt(3.0)
 GAUSS = (-GNODE, GNODE)
 GWEIGHT = 0.5
 
-PAD = 2  # ghost layers kept around the real cells in every direction
+PAD = 3  # ghost layers kept around the real cells in every direction (the
+         # wide stencil of Remark 1 reaches two cells beyond the ghost layer)
 
 
 def padded_vertices_uniform(n, origin, length, pad=PAD):

@@ -53,6 +53,7 @@ class Params:
     mu_T0: float = 1.0             # viscosity law mu (T / mu_T0)^mu_exponent (Sec. 4)
     mu_exponent: float = 0.0       # 0: constant mu
     prandtl: float = 1.0           # 1: the BGK flux as it stands
+    stencil: str = "S"             # "S" (Sec. 2) or "S_prime" (Remark 1)
 
 
 BOUNDARIES = ("periodic", "outflow", "symmetric")
@@ -135,6 +136,9 @@ class Problem:
                 if hi == "symmetric":
                     src[above] = 2 * n - 1 - idx[above]
                     sign[above] = -1.0
+                # a mirror deeper than the grid (n < PAD) only feeds ghost
+                # layers the stencil of Sec. 2 never reads
+                src = np.clip(src, 0, n - 1)
             out = np.take(out, src, axis=1 + d)
             if np.any(sign < 0):
                 shape = [1, 1, 1]
@@ -313,7 +317,7 @@ def residual(prob, Q, dt, alpha=0.0, keep_faces=False):
     vdot = prob.padded_velocities(dt) if prob.moving else None
     xq, wj = geo.cell_quadrature(vp)
     V, c, h = geo.cell_volume_centroid(xq, wj)
-    rec = weno.reconstruct(xq, wj, V, c, h, prob.pad_state(Q), P.weno_Gamma, P.weno_eps)
+    rec = weno.reconstruct(xq, wj, V, c, h, prob.pad_state(Q), P.weno_Gamma, P.weno_eps, P.stencil)
     n = prob.n
     R = np.zeros((5,) + n)
     dR = np.zeros((5,) + n)

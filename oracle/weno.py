@@ -30,6 +30,8 @@ cyclic permutations of the axes; each multi-index in beta appears once.
 
 import numpy as np
 
+from .geometry import PAD
+
 # Monomials x^n with 1 <= |n| <= 2, as exponent triples.
 MONO = [(1, 0, 0), (0, 1, 0), (0, 0, 1),
         (2, 0, 0), (0, 2, 0), (0, 0, 2),
@@ -71,11 +73,23 @@ def sub_stencil_offsets():
 
 SUB_OFFSETS = sub_stencil_offsets()
 
+# The alternative of Remark 1 (Sec. 2): big stencil S' = S plus the six
+# cells two steps away along the axes, and eight sub-stencils S'_1..S'_8,
+# each the centre and one face neighbour per axis, one per sign octant
+# (the printed S'_4 and S'_8 repeat S'_2 and S'_6; read as the two
+# remaining octants, as for S_4 and S_8).  The octant set is closed under
+# permutations of the axes, so there are no further sub-stencils.
+BIG_OFFSETS_WIDE = BIG_OFFSETS + [_unit(ax, 2 * sg) for ax in range(3) for sg in (-1, 1)]
+SUB_OFFSETS_WIDE = [[_unit(0, sx), _unit(1, sy), _unit(2, sz)]
+                    for sz in (1, -1) for sy in (1, -1) for sx in (1, -1)]
+STENCILS = {"S": (BIG_OFFSETS, SUB_OFFSETS), "S_prime": (BIG_OFFSETS_WIDE, SUB_OFFSETS_WIDE)}
 
-def linear_weights(Gamma):
-    """gamma_0 = 1 - 24 Gamma, gamma_m = Gamma (Sec. 2)."""
-    g = np.full(25, Gamma)
-    g[0] = 1.0 - 24.0 * Gamma
+
+def linear_weights(Gamma, M=24):
+    """gamma_0 = 1 - M Gamma, gamma_m = Gamma for the M sub-stencils
+    (Sec. 2: M = 24)."""
+    g = np.full(M + 1, Gamma)
+    g[0] = 1.0 - M * Gamma
     return g
 
 
@@ -127,19 +141,24 @@ def mono_hess():
 
 def _shift(arr, off, N):
     """Slice of a padded array at the reconstructed cells shifted by off.
-    Reconstructed cells are padded indices [1, N-1) along each axis."""
-    sl = tuple(slice(1 + off[d], N[d] - 1 + off[d]) for d in range(3))
+    Reconstructed cells are the real cells and one ghost layer, padded
+    indices [PAD-1, N-PAD+1) along each axis."""
+    g = PAD - 1
+    sl = tuple(slice(g + off[d], N[d] - g + off[d]) for d in range(3))
     return arr[(Ellipsis,) + sl]
 
 
-def reconstruct(xq, wj, V, c, h, Qp, Gamma, eps):
+def reconstruct(xq, wj, V, c, h, Qp, Gamma, eps, stencil="S"):
     """WENO-AO reconstruction for every cell with a full big stencil.
 
     Inputs are per padded cell: Gauss points xq (3,8,...), weights wj (8,...),
     volume V, centroid c (3,...), scale h, cell averages Qp (5,...).
     Returns a dict of per-reconstructed-cell arrays (padded indices
-    [1, N-1) along each axis).
+    [PAD-1, N-PAD+1) along each axis).  ``stencil`` is "S" (Sec. 2) or
+    "S_prime" (Remark 1).
     """
+    big_offs, sub_offs = STENCILS[stencil]
+    M = len(sub_offs)
     N = V.shape
     ci = _shift(c, (0, 0, 0), N)
     hi = _shift(h, (0, 0, 0), N)
@@ -153,20 +172,21 @@ def reconstruct(xq, wj, V, c, h, Qp, Gamma, eps):
         return (mono_values(X) * wo[None]).sum(axis=1) / Vo
 
     avg_i = mean_mono((0, 0, 0))
-    rows = {off: mean_mono(off) - avg_i for off in BIG_OFFSETS}
-    diffs = {off: _shift(Qp, off, N) - Qi for off in BIG_OFFSETS}
-    shp = V[1:-1, 1:-1, 1:-1].shape
+    rows = {off: mean_mono(off) - avg_i for off in big_offs}
+    diffs = {off: _shift(Qp, off, N) - Qi for off in big_offs}
+    shp = ci.shape[1:]
     nr = int(np.prod(shp))
 
     # P_0: 18 x 9 least squares per cell (Eq. (1) and the big-stencil
     # constraints).
-    A = np.stack([rows[o].reshape(9, nr).T for o in BIG_OFFSETS], axis=1)      # (nr,18,9)
-    D = np.stack([diffs[o].reshape(5, nr).T for o in BIG_OFFSETS], axis=1)     # (nr,18,5)
+    A = np.stack([rows[o].reshape(9, nr).T for o in big_offs], axis=1)         # (nr,18,9)
+    D = np.stack([diffs[o].reshape(5, nr).T for o in big_offs], axis=1)        # (nr,18,5)
     a = np.linalg.pinv(A) @ D                                                  # (nr,9,5)
 
-    # P_m: 4 x 3 least squares on the linear monomials (Eq. (2)).
-    b = np.empty((nr, 24, 3, 5))
-    for m, offs in enumerate(SUB_OFFSETS):
+    # P_m: 4 x 3 least squares on the linear monomials (Eq. (2)); 3 x 3 for
+    # the sub-stencils of Remark 1.
+    b = np.empty((nr, M, 3, 5))
+    for m, offs in enumerate(sub_offs):
         Am = np.stack([rows[o][:3].reshape(3, nr).T for o in offs], axis=1)     # (nr,4,3)
         Dm = np.stack([diffs[o].reshape(5, nr).T for o in offs], axis=1)        # (nr,4,5)
         b[:, m] = np.linalg.pinv(Am) @ Dm
@@ -184,16 +204,16 @@ def reconstruct(xq, wj, V, c, h, Qp, Gamma, eps):
     d2 = np.einsum("ns,rnv->svr", Hs, a) / hf ** 2       # (6,5,nr)
     int1 = (d1 ** 2 * wo[None, :, None, :]).sum(axis=(0, 1))            # (5,nr)
     int2 = (d2 ** 2).sum(axis=0) * Vi                                   # (5,nr)
-    beta = np.empty((25, 5, nr))
+    beta = np.empty((M + 1, 5, nr))
     beta[0] = Vi ** (2.0 / 3.0 - 1.0) * int1 + Vi ** (4.0 / 3.0 - 1.0) * int2
-    for m in range(24):
+    for m in range(M):
         g = b[:, m] / hf[:, None, None]                  # (nr,3,5) physical gradient
         intm = (g ** 2).sum(axis=1).T * wo.sum(axis=0)   # (5,nr)
         beta[1 + m] = Vi ** (2.0 / 3.0 - 1.0) * intm
 
     # Nonlinear weights, Eqs. (3) and (5).
-    gam = linear_weights(Gamma)
-    tau = np.abs(beta[0][None] - beta[1:]).sum(axis=0) / 24.0
+    gam = linear_weights(Gamma, M)
+    tau = np.abs(beta[0][None] - beta[1:]).sum(axis=0) / M
     omega = gam[:, None, None] * (1.0 + tau[None] / (beta + eps))
     wbar = omega / omega.sum(axis=0)[None]
 
@@ -221,25 +241,27 @@ def select(rec, index):
     out["xg"] = rec["xg"][:, :, flat].reshape((3, 8) + shp)
     out["wg"] = rec["wg"][:, flat].reshape((8,) + shp)
     out["a"] = np.moveaxis(rec["a"][flat], 0, -1).reshape((9, 5) + shp)
-    out["b"] = np.moveaxis(rec["b"][flat], 0, -1).reshape((24, 3, 5) + shp)
-    out["wbar"] = rec["wbar"][:, :, flat].reshape((25, 5) + shp)
+    M = rec["b"].shape[1]
+    out["b"] = np.moveaxis(rec["b"][flat], 0, -1).reshape((M, 3, 5) + shp)
+    out["wbar"] = rec["wbar"][:, :, flat].reshape((M + 1, 5) + shp)
     out["gamma"] = rec["gamma"]
     return out
 
 
 def eval_polys(sel, x):
-    """Values (25,5,...) and physical gradients (25,3,5,...) of P_0..P_24 of
-    the selected cells at physical points x (3, ...)."""
+    """Values (M+1,5,...) and physical gradients (M+1,3,5,...) of P_0..P_M
+    of the selected cells at physical points x (3, ...)."""
     X = (x - sel["c"]) / sel["h"]
     mv = mono_values(X) - sel["avg"]                     # (9,...)
     mg = mono_grad(X)                                    # (9,3,...)
     Q = sel["Q"]
     shp = np.broadcast_shapes(Q.shape[1:], X.shape[1:])
-    vals = np.empty((25, 5) + shp)
-    grads = np.empty((25, 3, 5) + shp)
+    M = sel["b"].shape[0]
+    vals = np.empty((M + 1, 5) + shp)
+    grads = np.empty((M + 1, 3, 5) + shp)
     vals[0] = Q + np.einsum("n...,nv...->v...", mv, sel["a"])
     grads[0] = np.einsum("nd...,nv...->dv...", mg, sel["a"]) / sel["h"]
-    for m in range(24):
+    for m in range(M):
         bm = sel["b"][m]                                 # (3,5,...)
         vals[1 + m] = Q + np.einsum("d...,dv...->v...", mv[:3], bm)
         grads[1 + m] = bm / sel["h"]
@@ -251,16 +273,18 @@ def combine(sel, vals, grads):
     wbar_0 (P_0/gamma_0 - sum gamma_m/gamma_0 P_m) + sum wbar_m P_m."""
     gam = sel["gamma"]
     w = sel["wbar"]
-    val = w[0] * (vals[0] / gam[0] - sum(gam[m] / gam[0] * vals[m] for m in range(1, 25))) \
-        + sum(w[m] * vals[m] for m in range(1, 25))
-    grad = w[0][None] * (grads[0] / gam[0] - sum(gam[m] / gam[0] * grads[m] for m in range(1, 25))) \
-        + sum(w[m][None] * grads[m] for m in range(1, 25))
+    K = len(gam)
+    val = w[0] * (vals[0] / gam[0] - sum(gam[m] / gam[0] * vals[m] for m in range(1, K))) \
+        + sum(w[m] * vals[m] for m in range(1, K))
+    grad = w[0][None] * (grads[0] / gam[0] - sum(gam[m] / gam[0] * grads[m] for m in range(1, K))) \
+        + sum(w[m][None] * grads[m] for m in range(1, K))
     return val, grad
 
 
 def positivity_trigger(vals, gamma):
-    """True where any of the 25 polynomials gives a non-positive density or
-    a negative pressure at the point (Sec. 4 limiting procedure)."""
+    """True where any of the polynomials (25, or 9 with the stencils of
+    Remark 1) gives a non-positive density or a negative pressure at the
+    point (Sec. 4 limiting procedure)."""
     rho = vals[:, 0]
     bad_rho = rho <= 0.0
     rs = np.where(bad_rho, 1.0, rho)

@@ -1,0 +1,175 @@
+"""Pins for the alternative stencils of Remark 1 (Sec. 2) in the oracle: the
+big stencil S' (S plus the six cells two steps away along the axes) and the
+eight sub-stencils S'_1..S'_8 (the centre and one face neighbour per axis).
+
+* structure against the printed list (tests/golden/substencils_Sprime.txt);
+* P_0 reproduces quadratics on boxes and deformed hexahedra;
+* linear data give equal indicators, the linear weights (gamma_0 = 1 - 8
+  Gamma) and the exact value;
+* closed forms of the 24x9 normal equations on unit cubes derived by hand:
+  a_d = (1/18) sum o_d d_o, a_de = (1/4) sum o_d o_e d_o,
+  a_dd = (r_d - (2/25)(r_x + r_y + r_z)) / 38 with r_d = sum o_d^2 d_o; the
+  sub-stencils interpolate, b_d = s_d d_{s_d e_d};
+* a hand-worked step: every cell with o_x >= 1 equal to 1, the centre 0:
+  a_x = 7/18, a_xx = 199/950, a_yy = a_zz = 12/475, four sub-stencils with
+  beta = 1 and four with beta = 0.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import geometry as geo
+from oracle import weno
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+W = "S_prime"
+
+
+def build(vp, avg_fn, Gamma=0.0025, eps=1e-8):
+    xq, wj = geo.cell_quadrature(vp)
+    V, c, h = geo.cell_volume_centroid(xq, wj)
+    return weno.reconstruct(xq, wj, V, c, h, avg_fn(xq, wj, V, c), Gamma, eps, stencil=W)
+
+
+def box(n=7, h=1.0):
+    return geo.padded_vertices_uniform((n, n, n), (0.0,) * 3, (n * h,) * 3, pad=0)
+
+
+def centre(rec):
+    shp = rec["shape"]
+    return np.ravel_multi_index(tuple(s // 2 for s in shp), shp)
+
+
+def test_structure_against_printed_list():
+    big = weno.BIG_OFFSETS_WIDE
+    assert len(big) == 24 and len(set(big)) == 24
+    assert set(weno.BIG_OFFSETS) < set(big)
+    assert {o for o in big if max(map(abs, o)) == 2} == {
+        tuple(2 * s if i == ax else 0 for i in range(3)) for ax in range(3) for s in (-1, 1)}
+    subs = weno.SUB_OFFSETS_WIDE
+    assert len(subs) == 8 and len({frozenset(s) for s in subs}) == 8
+    rows = np.loadtxt(os.path.join(GOLDEN, "substencils_Sprime.txt"), dtype=int)
+    printed = [frozenset(tuple(r[3 * k:3 * k + 3]) for k in range(3)) for r in rows[:8]]
+    read = [frozenset(tuple(r[3 * k:3 * k + 3]) for k in range(3)) for r in rows[8:]]
+    assert printed[3] == printed[1] and printed[7] == printed[5]   # the printed duplicates
+    ours = {frozenset(s) for s in subs}
+    assert ours == set(printed[:3] + printed[4:7] + read)
+    for s in subs:
+        assert all(o in big for o in s)
+
+
+def test_linear_weights():
+    g = weno.linear_weights(0.0025, 8)
+    assert g.size == 9 and abs(g.sum() - 1.0) < 1e-15 and abs(g[0] - 0.98) < 1e-15
+
+
+@pytest.mark.parametrize("deformed", [False, True])
+def test_quadratic_exactness(deformed):
+    rng = np.random.default_rng(20 + deformed)
+    vp = box(7, 0.3)
+    if deformed:
+        vp = vp + 0.04 * rng.uniform(-1, 1, size=vp.shape)
+    c0, lin = rng.standard_normal(), rng.standard_normal(3)
+    Qm = rng.standard_normal((3, 3))
+    Qm = 0.5 * (Qm + Qm.T)
+
+    def f(x):
+        return c0 + np.einsum("d,d...->...", lin, x) + np.einsum("de,d...,e...->...", Qm, x, x)
+
+    rec = build(vp, lambda xq, wj, V, c: np.stack([(f(xq) * wj).sum(axis=0) / V + k for k in range(5)]))
+    idx = centre(rec)
+    x = rec["c"][:, idx] + 0.1 * rng.standard_normal(3)
+    sel = weno.select(rec, np.array([[idx]]))
+    vals, grads = weno.eval_polys(sel, x[:, None, None])
+    assert vals.shape[0] == 9
+    assert abs(vals[0, 0, 0, 0] - f(x)) < 1e-12
+    e = 1e-3
+    g = np.array([(f(x + e * np.eye(3)[d]) - f(x - e * np.eye(3)[d])) / (2 * e) for d in range(3)])
+    assert np.allclose(grads[0, :, 0, 0, 0], g, atol=1e-9)
+
+
+def test_linear_data_gives_linear_weights_and_exact_value():
+    rng = np.random.default_rng(23)
+    vp = box(7, 0.2) + 0.03 * rng.uniform(-1, 1, size=box(7, 0.2).shape)
+    lin = rng.standard_normal(3)
+    rec = build(vp, lambda xq, wj, V, c: np.stack([((2.0 + np.einsum("d,d...->...", lin, xq)) * wj).sum(0) / V] * 5))
+    idx = centre(rec)
+    beta = rec["beta"][:, 0, idx]
+    assert np.allclose(beta, beta[0], rtol=1e-12)
+    assert np.allclose(rec["wbar"][:, 0, idx], weno.linear_weights(0.0025, 8), rtol=1e-10)
+    x = rec["c"][:, idx] + 0.05
+    sel = weno.select(rec, np.array([[idx]]))
+    vals, grads = weno.eval_polys(sel, x[:, None, None])
+    val, grad = weno.combine(sel, vals, grads)
+    assert abs(val[0, 0, 0] - (2.0 + lin @ x)) < 1e-13
+    assert np.allclose(grad[:, 0, 0, 0], lin, atol=1e-12)
+
+
+def test_closed_forms_on_unit_cubes():
+    rng = np.random.default_rng(24)
+    data = rng.standard_normal((5, 7, 7, 7))
+    rec = build(box(7, 1.0), lambda xq, wj, V, c: data)
+    idx = centre(rec)
+    Qc = data[:, 3, 3, 3]
+    d = {o: data[:, 3 + o[0], 3 + o[1], 3 + o[2]] - Qc for o in weno.BIG_OFFSETS_WIDE}
+    a = rec["a"][idx]
+    for ax in range(3):
+        assert np.allclose(a[ax], sum(o[ax] * d[o] for o in d) / 18.0, atol=1e-13)
+    r = [sum(o[ax] ** 2 * d[o] for o in d) for ax in range(3)]
+    for ax in range(3):
+        assert np.allclose(a[3 + ax], (r[ax] - 2.0 / 25.0 * sum(r)) / 38.0, atol=1e-13)
+    for k, (p, q) in enumerate(((0, 1), (1, 2), (0, 2))):
+        assert np.allclose(a[6 + k], sum(o[p] * o[q] * d[o] for o in d) / 4.0, atol=1e-13)
+    beta0 = (a[:3] ** 2).sum(0) + 13.0 / 3.0 * (a[3:6] ** 2).sum(0) + 7.0 / 6.0 * (a[6:] ** 2).sum(0)
+    assert np.allclose(rec["beta"][0, :, idx], beta0, rtol=1e-12)
+    for m, offs in enumerate(weno.SUB_OFFSETS_WIDE):
+        b = rec["b"][idx, m]
+        for ax, o in enumerate(offs):
+            assert np.allclose(b[ax], o[ax] * d[o], atol=1e-13)
+        assert np.allclose(rec["beta"][1 + m, :, idx], (b ** 2).sum(0), rtol=1e-12)
+
+
+def test_hand_worked_step():
+    data = np.zeros((5, 7, 7, 7))
+    data[:, 4:, :, :] = 1.0
+    rec = build(box(7, 1.0), lambda xq, wj, V, c: data)
+    idx = centre(rec)
+    a = rec["a"][idx][:, 0]
+    assert abs(a[0] - 7.0 / 18.0) < 1e-14 and abs(a[1]) < 1e-14 and abs(a[2]) < 1e-14
+    assert abs(a[3] - 199.0 / 950.0) < 1e-14
+    assert abs(a[4] - 12.0 / 475.0) < 1e-14 and abs(a[5] - 12.0 / 475.0) < 1e-14
+    assert np.abs(a[6:]).max() < 1e-14
+    beta = rec["beta"][:, 0, idx]
+    assert sorted(np.round(beta[1:], 12)) == [0.0] * 4 + [1.0] * 4
+    b0 = (7.0 / 18.0) ** 2 + 13.0 / 3.0 * ((199.0 / 950.0) ** 2 + 2 * (12.0 / 475.0) ** 2)
+    assert abs(beta[0] - b0) < 1e-13
+    assert abs(rec["tau"][0, idx] - (4 * abs(b0 - 1.0) + 4 * b0) / 8.0) < 1e-13
+
+
+def test_scheme_with_wide_stencil():
+    """A whole step with S': a uniform state stays uniform, a periodic
+    random state conserves its totals, and the result differs from the
+    stencil of Sec. 2 (the option is not a no-op)."""
+    import oracle
+    rng = np.random.default_rng(25)
+    n = (7, 6, 5)
+    shp = n[::-1]
+    rho = 1 + 0.3 * rng.random(shp)
+    V = 0.4 * rng.normal(size=(3,) + shp)
+    p = 1 + 0.3 * rng.random(shp)
+    Q = np.concatenate([rho[None], rho * V, (p / 0.4 + 0.5 * rho * (V ** 2).sum(0))[None]])
+    out = {}
+    for st in ("S", W):
+        prob = oracle.uniform_problem(n, (0, 0, 0), (1.0, 0.9, 0.8), params=oracle.Params(stencil=st))
+        out[st] = oracle.step(prob, Q, 0.01)
+        t0, t1 = oracle.totals(prob, Q), oracle.totals(prob, out[st])
+        assert np.abs(t1 - t0).max() < 1e-14 * np.abs(t0).max()
+        U = np.broadcast_to(np.array([1.2, 1.0, 0.3, -0.2, 3.5])[:, None, None, None], Q.shape).copy()
+        assert np.abs(oracle.step(prob, U, 0.01) - U).max() < 1e-14
+    assert np.abs(out[W] - out["S"]).max() > 1e-5
+    # outflow and symmetric ends reach two cells past the ghost layer
+    prob = oracle.uniform_problem(n, (0, 0, 0), (1.0, 0.9, 0.8), bc=(("symmetric", "outflow"), "outflow", "periodic"),
+                                  params=oracle.Params(stencil=W))
+    assert np.isfinite(oracle.step(prob, Q, 0.01)).all()
