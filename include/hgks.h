@@ -109,6 +109,14 @@ typedef struct {
                              velocity is added to the energy flux (Sec. 4
                              gives Pr = 0.71).  Both on box grids only, not
                              in batches                                      */
+  int32_t stencil;        /* 0 (default): the big stencil S and 24
+                             sub-stencils of Sec. 2; 1: the alternative of
+                             Remark 1 (S plus the cells two steps away along
+                             the axes, 8 octant sub-stencils, linear weights
+                             1 - 8 Gamma and Gamma).  Box grids,
+                             component-wise reconstruction, not in batches;
+                             a symmetric end needs at least 3 cells on its
+                             axis                                            */
 } hgks_config;
 
 /* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,

@@ -214,8 +214,9 @@ __device__ __forceinline__ int rec_index(const BoxGrid& G, int ax, int i) {
 }
 
 // ---------------------------------------------------------------- recon
-// Reconstruction of reconstruction-box cell idx (< NR).
-template <typename TC>
+// Reconstruction of reconstruction-box cell idx (< NR).  WIDE: the
+// stencils of Remark 1 (the big stencil reaches two cells along the axes).
+template <typename TC, bool WIDE = false>
 __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC* __restrict__ coef,
                                                uint32_t* __restrict__ mask, const BoxGrid& G,
                                                const WenoParams<TC>& P, TC margin, TC gm1, size_t NR, size_t idx) {
@@ -229,6 +230,17 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
     ix[o] = bc_index(G, 0, i + o - 1, sx[o]);
     iy[o] = bc_index(G, 1, j + o - 1, sy[o]);
     iz[o] = bc_index(G, 2, k + o - 1, sz[o]);
+  }
+  // cells two steps away along each axis (wide stencil only)
+  int fx[2] = {0, 0}, fy[2] = {0, 0}, fz[2] = {0, 0};
+  double gx[2] = {1.0, 1.0}, gy[2] = {1.0, 1.0}, gz[2] = {1.0, 1.0};
+  if constexpr (WIDE) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      fx[t] = bc_index(G, 0, i + 4 * t - 2, gx[t]);
+      fy[t] = bc_index(G, 1, j + 4 * t - 2, gy[t]);
+      fz[t] = bc_index(G, 2, k + 4 * t - 2, gz[t]);
+    }
   }
   const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
   TC qc[5], bnd[5];
@@ -257,7 +269,23 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
           }
         }
     BoxRecon<TC> r;
-    weno_box(d, P, r);
+    if constexpr (WIDE) {
+      // far cells: (-2x, +2x, -2y, +2y, -2z, +2z); a mirror flips the
+      // momentum along its own axis
+      TC f[6];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double s0 = v == 1 ? gx[t] : (v == 2 ? sy[1] : (v == 3 ? sz[1] : 1.0));
+        const double s1 = v == 1 ? sx[1] : (v == 2 ? gy[t] : (v == 3 ? sz[1] : 1.0));
+        const double s2 = v == 1 ? sx[1] : (v == 2 ? sy[1] : (v == 3 ? gz[t] : 1.0));
+        f[t] = TC(s0 * qv[iz[1] * nxy + iy[1] * nx + fx[t]] - c);
+        f[2 + t] = TC(s1 * qv[iz[1] * nxy + fy[t] * nx + ix[1]] - c);
+        f[4 + t] = TC(s2 * qv[fz[t] * nxy + iy[1] * nx + ix[1]] - c);
+      }
+      weno_box_wide(d, f, P, r);
+    } else {
+      weno_box(d, P, r);
+    }
     TC* cv = coef + coef_cell<TC>(idx) + v * 10 * kCB<TC>;
     cv[0] = TC(c);
 #pragma unroll
@@ -287,7 +315,7 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
   mask[idx] = safe ? 0u : kNeedsCheck;
 }
 
-template <typename TC>
+template <typename TC, bool WIDE = false>
 __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__ q, TC* __restrict__ coef,
                                                       uint32_t* __restrict__ mask, BoxGrid G,
                                                       WenoParams<TC> P, TC margin, TC gm1, size_t NR,
@@ -296,12 +324,13 @@ __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__
   if (b >= nblk) return;
   const size_t idx = (size_t)b * kBlock + threadIdx.x;
   if (idx >= NR) return;
-  recon_box_cell(q, coef, mask, G, P, margin, gm1, NR, idx);
+  recon_box_cell<TC, WIDE>(q, coef, mask, G, P, margin, gm1, NR, idx);
 }
 
 // Exact fallback test (Sec. 4): for every Gauss point of the cell, any of
-// the 25 polynomials with rho <= 0 or p < 0 marks the point.
-template <typename TC>
+// the 25 polynomials (9 with the stencils of Remark 1) with rho <= 0 or
+// p < 0 marks the point.
+template <typename TC, bool WIDE = false>
 __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ q, uint32_t* __restrict__ mask,
                                                      const BoxGrid& G, TC gm1, size_t idx) {
   int ri, rj, rk;
@@ -312,50 +341,33 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
     double s[3];
     const int a = bc_index(G, 0, i + ox, s[0]), bb = bc_index(G, 1, j + oy, s[1]), c = bc_index(G, 2, k + oz, s[2]);
     const double val = q[v * N + c * nxy + bb * nx + a];
-    return (v >= 1 && v <= 3) ? s[v - 1] * val : val;
+    return v == 1 ? s[0] * val : (v == 2 ? s[1] * val : (v == 3 ? s[2] * val : val));
   };
-  uint32_t bits = 0;
-  for (int m = 0; m < 25; ++m) {
-    TC qc[5], cf[5][9];
-    for (int v = 0; v < 5; ++v) {
-      const double c = at(v, 0, 0, 0);
-      qc[v] = TC(c);
-      for (int t = 0; t < 9; ++t) cf[v][t] = TC(0);
-      if (m == 0) {
-        TC d[27];
-        for (int oz = -1; oz <= 1; ++oz)
-          for (int oy = -1; oy <= 1; ++oy)
-            for (int ox = -1; ox <= 1; ++ox) {
-              const int nz = (ox != 0) + (oy != 0) + (oz != 0);
-              d[sidx(ox, oy, oz)] = (nz == 0 || nz == 3) ? TC(0) : TC(at(v, ox, oy, oz) - c);
-            }
-        big_quadratic(d, cf[v]);
-      } else {
-        const int mm = m - 1, t = mm / 8, r = mm % 8;
-        const int ic = r / 4, ib = (r / 2) % 2, ia = r % 2;
-        const int ea = t, eb = (t + 1) % 3, ec = (t + 2) % 3;
-        const int sa = ia ? -1 : 1, sb = ib ? -1 : 1, sc = ic ? -1 : 1;
-        int oa[3] = {0, 0, 0}, ob[3] = {0, 0, 0}, oc[3] = {0, 0, 0};
-        oa[ea] = sa; ob[eb] = sb; oc[ec] = sc;
-        const TC da = TC(at(v, oa[0], oa[1], oa[2]) - c);
-        const TC db = TC(at(v, ob[0], ob[1], ob[2]) - c);
-        const TC dab = TC(at(v, oa[0] + ob[0], oa[1] + ob[1], oa[2] + ob[2]) - c);
-        const TC dc = TC(at(v, oc[0], oc[1], oc[2]) - c);
-        cf[v][ec] = TC(sc) * dc;
-        cf[v][ea] = TC(sa) * (TC(2) * da - db + dab) * TC(1.0 / 3.0);
-        cf[v][eb] = TC(sb) * (TC(2) * db - da + dab) * TC(1.0 / 3.0);
-      }
-    }
-    for (int bit = 0; bit < 24; ++bit) {
-      const int f = bit >> 2, gp = bit & 3, d = f >> 1;
-      TC xi[3];
-      xi[d] = (f & 1) ? TC(0.5) : TC(-0.5);
-      xi[(d + 1) % 3] = (gp >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
-      xi[(d + 2) % 3] = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
+  TC qc[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qc[v] = TC(at(v, 0, 0, 0));
+  // Values at the 24 points of one polynomial per variable (coefficients in
+  // registers, indices fixed after unrolling), then the test.
+  auto test = [&](const TC (&cf)[5][9]) -> uint32_t {
+    uint32_t bits = 0;
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      const TC xs = (f & 1) ? TC(0.5) : TC(-0.5);
+#pragma unroll
+      for (int gp = 0; gp < 4; ++gp) {
+      const int bit = 4 * f + gp;
+      // the face axis d takes xs, axes d+1 and d+2 (cyclic) the Gauss nodes
+      const TC pa = (gp >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
+      const TC pb = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
+      const TC x0 = d == 0 ? xs : (d == 2 ? pa : pb);
+      const TC x1 = d == 1 ? xs : (d == 0 ? pa : pb);
+      const TC x2 = d == 2 ? xs : (d == 1 ? pa : pb);
       TC val[5];
+#pragma unroll
       for (int v = 0; v < 5; ++v) {
         TC gx, gy, gz;
-        quad_eval(qc[v], cf[v], xi[0], xi[1], xi[2], val[v], gx, gy, gz);
+        quad_eval(qc[v], cf[v], x0, x1, x2, val[v], gx, gy, gz);
       }
       bool bad = !(val[0] > TC(0));
       if (!bad) {
@@ -363,18 +375,90 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
         bad = p < TC(0);
       }
       if (bad) bits |= 1u << bit;
+      }
     }
+    return bits;
+  };
+  uint32_t bits = 0;
+  {
+    // P_0 from the big stencil
+    TC cf[5][9];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double c = at(v, 0, 0, 0);
+      TC d[27];
+#pragma unroll
+      for (int oz = -1; oz <= 1; ++oz)
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+          for (int ox = -1; ox <= 1; ++ox) {
+            const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+            d[sidx(ox, oy, oz)] = (nz == 0 || nz == 3) ? TC(0) : TC(at(v, ox, oy, oz) - c);
+          }
+      if constexpr (WIDE) {
+        const TC f[6] = {TC(at(v, -2, 0, 0) - c), TC(at(v, 2, 0, 0) - c), TC(at(v, 0, -2, 0) - c),
+                         TC(at(v, 0, 2, 0) - c), TC(at(v, 0, 0, -2) - c), TC(at(v, 0, 0, 2) - c)};
+        big_quadratic_wide(d, f, cf[v]);
+      } else {
+        big_quadratic(d, cf[v]);
+      }
+      // one variable's stencil in registers at a time
+      asm volatile("" ::: "memory");
+    }
+    bits |= test(cf);
+  }
+  // the linear sub-stencil polynomials, one at a time
+  constexpr int nsub = WIDE ? 8 : 24;
+  for (int m = 0; m < nsub; ++m) {
+    TC cf[5][9];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double c = at(v, 0, 0, 0);
+#pragma unroll
+      for (int t = 3; t < 9; ++t) cf[v][t] = TC(0);
+      TC b[3];
+      if constexpr (WIDE) {
+        const int sx = (m & 1) ? -1 : 1, sy = (m & 2) ? -1 : 1, sz = (m & 4) ? -1 : 1;
+        b[0] = TC(sx) * TC(at(v, sx, 0, 0) - c);
+        b[1] = TC(sy) * TC(at(v, 0, sy, 0) - c);
+        b[2] = TC(sz) * TC(at(v, 0, 0, sz) - c);
+      } else {
+        const int t = m / 8, r = m % 8;
+        const int sa = (r & 1) ? -1 : 1, sb = (r & 2) ? -1 : 1, sc = (r & 4) ? -1 : 1;
+        // axis triple (a, b; c) = (t, t+1; t+2) cyclic; offsets as (x, y, z)
+        const int ea = t, eb = t == 2 ? 0 : t + 1, ec = t == 0 ? 2 : t - 1;
+        const int oa[3] = {ea == 0 ? sa : 0, ea == 1 ? sa : 0, ea == 2 ? sa : 0};
+        const int ob[3] = {eb == 0 ? sb : 0, eb == 1 ? sb : 0, eb == 2 ? sb : 0};
+        const int oc[3] = {ec == 0 ? sc : 0, ec == 1 ? sc : 0, ec == 2 ? sc : 0};
+        const TC da = TC(at(v, oa[0], oa[1], oa[2]) - c);
+        const TC db = TC(at(v, ob[0], ob[1], ob[2]) - c);
+        const TC dab = TC(at(v, oa[0] + ob[0], oa[1] + ob[1], oa[2] + ob[2]) - c);
+        const TC dc = TC(at(v, oc[0], oc[1], oc[2]) - c);
+        const TC ba = TC(sa) * (TC(2) * da - db + dab) * TC(1.0 / 3.0);
+        const TC bb = TC(sb) * (TC(2) * db - da + dab) * TC(1.0 / 3.0);
+        const TC bc = TC(sc) * dc;
+        // slope along x, y, z by selects (the axis of each is uniform)
+        b[0] = ea == 0 ? ba : (eb == 0 ? bb : bc);
+        b[1] = ea == 1 ? ba : (eb == 1 ? bb : bc);
+        b[2] = ea == 2 ? ba : (eb == 2 ? bb : bc);
+      }
+      cf[v][0] = b[0];
+      cf[v][1] = b[1];
+      cf[v][2] = b[2];
+    }
+    bits |= test(cf);
   }
   mask[idx] = bits;
 }
 
-template <typename TC>
+template <typename TC, bool WIDE = false>
 __global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __restrict__ q, uint32_t* __restrict__ mask,
                                                             BoxGrid G, TC gm1, size_t NR) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= NR) return;
   if (mask[idx] != kNeedsCheck) return;
-  posit_exact_box_cell(q, mask, G, gm1, idx);
+  posit_exact_box_cell<TC, WIDE>(q, mask, G, gm1, idx);
 }
 
 // ---------------------------------------------------------------- flux

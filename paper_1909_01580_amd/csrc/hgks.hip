@@ -71,6 +71,15 @@ bool valid_config(const hgks_config* c) {
     return false;
   // the viscosity law and the Prandtl correction are offered on box grids
   if (c->moving && (c->mu_exponent != 0.0 || c->prandtl != 1.0)) return false;
+  // the stencils of Remark 1: box grids, component-wise reconstruction; a
+  // mirror two cells past the ghost layer needs three cells on that axis
+  if (c->stencil != 0 && c->stencil != 1) return false;
+  if (c->stencil && (c->moving || c->characteristic || !(c->weno_Gamma < 1.0 / 24.0))) return false;
+  if (c->stencil) {
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int d = 0; d < 3; ++d)
+      if ((c->bc[d] == HGKS_BC_SYMMETRIC || bc_high(c, d) == HGKS_BC_SYMMETRIC) && n[d] < 3) return false;
+  }
   if (c->moving)
     for (int d = 0; d < 3; ++d)
       if (c->bc[d] != HGKS_BC_PERIODIC) return false;
@@ -206,7 +215,8 @@ hgks_status usable(hgks_ctx c) {
 template <typename T>
 WenoParams<T> weno_params(const hgks_config& cfg, const double dx[3]) {
   WenoParams<T> P;
-  P.gamma0 = T(1.0 - 24.0 * cfg.weno_Gamma);
+  // 24 sub-stencils (Sec. 2) or 8 (Remark 1)
+  P.gamma0 = T(1.0 - (cfg.stencil ? 8.0 : 24.0) * cfg.weno_Gamma);
   P.Gamma = T(cfg.weno_Gamma);
   P.eps = T(cfg.weno_eps);
   const double h = std::cbrt(dx[0] * dx[1] * dx[2]);
@@ -261,13 +271,21 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
   {
     const unsigned nb = blocks_for(D.NR);
     prof_mark(c, HGKS_PHASE_RECON, true);
-    hipLaunchKernelGGL((k_recon_box<TC>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(), c->G, P,
-                       margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
+    if (c->cfg.stencil)
+      hipLaunchKernelGGL((k_recon_box<TC, true>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(),
+                         c->G, P, margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
+    else
+      hipLaunchKernelGGL((k_recon_box<TC, false>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(),
+                         c->G, P, margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
     prof_mark(c, HGKS_PHASE_RECON, false);
     if (hgks_status s = launched(c, "recon")) return s;
     prof_mark(c, HGKS_PHASE_FALLBACK, true);
-    hipLaunchKernelGGL((k_posit_exact_box<TC>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
-                       TC(c->cfg.gamma - 1.0), D.NR);
+    if (c->cfg.stencil)
+      hipLaunchKernelGGL((k_posit_exact_box<TC, true>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+                         TC(c->cfg.gamma - 1.0), D.NR);
+    else
+      hipLaunchKernelGGL((k_posit_exact_box<TC, false>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+                         TC(c->cfg.gamma - 1.0), D.NR);
     prof_mark(c, HGKS_PHASE_FALLBACK, false);
     if (hgks_status s = launched(c, "positivity")) return s;
     if (c->cfg.characteristic) {
@@ -786,7 +804,8 @@ hgks_status busable(hgks_batch b) {
 }
 
 bool batch_compatible(const hgks_config& a, const hgks_config& c) {
-  if (!valid_config(&c) || c.moving || c.characteristic || c.mu_exponent != 0.0 || c.prandtl != 1.0) return false;
+  if (!valid_config(&c) || c.moving || c.characteristic || c.mu_exponent != 0.0 || c.prandtl != 1.0 || c.stencil)
+    return false;
   for (int d = 0; d < 3; ++d)
     if (c.bc[d] != HGKS_BC_PERIODIC) return false;
   return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&

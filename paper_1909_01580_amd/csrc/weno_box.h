@@ -194,6 +194,127 @@ HGKS_FN void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out
   out.bound = bnd;
 }
 
+// The alternative of Remark 1: big stencil S' = S plus the six cells two
+// steps away along the axes (far differences f, order -2x, +2x, -2y, +2y,
+// -2z, +2z), sub-stencils S'_m = the centre and one face neighbour per axis,
+// one per sign octant (s_x, s_y, s_z).  Closed forms on the unit cube:
+//   a_d  = (1/18) sum_{o in S'} o_d d_o
+//   a_de = (1/4)  sum o_d o_e d_o                          (as for S)
+//   a_dd = (r_d - (2/25)(r_x + r_y + r_z)) / 38,  r_d = sum o_d^2 d_o
+// (the 24x9 normal equations: diagonal 18 for the linear terms, 4 for the
+// mixed ones, 38 I + 4 (1 1^T) for the squares); each sub-stencil is
+// interpolated, b_d = s_d d_{s_d e_d}.  Linear weights 1 - 8 Gamma and
+// Gamma, tau the mean over the eight sub-stencils.
+template <typename T>
+HGKS_FN void big_quadratic_wide(const T (&d)[27], const T (&f)[6], T (&a)[9]) {
+  T r[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    T s = T(0), rr = T(0);
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+      int o[3] = {0, 0, 0};
+      o[ax] = sg;
+      T acc = d[sidx3(o)];
+#pragma unroll
+      for (int oth = 1; oth <= 2; ++oth) {
+        const int e = (ax + oth) % 3;
+#pragma unroll
+        for (int se = -1; se <= 1; se += 2) {
+          int oo[3] = {0, 0, 0};
+          oo[ax] = sg;
+          oo[e] = se;
+          acc += d[sidx3(oo)];
+        }
+      }
+      const T far = f[2 * ax + (sg > 0 ? 1 : 0)];
+      s += T(sg) * (acc + T(2) * far);
+      rr += acc + T(4) * far;
+    }
+    a[ax] = s * T(1.0 / 18.0);
+    r[ax] = rr;
+  }
+  const T rs = T(2.0 / 25.0) * (r[0] + r[1] + r[2]);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) a[3 + ax] = (r[ax] - rs) * T(1.0 / 38.0);
+  const int pd[3] = {0, 1, 0}, pe[3] = {1, 2, 2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T s = T(0);
+#pragma unroll
+    for (int s1 = -1; s1 <= 1; s1 += 2)
+#pragma unroll
+      for (int s2 = -1; s2 <= 1; s2 += 2) {
+        int o[3] = {0, 0, 0};
+        o[pd[k]] = s1;
+        o[pe[k]] = s2;
+        s += T(s1 * s2) * d[sidx3(o)];
+      }
+    a[6 + k] = T(0.25) * s;
+  }
+}
+
+// Slopes of the octant sub-stencil m = 4 iz + 2 iy + ix (sign - for a set
+// bit), in the order of the printed S'_1..S'_8 read as x fastest.
+template <typename T>
+HGKS_FN void octant_slopes(const T (&d)[27], int m, T (&b)[3]) {
+  const int sx = (m & 1) ? -1 : 1, sy = (m & 2) ? -1 : 1, sz = (m & 4) ? -1 : 1;
+  b[0] = T(sx) * d[sidx(sx, 0, 0)];
+  b[1] = T(sy) * d[sidx(0, sy, 0)];
+  b[2] = T(sz) * d[sidx(0, 0, sz)];
+}
+
+template <typename T>
+HGKS_FN void weno_box_wide(const T (&d)[27], const T (&f)[6], const WenoParams<T>& P, BoxRecon<T>& out) {
+  T a[9];
+  big_quadratic_wide(d, f, a);
+  const T beta0 = P.kl[0] * a[0] * a[0] + P.kl[1] * a[1] * a[1] + P.kl[2] * a[2] * a[2] +
+                  P.kq[0] * a[3] * a[3] + P.kq[1] * a[4] * a[4] + P.kq[2] * a[5] * a[5] +
+                  P.km[0] * a[6] * a[6] + P.km[1] * a[7] * a[7] + P.km[2] * a[8] * a[8];
+  T beta[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    T b[3];
+    octant_slopes(d, m, b);
+    beta[m] = P.kl[0] * b[0] * b[0] + P.kl[1] * b[1] * b[1] + P.kl[2] * b[2] * b[2];
+  }
+  T tau = T(0);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) tau += d_abs(beta0 - beta[m]);
+  tau *= T(1.0 / 8.0);
+  const T w0r = T(1) + tau * d_rcp(beta0 + P.eps);
+  T wsum = P.gamma0 * w0r;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    beta[m] = P.Gamma * (T(1) + tau * d_rcp(beta[m] + P.eps));
+    wsum += beta[m];
+  }
+  const T iw = d_rcp(wsum);
+  const T w0g = w0r * iw;
+  const T off = w0g * P.Gamma;
+  T cl[3] = {w0g * a[0], w0g * a[1], w0g * a[2]};
+  T bnd = T(0.5) * (d_abs(a[0]) + d_abs(a[1]) + d_abs(a[2])) +
+          T(1.0 / 6.0) * (d_abs(a[3]) + d_abs(a[4]) + d_abs(a[5])) +
+          T(0.14433756729740644113) * (d_abs(a[6]) + d_abs(a[7]) + d_abs(a[8]));
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    T b[3];
+    octant_slopes(d, m, b);
+    const T cm = beta[m] * iw - off;
+    cl[0] += cm * b[0];
+    cl[1] += cm * b[1];
+    cl[2] += cm * b[2];
+    const T bm = T(0.5) * (d_abs(b[0]) + d_abs(b[1]) + d_abs(b[2]));
+    bnd = bnd > bm ? bnd : bm;
+  }
+  out.c[0] = cl[0];
+  out.c[1] = cl[1];
+  out.c[2] = cl[2];
+#pragma unroll
+  for (int k = 3; k < 9; ++k) out.c[k] = w0g * a[k];
+  out.bound = bnd;
+}
+
 // Value and unit-cube gradient of a quadratic with coefficients c (order x,
 // y, z, xx, yy, zz, xy, yz, xz) about the cell mean q at xi.
 template <typename T>

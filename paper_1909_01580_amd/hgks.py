@@ -21,6 +21,7 @@ HGKS_OK, HGKS_EINVAL, HGKS_ENOMEM, HGKS_EDEVICE, HGKS_ESTATE, HGKS_ENONPHYS, HGK
 BC = {"same": -1, "periodic": 0, "outflow": 1, "symmetric": 2}
 PREC = {"fp64": 0, "mixed": 1}
 
+STENCIL = {"S": 0, "S_prime": 1}
 EXPORTS = [
     "hgks_default_config", "hgks_workspace_size", "hgks_create", "hgks_destroy",
     "hgks_set_uniform_grid", "hgks_set_vertices", "hgks_set_next_vertices",
@@ -47,6 +48,7 @@ class hgks_config(ctypes.Structure):
         ("bc_hi", ctypes.c_int32 * 3),
         ("characteristic", ctypes.c_int32),
         ("mu_T0", ctypes.c_double), ("mu_exponent", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("stencil", ctypes.c_int32),
     ]
 
 
@@ -236,7 +238,8 @@ class Context:
 
     def __init__(self, n, bc=("periodic",) * 3, gamma=1.4, mu=0.0, weno_Gamma=0.0025,
                  weno_eps=1e-8, tau_eps=0.01, tau_C=1.0, precision="fp64", moving=False,
-                 characteristic=False, mu_T0=1.0, mu_exponent=0.0, prandtl=1.0, device="cuda:0", stream=None):
+                 characteristic=False, mu_T0=1.0, mu_exponent=0.0, prandtl=1.0, stencil="S", device="cuda:0",
+                 stream=None):
         self.n = tuple(int(x) for x in n)
         self.device = torch.device(device)
         cfg = hgks_default_config(*self.n)
@@ -252,6 +255,7 @@ class Context:
         cfg.moving = 1 if moving else 0
         cfg.characteristic = 1 if characteristic else 0
         cfg.mu_T0, cfg.mu_exponent, cfg.prandtl = mu_T0, mu_exponent, prandtl
+        cfg.stencil = STENCIL[stencil]
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
