@@ -532,8 +532,9 @@ HGKS_FN void eval_box_gp_dir(int D, const TC* __restrict__ coef, size_t cell, TC
 // a face sum their weighted fluxes with lane shuffles.  Lane l of the
 // 256-lane block lb of direction D takes Gauss point l % 4 of face slot
 // l / 4 (face_of_block).
-// PR: with the Prandtl correction of the energy flux.
-template <typename TC, bool PR = false>
+// PR: the extended viscous model (viscosity law, Prandtl correction); FS:
+// per-face coefficient arrays (characteristic reconstruction).
+template <typename TC, bool PR = false, bool FS = false>
 __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
                                               TC dt, TC idt, unsigned lb, int D) {
@@ -558,8 +559,8 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
 
   // the left cell's quadratic for its high face, the right cell's for its
   // low face (the same array unless the faces have their own)
-  const TC* coefL = coef + (size_t)(2 * D + 1) * G.fs_stride;
-  const TC* coefR = coef + (size_t)(2 * D) * G.fs_stride;
+  const TC* coefL = FS ? coef + (size_t)(2 * D + 1) * G.fs_stride : coef;
+  const TC* coefR = FS ? coef + (size_t)(2 * D) * G.fs_stride : coef;
   FluxAcc<TC> acc;
   acc_zero(acc);
   {
@@ -620,7 +621,7 @@ HGKS_FN void flux_block(unsigned b, const unsigned (&nb)[3], int& D, unsigned& l
 }
 
 // All faces of the three directions in one launch (see flux_block).
-template <typename TC, bool PR = false>
+template <typename TC, bool PR = false, bool FS = false>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
     const TC* __restrict__ coef, const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy,
     TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, unsigned nb0, unsigned nb1, unsigned nb2) {
@@ -631,7 +632,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
   unsigned lb;
   flux_block(b, nb, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
-  flux_box_face<TC, PR>(coef, mask, face, G, gp, dt, idt, lb, D);
+  flux_box_face<TC, PR, FS>(coef, mask, face, G, gp, dt, idt, lb, D);
 }
 
 // ---------------------------------------------------------------- update

@@ -357,6 +357,8 @@ HGKS_FN void time_integrals(T delta, T tau, T itau, T (&Tc)[5]) {
 // conservative variables of g_0.  The collision time and the coefficients
 // of the time fit come first, so that every moment is folded into F and dF
 // as soon as it is formed.
+// PR: the extended viscous model -- the viscosity law and the Prandtl
+// correction (either may be trivial: mu_exp = 0, pr_fix = 0).
 template <bool PR = false, typename T>
 HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&F)[5], T (&dF)[5]) {
   Prim<T> P;
@@ -367,7 +369,9 @@ HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&
   // mu / p_0 = mu (rho_0 / p_0) (1 / rho_0); mu = mu0 (T / T0)^omega with
   // T = p_0 / rho_0 when a viscosity law is set
   T mu = g.mu;
-  if (g.mu_exp != T(0)) mu *= exp(g.mu_exp * log(P.h * g.mu_iT0));
+  if constexpr (PR) {
+    if (g.mu_exp != T(0)) mu *= exp(g.mu_exp * log(P.h * g.mu_iT0));
+  }
   const T tau = g.viscous ? mu * il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
   const T itau = T(1) / tau;
   T c[5], d[5];

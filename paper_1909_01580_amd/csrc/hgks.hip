@@ -302,12 +302,20 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
   const dim3 grid(pad8(nb[0] + nb[1] + nb[2]));
   const TC* fc = face_coef<TC>(c);
   TC* f[3] = {(TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2)};
-  if (c->cfg.prandtl != 1.0)
-    hipLaunchKernelGGL((k_flux_box<TC, true>), grid, dim3(kBlock), 0, c->stream, fc, c->mask(), f[0], f[1], f[2],
-                       c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2]);
+  // compile-time variants: the extended viscous model and per-face arrays
+  const bool ext = c->cfg.prandtl != 1.0 || c->cfg.mu_exponent != 0.0, fs = c->cfg.characteristic != 0;
+#define HGKS_FLUX_LAUNCH(E, F)                                                                                   \
+  hipLaunchKernelGGL((k_flux_box<TC, E, F>), grid, dim3(kBlock), 0, c->stream, fc, c->mask(), f[0], f[1], f[2], \
+                     c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2])
+  if (ext && fs)
+    HGKS_FLUX_LAUNCH(true, true);
+  else if (ext)
+    HGKS_FLUX_LAUNCH(true, false);
+  else if (fs)
+    HGKS_FLUX_LAUNCH(false, true);
   else
-    hipLaunchKernelGGL((k_flux_box<TC, false>), grid, dim3(kBlock), 0, c->stream, fc, c->mask(), f[0], f[1], f[2],
-                       c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2]);
+    HGKS_FLUX_LAUNCH(false, false);
+#undef HGKS_FLUX_LAUNCH
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
