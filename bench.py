@@ -2,8 +2,9 @@
 
 One step = one two-stage fourth-order time step of the whole hot path
 (WENO-AO reconstruction, gas-kinetic face flux, stage update) over the
-128^3 periodic grid on [-pi, pi]^3 (Re 1600, Ma 0.1), including the
-per-step time-step reduction.  The FP64 path gives ``value``; the mixed
+128^3 periodic grid on [-pi, pi]^3 (Re 1600, Ma 0.1, Prandtl number 0.72
+through the heat-flux correction), including the per-step time-step
+reduction.  The FP64 path gives ``value``; the mixed
 path (FP32 reconstruction and flux, FP64 accumulation) is reported beside
 it with its error against the FP64 result.
 
@@ -67,7 +68,8 @@ def run_gpu(n, steps, warmup, precision, cfl=0.35, record_first=False, character
     from paper_1909_01580_amd import workloads as wl
 
     q0 = torch.tensor(wl.tgv_state(n), device="cuda:0")
-    ctx = hgks.Context((n, n, n), mu=wl.TGV_MU, precision=precision, characteristic=characteristic, stencil=stencil)
+    ctx = hgks.Context((n, n, n), mu=wl.TGV_MU, precision=precision, characteristic=characteristic, stencil=stencil,
+                       prandtl=wl.TGV_PRANDTL)
     ctx.set_uniform_grid((-np.pi,) * 3, (2 * np.pi,) * 3)
     ctx.set_state(q0)
     first = None
@@ -278,7 +280,7 @@ def sampled_oracle_error(q0, first, n):
         idx = [np.arange(c - 6, c + 7) % n for c in (i, j, k)]
         patch = q0[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
         prob = oracle.uniform_problem((13, 13, 13), (0, 0, 0), (13 * h,) * 3, bc=("outflow",) * 3,
-                                      params=oracle.Params(mu=wl.TGV_MU))
+                                      params=oracle.Params(mu=wl.TGV_MU, prandtl=wl.TGV_PRANDTL))
         ref = oracle.step(prob, patch, dt)[:, 6, 6, 6]
         got = gpu[:, k, j, i]
         scale = np.array([1.0, 1.0, 1.0, 1.0, np.abs(q0[4]).max()])
@@ -301,7 +303,7 @@ def cpu_baseline(q0, n, budget_cells=32):
     h = 2 * np.pi / n
     block = np.ascontiguousarray(q0[:, :m, :m, :m])
     prob = oracle.uniform_problem((m, m, m), (0, 0, 0), (m * h,) * 3, bc=("outflow",) * 3,
-                                  params=oracle.Params(mu=wl.TGV_MU))
+                                  params=oracle.Params(mu=wl.TGV_MU, prandtl=wl.TGV_PRANDTL))
     dt = oracle.max_dt(prob, block, 0.35)
     t0 = time.perf_counter()
     oracle.step(prob, block, dt)
@@ -360,7 +362,8 @@ def main():
     value = cells * 2 * args.steps / (head["ms"] / 1e3)
     fl_ms, fl_n = head["prof"]["flux"]
     launch_ms = fl_ms / max(fl_n, 1)
-    flops_per_launch = 12 * cells * ops["flux_gp_ops"]
+    # the Taylor-Green flux runs the Prandtl-corrected instantiation
+    flops_per_launch = 12 * cells * ops["flux_gp_ops_prandtl"]
     achieved = flops_per_launch / (launch_ms / 1e3) / 1e12
     peak = PEAK["fp64" if head_prec == "fp64" else "fp32"]
     out = {
@@ -376,12 +379,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head_prec == "fp64" else "f32 (f64 accumulation)",
         "data": "synthetic",
-        "config": {"workload": "taylor-green-vortex 128^3 periodic [-pi,pi]^3, Re 1600, Ma 0.1, "
+        "config": {"workload": "taylor-green-vortex 128^3 periodic [-pi,pi]^3, Re 1600, Ma 0.1, Pr 0.72, "
                                "gamma 1.4, CFL 0.35, two-stage steps with per-step dt reduction",
                    "cells": cells, "precision": head_prec},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(head_prec),
-                     "kernel": "k_flux_box", "launch_ms": launch_ms,
+                     "kernel": "k_flux_box<double, true, false> (Prandtl-corrected)", "launch_ms": launch_ms,
                      "ops_per_launch": flops_per_launch},
         "hbm": {"algorithmic_GBps": BYTES_PER_CELL_STAGE * value / 1e9,
                 "frac_of_8TBps": BYTES_PER_CELL_STAGE * value / 1e9 / HBM_PEAK},

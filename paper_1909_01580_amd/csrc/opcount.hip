@@ -85,6 +85,27 @@ int main() {
   const double flux_gp = (double)cnt::total() + 10.0 + 7.5;
   const long long f_add = cnt::add, f_mul = cnt::mul, f_div = cnt::dv, f_tr = cnt::tr;
 
+  // The same with the Prandtl correction (Pr 0.72, constant mu): the
+  // instantiation the Taylor-Green benchmark runs.
+  g.pr_fix = Cnt(1.0 / 0.72 - 1.0);
+  cnt::reset();
+  {
+    FluxAcc<Cnt> accp;
+    acc_zero(accp);
+    {
+      Cnt W[5], dW[3][5];
+      eval_box_gp<0>(coef, 0, Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
+      side_terms<+1, true>(W, dW, g, accp);
+    }
+    {
+      Cnt W[5], dW[3][5];
+      eval_box_gp<0>(coef, 1, Cnt(-0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
+      side_terms<-1, true>(W, dW, g, accp);
+    }
+    finish_flux<true>(accp, g, Cnt(1.5e-3), Cnt(1.0 / 1.5e-3), F, dF);
+  }
+  const double flux_gp_pr = (double)cnt::total() + 10.0 + 7.5;
+
   // Reconstruction of one cell: differences (double), five variables, and
   // the sufficient positivity test (about 20 operations).
   WenoParams<Cnt> P;
@@ -107,7 +128,7 @@ int main() {
   std::printf(
       "{\"flux_gp_ops\": %.1f, \"flux_gp_add\": %lld, \"flux_gp_mul\": %lld, \"flux_gp_div\": %lld, "
       "\"flux_gp_transcendental\": %lld, \"recon_cell_ops\": %.1f, \"recon_cell_div\": %lld, "
-      "\"update_cell_ops\": %.1f, \"gp_per_cell_stage\": 12}\n",
-      flux_gp, f_add, f_mul, f_div, f_tr, recon_cell, r_div, update_cell);
+      "\"update_cell_ops\": %.1f, \"gp_per_cell_stage\": 12, \"flux_gp_ops_prandtl\": %.1f}\n",
+      flux_gp, f_add, f_mul, f_div, f_tr, recon_cell, r_div, update_cell, flux_gp_pr);
   return 0;
 }

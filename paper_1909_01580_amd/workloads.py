@@ -84,6 +84,7 @@ def tgv_state(n, mach=0.1, gamma=GAMMA):
 
 
 TGV_MU = 1.0 / 1600.0
+TGV_PRANDTL = 0.72  # the benchmark configuration's Prandtl number (Sec. 4.6 prints 0.71)
 
 
 # ------------------------------------------------------------ explosion
