@@ -153,9 +153,15 @@ HGKS_FN bool face_of_block(const BoxGrid& G, int D, unsigned lb, unsigned slot, 
     live = e < nbnd;
     if (!live) e = nbnd - 1;
     const uint32_t q = (uint32_t)((double)e * div_inv(G.n[a0]));
-    c[a0] = (int)(e - q * (uint32_t)G.n[a0]);
-    c[a1] = (int)q;
-    c[D] = G.n[D];
+    const int u0 = (int)(e - q * (uint32_t)G.n[a0]), u1 = (int)q;
+    // constant indices in each branch (no indexed private array)
+    if (D == 0) {
+      c[0] = G.n[0]; c[1] = u0; c[2] = u1;
+    } else if (D == 1) {
+      c[0] = u0; c[1] = G.n[1]; c[2] = u1;
+    } else {
+      c[0] = u0; c[1] = u1; c[2] = G.n[2];
+    }
   }
   f = (size_t)c[0] + (size_t)G.nf[D][0] * ((size_t)c[1] + (size_t)G.nf[D][1] * c[2]);
   return live;
@@ -483,13 +489,12 @@ HGKS_FN FaceAxes face_axes(int D) {
 // from global axis (D, A, B)[j], the local mixed terms (DA, AB, DB) from
 // the global mixed terms 6 + D, 6 + A, 6 + B.  D is a template parameter
 // so that every load has a constant offset from the cell's address.
-template <int D, typename TC>
-HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t cell, TC xD, TC xA, TC xB, bool fallback,
-                         const TC (&invd)[3], TC (&W)[5], TC (&dW)[3][5]) {
-  constexpr int A = (D + 1) % 3, B = (D + 2) % 3, CB = kCB<TC>;
+template <int D, int CB, typename TC>
+HGKS_FN void eval_rows_gp(const TC* cv, TC xD, TC xA, TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
+                          TC (&dW)[3][5]) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
   constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
   constexpr int cp[9] = {D, A, B, 3 + D, 3 + A, 3 + B, 6 + D, 6 + A, 6 + B};
-  const TC* cv = coef + coef_cell<TC>(cell);
 #pragma unroll
   for (int kk = 0; kk < 5; ++kk) {
     const TC* ck = cv + lv[kk] * 10 * CB;
@@ -514,6 +519,13 @@ HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t cell, TC xD, TC xA,
       for (int j = 0; j < 3; ++j) dW[j][kk] = TC(0);
     }
   }
+}
+
+// The 50 values of a cell are rows 10 v + k, CB elements apart.
+template <int D, typename TC>
+HGKS_FN void eval_box_gp(const TC* __restrict__ coef, size_t cell, TC xD, TC xA, TC xB, bool fallback,
+                         const TC (&invd)[3], TC (&W)[5], TC (&dW)[3][5]) {
+  eval_rows_gp<D, kCB<TC>>(coef + coef_cell<TC>(cell), xD, xA, xB, fallback, invd, W, dW);
 }
 
 // eval_box_gp for a direction D that is uniform over the workgroup.
@@ -543,8 +555,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   int cR[3];
   size_t f;
   const bool live = face_of_block(G, D, lb, threadIdx.x >> 2, cR, f);
-  int cL[3] = {cR[0], cR[1], cR[2]};
-  cL[D] -= 1;
+  const int cL[3] = {cR[0] - (D == 0), cR[1] - (D == 1), cR[2] - (D == 2)};
   size_t iL = 0, iR = 0;
   {
     const size_t s1 = G.nr[0], s2 = (size_t)G.nr[0] * G.nr[1];
