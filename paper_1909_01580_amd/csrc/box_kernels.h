@@ -335,10 +335,11 @@ __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__
 
 // Exact fallback test (Sec. 4): for every Gauss point of the cell, any of
 // the 25 polynomials (9 with the stencils of Remark 1) with rho <= 0 or
-// p < 0 marks the point.
+// p < 0 marks the point.  posit_poly_bits: the 24 point bits of polynomial
+// m of cell idx (m = 0 the big stencil's, then the sub-stencils').
 template <typename TC, bool WIDE = false>
-__device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ q, uint32_t* __restrict__ mask,
-                                                     const BoxGrid& G, TC gm1, size_t idx) {
+__device__ __forceinline__ uint32_t posit_poly_bits(const double* __restrict__ q, const BoxGrid& G, TC gm1, size_t idx,
+                                                    int m) {
   int ri, rj, rk;
   split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
   const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
@@ -385,8 +386,7 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
     }
     return bits;
   };
-  uint32_t bits = 0;
-  {
+  if (m == 0) {
     // P_0 from the big stencil
     TC cf[5][9];
 #pragma unroll
@@ -412,11 +412,11 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
       // one variable's stencil in registers at a time
       asm volatile("" ::: "memory");
     }
-    bits |= test(cf);
+    return test(cf);
   }
-  // the linear sub-stencil polynomials, one at a time
-  constexpr int nsub = WIDE ? 8 : 24;
-  for (int m = 0; m < nsub; ++m) {
+  {
+    // linear sub-stencil polynomial m - 1
+    const int ms = m - 1;
     TC cf[5][9];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -425,12 +425,12 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
       for (int t = 3; t < 9; ++t) cf[v][t] = TC(0);
       TC b[3];
       if constexpr (WIDE) {
-        const int sx = (m & 1) ? -1 : 1, sy = (m & 2) ? -1 : 1, sz = (m & 4) ? -1 : 1;
+        const int sx = (ms & 1) ? -1 : 1, sy = (ms & 2) ? -1 : 1, sz = (ms & 4) ? -1 : 1;
         b[0] = TC(sx) * TC(at(v, sx, 0, 0) - c);
         b[1] = TC(sy) * TC(at(v, 0, sy, 0) - c);
         b[2] = TC(sz) * TC(at(v, 0, 0, sz) - c);
       } else {
-        const int t = m / 8, r = m % 8;
+        const int t = ms / 8, r = ms % 8;
         const int sa = (r & 1) ? -1 : 1, sb = (r & 2) ? -1 : 1, sc = (r & 4) ? -1 : 1;
         // axis triple (a, b; c) = (t, t+1; t+2) cyclic; offsets as (x, y, z)
         const int ea = t, eb = t == 2 ? 0 : t + 1, ec = t == 0 ? 2 : t - 1;
@@ -453,19 +453,66 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
       cf[v][1] = b[1];
       cf[v][2] = b[2];
     }
-    bits |= test(cf);
+    return test(cf);
   }
+}
+
+template <bool WIDE>
+constexpr int kPosPolys = WIDE ? 9 : 25;
+
+template <typename TC, bool WIDE = false>
+__device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ q, uint32_t* __restrict__ mask,
+                                                     const BoxGrid& G, TC gm1, size_t idx) {
+  uint32_t bits = 0;
+  for (int m = 0; m < kPosPolys<WIDE>; ++m) bits |= posit_poly_bits<TC, WIDE>(q, G, gm1, idx, m);
   mask[idx] = bits;
+}
+
+// The exact test runs on a list of the flagged cells: k_posit_compact
+// appends them (one counter add per wave), then a fixed grid walks the
+// (flagged cell, polynomial) pairs, polynomial fastest, or-ing point bits
+// into the mask word; its "needs the test" bit stays set until
+// k_posit_finalize clears it, so every pair sees the flag.  counter[0] must
+// be zero before k_posit_compact.
+__global__ void __launch_bounds__(kBlock) k_posit_compact(const uint32_t* __restrict__ mask, size_t NR,
+                                                          uint32_t* __restrict__ list, uint32_t* __restrict__ counter) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool flagged = idx < NR && (mask[idx] & kNeedsCheck);
+  const uint64_t ballot = __ballot(flagged);
+  if (ballot == 0) return;
+  const int lane = (int)(threadIdx.x & 63u);
+  const int leader = __ffsll((long long)ballot) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(ballot));
+  base = __shfl(base, leader);
+  if (flagged) {
+    const uint64_t below = lane ? (ballot & ((~0ull) >> (64 - lane))) : 0ull;
+    list[base + (uint32_t)__popcll(below)] = (uint32_t)idx;
+  }
 }
 
 template <typename TC, bool WIDE = false>
 __global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __restrict__ q, uint32_t* __restrict__ mask,
-                                                            BoxGrid G, TC gm1, size_t NR) {
-  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= NR) return;
-  if (mask[idx] != kNeedsCheck) return;
-  posit_exact_box_cell<TC, WIDE>(q, mask, G, gm1, idx);
+                                                            BoxGrid G, TC gm1, const uint32_t* __restrict__ list,
+                                                            const uint32_t* __restrict__ counter) {
+  const size_t total = (size_t)counter[0] * kPosPolys<WIDE>;
+  for (size_t w = (size_t)blockIdx.x * kBlock + threadIdx.x; w < total; w += (size_t)gridDim.x * kBlock) {
+    const size_t e = w / kPosPolys<WIDE>;
+    const int m = (int)(w - e * kPosPolys<WIDE>);
+    const size_t idx = list[e];
+    const uint32_t bits = posit_poly_bits<TC, WIDE>(q, G, gm1, idx, m);
+    if (bits) atomicOr(&mask[idx], bits);
+  }
 }
+
+__global__ void __launch_bounds__(kBlock) k_posit_finalize(uint32_t* __restrict__ mask,
+                                                           const uint32_t* __restrict__ list,
+                                                           uint32_t* __restrict__ counter) {
+  const uint32_t n = counter[0];
+  for (uint32_t w = blockIdx.x * kBlock + threadIdx.x; w < n; w += gridDim.x * kBlock) mask[list[w]] &= ~kNeedsCheck;
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p) { p[threadIdx.x] = 0u; }
 
 // ---------------------------------------------------------------- flux
 // Local frame of a face normal to axis D: local axes (D, A, B) with

@@ -39,7 +39,7 @@ unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 unsigned pad8(unsigned nb) { return (nb + 7u) & ~7u; }
 
 struct Layout {
-  size_t q, qs, acc, back, coef, mask, face[3], red, geo, verts, vnext, vol, vacc, total;
+  size_t q, qs, acc, back, coef, mask, plist, face[3], red, geo, verts, vnext, vol, vacc, total;
 };
 
 struct Dims {
@@ -129,6 +129,8 @@ Layout make_layout(const hgks_config* c, const Dims& D) {
   // one coefficient array, plus six per-face arrays in characteristic mode
   L.coef = take(coef_elems(D.NR, tc) * tc * (c->characteristic ? 7 : 1));
   L.mask = take(D.NR * sizeof(uint32_t));
+  // list of the cells the exact positivity test examines, and its counter
+  L.plist = c->moving ? 0 : take((D.NR + 64) * sizeof(uint32_t));
   const size_t nface = c->moving ? 12 : 10;
   for (int d = 0; d < 3; ++d) L.face[d] = take(nface * D.NF[d] * tc);
   L.red = take(D.nred * sizeof(double));
@@ -171,6 +173,7 @@ struct hgks_ctx_s {
   double* back() { return (double*)(ws + L.back); }
   void* coef() { return ws + L.coef; }
   uint32_t* mask() { return (uint32_t*)(ws + L.mask); }
+  uint32_t* plist() { return (uint32_t*)(ws + L.plist); }
   void* face(int d) { return ws + L.face[d]; }
   double* red() { return (double*)(ws + L.red); }
   double* geo() { return (double*)(ws + L.geo); }
@@ -280,12 +283,19 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
     prof_mark(c, HGKS_PHASE_RECON, false);
     if (hgks_status s = launched(c, "recon")) return s;
     prof_mark(c, HGKS_PHASE_FALLBACK, true);
+    // flagged cells to a list, then the (cell, polynomial) pairs on a
+    // fixed grid of 8 workgroups per compute unit
+    uint32_t* counter = c->plist() + D.NR;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, counter);
+    hipLaunchKernelGGL(k_posit_compact, dim3(nb), dim3(kBlock), 0, c->stream, c->mask(), D.NR, c->plist(), counter);
+    const unsigned pg = 2048;
     if (c->cfg.stencil)
-      hipLaunchKernelGGL((k_posit_exact_box<TC, true>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
-                         TC(c->cfg.gamma - 1.0), D.NR);
+      hipLaunchKernelGGL((k_posit_exact_box<TC, true>), dim3(pg), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+                         TC(c->cfg.gamma - 1.0), c->plist(), counter);
     else
-      hipLaunchKernelGGL((k_posit_exact_box<TC, false>), dim3(nb), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
-                         TC(c->cfg.gamma - 1.0), D.NR);
+      hipLaunchKernelGGL((k_posit_exact_box<TC, false>), dim3(pg), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+                         TC(c->cfg.gamma - 1.0), c->plist(), counter);
+    hipLaunchKernelGGL(k_posit_finalize, dim3(pg), dim3(kBlock), 0, c->stream, c->mask(), c->plist(), counter);
     prof_mark(c, HGKS_PHASE_FALLBACK, false);
     if (hgks_status s = launched(c, "positivity")) return s;
     if (c->cfg.characteristic) {
