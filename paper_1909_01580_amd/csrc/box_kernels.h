@@ -19,6 +19,7 @@
 #pragma once
 
 #include "common.h"
+#include "char_basis.h"
 #include "gks_flux.h"
 #include "weno_box.h"
 
@@ -587,6 +588,65 @@ HGKS_FN void eval_box_gp_dir(int D, const TC* __restrict__ coef, size_t cell, TC
     eval_box_gp<2>(coef, cell, xD, xA, xB, fallback, invd, W, dW);
 }
 
+// Value and gradient (local axes D, A, B; per unit length) at the Gauss
+// point of a cell reconstructed in characteristic variables: cv points at
+// the cell in its face array, Qbar is the face's mean state.  The result is
+// in the local variable order of eval_box_gp.
+template <int D, typename TC>
+__device__ __forceinline__ void eval_char_gp(const TC* cv, const double (&Qbar)[5], double gamma, TC xD, TC xA,
+                                             TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
+                                             TC (&dW)[3][5]) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3, CB = kCB<TC>;
+  constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
+  constexpr int cp[9] = {D, A, B, 3 + D, 3 + A, 3 + B, 6 + D, 6 + A, 6 + B};
+  CharBasis Bs;
+  char_basis(Qbar, D, gamma, Bs);
+  TC val[5], grad[5][3];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    val[v] = cv[v * 10 * CB];
+    grad[v][0] = grad[v][1] = grad[v][2] = TC(0);
+  }
+  if (!fallback) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      const TC* ck = cv + f * 10 * CB;
+      TC c[9];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) c[m] = ck[(cp[m] + 1) * CB];
+      TC du, g[3];
+      quad_eval(TC(0), c, xD, xA, xB, du, g[0], g[1], g[2]);
+      double r[5];
+      char_rcol(Bs, f, r);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const TC rv = TC(r[v]);
+        val[v] += rv * du;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) grad[v][j] += rv * g[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < 5; ++kk) {
+    W[kk] = val[lv[kk]];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dW[j][kk] = grad[lv[kk]][j] * invd[j];
+  }
+}
+
+template <typename TC>
+__device__ __forceinline__ void eval_char_gp_dir(int D, const TC* cv, const double (&Qbar)[5], double gamma, TC xD,
+                                                 TC xA, TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
+                                                 TC (&dW)[3][5]) {
+  if (D == 0)
+    eval_char_gp<0>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
+  else if (D == 1)
+    eval_char_gp<1>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
+  else
+    eval_char_gp<2>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
+}
+
 // One lane = one Gauss point of one face normal to axis D; the four lanes of
 // a face sum their weighted fluxes with lane shuffles.  Lane l of the
 // 256-lane block lb of direction D takes Gauss point l % 4 of face slot
@@ -621,16 +681,37 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   const TC* coefR = FS ? coef + (size_t)(2 * D) * G.fs_stride : coef;
   FluxAcc<TC> acc;
   acc_zero(acc);
-  {
-    TC W[5], dW[3][5];
-    eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
-    side_terms<+1, PR>(W, dW, gp, acc);
-  }
-  after_left_side(iR, acc);
-  {
-    TC W[5], dW[3][5];
-    eval_box_gp_dir(D, coefR, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
-    side_terms<-1, PR>(W, dW, gp, acc);
+  if constexpr (FS) {
+    // characteristic reconstruction: the face's mean state from the two
+    // cells' conservative means gives R for both sides
+    double Qbar[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      Qbar[v] = 0.5 * ((double)coefL[coef_cell<TC>(iL) + v * 10 * kCB<TC>] +
+                       (double)coefR[coef_cell<TC>(iR) + v * 10 * kCB<TC>]);
+    {
+      TC W[5], dW[3][5];
+      eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, W, dW);
+      side_terms<+1, PR>(W, dW, gp, acc);
+    }
+    after_left_side(iR, acc);
+    {
+      TC W[5], dW[3][5];
+      eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, W, dW);
+      side_terms<-1, PR>(W, dW, gp, acc);
+    }
+  } else {
+    {
+      TC W[5], dW[3][5];
+      eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
+      side_terms<+1, PR>(W, dW, gp, acc);
+    }
+    after_left_side(iR, acc);
+    {
+      TC W[5], dW[3][5];
+      eval_box_gp_dir(D, coefR, iR, TC(-0.5), xa, xb, fbR, invd, W, dW);
+      side_terms<-1, PR>(W, dW, gp, acc);
+    }
   }
   TC F[5], dF[5];
   finish_flux<PR>(acc, gp, dt, idt, F, dF);
@@ -850,7 +931,8 @@ __global__ void __launch_bounds__(kBlock) k_check_box(const double* __restrict__
 // ---------------------------------------------------------------- debug
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) k_debug_gp_box(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
-                                                         BoxGrid G, size_t NR, size_t N, double* __restrict__ out) {
+                                                         BoxGrid G, size_t NR, size_t N, double gamma,
+                                                         double* __restrict__ out) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
   const int c0 = (int)(idx % G.n[0]), c1 = (int)((idx / G.n[0]) % G.n[1]);
@@ -864,6 +946,47 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_box(const TC* __restrict__ 
     xi[(d + 1) % 3] = (gp >> 1) ? TC(kGaussNode) : TC(-kGaussNode);
     xi[(d + 2) % 3] = (gp & 1) ? TC(kGaussNode) : TC(-kGaussNode);
     const bool fb = (mk >> bit) & 1u;
+    if (G.fs_stride) {
+      // characteristic reconstruction: R from the mean of the two cells
+      // sharing face f, the fields' deviations projected back
+      const TC* cv = coef + (size_t)f * G.fs_stride + coef_cell<TC>(r);
+      int cc[3] = {c0, c1, c2};
+      cc[d] += (f & 1) ? 1 : -1;
+      const size_t rn = ((size_t)rec_index(G, 2, cc[2]) * G.nr[1] + rec_index(G, 1, cc[1])) * G.nr[0] +
+                        rec_index(G, 0, cc[0]);
+      const TC* cn = coef + (size_t)f * G.fs_stride + coef_cell<TC>(rn);
+      double Qbar[5];
+      for (int v = 0; v < 5; ++v) Qbar[v] = 0.5 * ((double)cv[v * 10 * kCB<TC>] + (double)cn[v * 10 * kCB<TC>]);
+      CharBasis Bs;
+      char_basis(Qbar, d, gamma, Bs);
+      double val[5], g[5][3];
+      for (int v = 0; v < 5; ++v) {
+        val[v] = (double)cv[v * 10 * kCB<TC>];
+        g[v][0] = g[v][1] = g[v][2] = 0.0;
+      }
+      if (!fb) {
+        for (int fld = 0; fld < 5; ++fld) {
+          const TC* ck = cv + fld * 10 * kCB<TC>;
+          TC c[9];
+          for (int m = 0; m < 9; ++m) c[m] = ck[(m + 1) * kCB<TC>];
+          TC du, gu[3];
+          quad_eval(TC(0), c, xi[0], xi[1], xi[2], du, gu[0], gu[1], gu[2]);
+          double rc[5];
+          char_rcol(Bs, fld, rc);
+          for (int v = 0; v < 5; ++v) {
+            const TC rv = TC(rc[v]);
+            val[v] += (double)(rv * du);
+            for (int j = 0; j < 3; ++j) g[v][j] += (double)(rv * gu[j]);
+          }
+        }
+      }
+      for (int v = 0; v < 5; ++v) {
+        double* o = out + ((idx * 24 + bit) * 5 + v) * 4;
+        o[0] = val[v];
+        for (int j = 0; j < 3; ++j) o[1 + j] = g[v][j] * G.inv_dx[j];
+      }
+      continue;
+    }
     for (int v = 0; v < 5; ++v) {
       const TC* cv = coef + (size_t)f * G.fs_stride + coef_cell<TC>(r) + v * 10 * kCB<TC>;
       TC c[9];

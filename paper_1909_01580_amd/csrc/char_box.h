@@ -7,12 +7,16 @@
 // mean of the two cell averages that share the face.  The WENO-AO
 // reconstruction of Sec. 2 runs on each component of U -- the least squares
 // are linear, so its polynomials are the projected ones, while indicators
-// and nonlinear weights belong to each characteristic field -- and its
-// quadratic is projected back with R.  Each cell thus gets six quadratics,
-// one per face, stored as six coefficient arrays of the usual layout
-// (array 2 D + s); the face flux reads the left cell's array 2 D + 1 and the
-// right cell's array 2 D.  The positivity fallback stays on the conservative
-// polynomials (the mask of the component-wise reconstruction).
+// and nonlinear weights belong to each characteristic field.  Each cell
+// thus gets six reconstructions, one per face, stored as six coefficient
+// arrays of the usual layout (array 2 D + s): row 10 v holds the
+// conservative cell mean of variable v, rows 10 f + 1 .. 10 f + 9 the nine
+// coefficients of characteristic field f.  The face flux reads the left
+// cell's array 2 D + 1 and the right cell's array 2 D, forms R from the two
+// means (the same mean state) and projects back at its Gauss point: value
+// Q_c + R dU(x), gradient R grad U(x), dU the fields' deviation from their
+// means.  The positivity fallback stays on the conservative polynomials
+// (the mask of the component-wise reconstruction).
 //
 // The shear eigenvectors are the tangential axes D+1, D+2 in cyclic order,
 // the frame of the face flux.
@@ -21,78 +25,6 @@
 #include "box_kernels.h"
 
 namespace hgks {
-
-// Eigenvectors of the Euler Jacobian along axis D at a state, in terms of a
-// few scalars; rows of L = R^-1 and columns of R are formed on demand.
-// Order of the fields: u_n - c, entropy, shear along axis D+1, shear along
-// axis D+2 (cyclic), u_n + c.
-struct CharBasis {
-  double V[3], c, ic, H, q2, b1, b2;
-  double un, vA, vC;  // velocity along D, D+1, D+2
-  int D, A, C;
-};
-
-// v[i] for a lane-uniform runtime i, by selects (no indexed private array).
-HGKS_FN double pick3(const double (&v)[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
-
-HGKS_FN void char_basis(const double (&Qb)[5], int D, double gamma, CharBasis& B) {
-  B.D = D;
-  B.A = D == 2 ? 0 : D + 1;
-  B.C = D == 0 ? 2 : D - 1;
-  const double ir = 1.0 / Qb[0];
-  for (int e = 0; e < 3; ++e) B.V[e] = Qb[1 + e] * ir;
-  B.q2 = B.V[0] * B.V[0] + B.V[1] * B.V[1] + B.V[2] * B.V[2];
-  const double p = (gamma - 1.0) * (Qb[4] - 0.5 * Qb[0] * B.q2);
-  const double c2 = gamma * p * ir;
-  B.c = sqrt(c2);
-  B.ic = 1.0 / B.c;
-  B.H = (Qb[4] + p) * ir;
-  B.b1 = (gamma - 1.0) / c2;
-  B.b2 = 0.5 * B.b1 * B.q2;
-  B.un = pick3(B.V, D);
-  B.vA = pick3(B.V, B.A);
-  B.vC = pick3(B.V, B.C);
-}
-
-// Row f of L (acting on rho, rho u, rho v, rho w, rho E).
-HGKS_FN void char_lrow(const CharBasis& B, int f, double (&l)[5]) {
-  const double un = B.un;
-  if (f == 0 || f == 4) {
-    const double sg = f == 0 ? 1.0 : -1.0;
-    l[0] = 0.5 * (B.b2 + sg * un * B.ic);
-    for (int e = 0; e < 3; ++e) l[1 + e] = -0.5 * (B.b1 * B.V[e] + (e == B.D ? sg * B.ic : 0.0));
-    l[4] = 0.5 * B.b1;
-  } else if (f == 1) {
-    l[0] = 1.0 - B.b2;
-    for (int e = 0; e < 3; ++e) l[1 + e] = B.b1 * B.V[e];
-    l[4] = -B.b1;
-  } else {
-    const int t = f == 2 ? B.A : B.C;
-    l[0] = f == 2 ? -B.vA : -B.vC;
-    for (int e = 0; e < 3; ++e) l[1 + e] = e == t ? 1.0 : 0.0;
-    l[4] = 0.0;
-  }
-}
-
-// Column f of R.
-HGKS_FN void char_rcol(const CharBasis& B, int f, double (&r)[5]) {
-  const double un = B.un;
-  if (f == 0 || f == 4) {
-    const double sg = f == 0 ? -1.0 : 1.0;
-    r[0] = 1.0;
-    for (int e = 0; e < 3; ++e) r[1 + e] = B.V[e] + (e == B.D ? sg * B.c : 0.0);
-    r[4] = B.H + sg * B.c * un;
-  } else if (f == 1) {
-    r[0] = 1.0;
-    for (int e = 0; e < 3; ++e) r[1 + e] = B.V[e];
-    r[4] = 0.5 * B.q2;
-  } else {
-    const int t = f == 2 ? B.A : B.C;
-    r[0] = 0.0;
-    for (int e = 0; e < 3; ++e) r[1 + e] = e == t ? 1.0 : 0.0;
-    r[4] = f == 2 ? B.vA : B.vC;
-  }
-}
 
 // Characteristic reconstruction of reconstruction-box cell idx for its face
 // fs = 2 D + s, written into the face array `out` (coefficient layout).
@@ -168,36 +100,12 @@ __device__ __forceinline__ void char_recon_box_cell(const double* __restrict__ q
     BoxRecon<TC> r;
     weno_box(d, P, r);
     TC* cv = base + f * 10 * kCB<TC>;
+    cv[0] = TC(Qc[f]);  // the conservative mean of variable f
 #pragma unroll
     for (int m = 0; m < 9; ++m) cv[(m + 1) * kCB<TC>] = r.c[m];
-    // The next field's loads and the projection back read memory again
-    // instead of keeping this field's results in registers.
+    // the next field's loads are not hoisted into this field's work
     asm volatile("" ::: "memory");
   }
-  // Back to conservative variables, coefficient by coefficient, in place.
-  TC R[5][5];
-#pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    double r[5];
-    char_rcol(B, f, r);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) R[v][f] = TC(r[v]);
-  }
-#pragma unroll
-  for (int m = 1; m < 10; ++m) {
-    TC u[5];
-#pragma unroll
-    for (int f = 0; f < 5; ++f) u[f] = base[(10 * f + m) * kCB<TC>];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      TC s = TC(0);
-#pragma unroll
-      for (int f = 0; f < 5; ++f) s += R[v][f] * u[f];
-      base[(10 * v + m) * kCB<TC>] = s;
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 5; ++v) base[10 * v * kCB<TC>] = TC(Qc[v]);
 }
 
 // One lane per reconstruction-box cell, blockIdx.y = face 2 D + s.

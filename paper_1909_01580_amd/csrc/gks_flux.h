@@ -62,6 +62,7 @@ struct GasParams {
   T mu_exp;   // viscosity law mu (T / T0)^mu_exp on the viscous branch (0: constant)
   T mu_iT0;   // 1 / T0
   T pr_fix;   // 1 / Pr - 1: weight of the heat flux added to the energy flux
+  double gamma;  // ratio of specific heats (characteristic projection)
 };
 
 // Gaussian moments of the tangential and internal velocities of one state.

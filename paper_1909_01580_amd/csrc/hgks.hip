@@ -251,6 +251,7 @@ GasParams<T> gas_params(const hgks_config& cfg) {
   g.mu_exp = T(cfg.mu_exponent);
   g.mu_iT0 = T(1.0 / cfg.mu_T0);
   g.pr_fix = T(1.0 / cfg.prandtl - 1.0);
+  g.gamma = cfg.gamma;
   return g;
 }
 
@@ -717,10 +718,10 @@ hgks_status hgks_debug_gp_states(hgks_ctx c, double dt, double* out) {
   if (s) return s;
   if (c->mixed())
     hipLaunchKernelGGL((k_debug_gp_box<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
-                       (const float*)face_coef<float>(c), c->mask(), c->G, c->D.NR, c->D.N, out);
+                       (const float*)face_coef<float>(c), c->mask(), c->G, c->D.NR, c->D.N, c->cfg.gamma, out);
   else
     hipLaunchKernelGGL((k_debug_gp_box<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream,
-                       (const double*)face_coef<double>(c), c->mask(), c->G, c->D.NR, c->D.N, out);
+                       (const double*)face_coef<double>(c), c->mask(), c->G, c->D.NR, c->D.N, c->cfg.gamma, out);
   return launched(c, "debug gp");
 }
 
