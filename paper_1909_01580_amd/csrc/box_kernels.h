@@ -222,8 +222,10 @@ __device__ __forceinline__ int rec_index(const BoxGrid& G, int ax, int i) {
 
 // ---------------------------------------------------------------- recon
 // Reconstruction of reconstruction-box cell idx (< NR).  WIDE: the
-// stencils of Remark 1 (the big stencil reaches two cells along the axes).
-template <typename TC, bool WIDE = false>
+// stencils of Remark 1 (the big stencil reaches two cells along the axes);
+// COEF = false: the fallback mask only (the characteristic reconstruction
+// stores its own coefficients).
+template <typename TC, bool WIDE = false, bool COEF = true>
 __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC* __restrict__ coef,
                                                uint32_t* __restrict__ mask, const BoxGrid& G,
                                                const WenoParams<TC>& P, TC margin, TC gm1, size_t NR, size_t idx) {
@@ -293,10 +295,12 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
     } else {
       weno_box(d, P, r);
     }
-    TC* cv = coef + coef_cell<TC>(idx) + v * 10 * kCB<TC>;
-    cv[0] = TC(c);
+    if constexpr (COEF) {
+      TC* cv = coef + coef_cell<TC>(idx) + v * 10 * kCB<TC>;
+      cv[0] = TC(c);
 #pragma unroll
-    for (int m = 0; m < 9; ++m) cv[(m + 1) * kCB<TC>] = r.c[m];
+      for (int m = 0; m < 9; ++m) cv[(m + 1) * kCB<TC>] = r.c[m];
+    }
     qc[v] = TC(c);
     bnd[v] = r.bound;
     // The next variable's stencil loads wait for this variable's results
@@ -322,7 +326,7 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
   mask[idx] = safe ? 0u : kNeedsCheck;
 }
 
-template <typename TC, bool WIDE = false>
+template <typename TC, bool WIDE = false, bool COEF = true>
 __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__ q, TC* __restrict__ coef,
                                                       uint32_t* __restrict__ mask, BoxGrid G,
                                                       WenoParams<TC> P, TC margin, TC gm1, size_t NR,
@@ -331,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__
   if (b >= nblk) return;
   const size_t idx = (size_t)b * kBlock + threadIdx.x;
   if (idx >= NR) return;
-  recon_box_cell<TC, WIDE>(q, coef, mask, G, P, margin, gm1, NR, idx);
+  recon_box_cell<TC, WIDE, COEF>(q, coef, mask, G, P, margin, gm1, NR, idx);
 }
 
 // Exact fallback test (Sec. 4): for every Gauss point of the cell, any of

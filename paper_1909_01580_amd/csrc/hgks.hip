@@ -278,6 +278,9 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
     if (c->cfg.stencil)
       hipLaunchKernelGGL((k_recon_box<TC, true>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(),
                          c->G, P, margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
+    else if (c->cfg.characteristic)  // the fallback mask only
+      hipLaunchKernelGGL((k_recon_box<TC, false, false>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef,
+                         c->mask(), c->G, P, margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
     else
       hipLaunchKernelGGL((k_recon_box<TC, false>), dim3(pad8(nb)), dim3(kBlock), 0, c->stream, qin, coef, c->mask(),
                          c->G, P, margin, TC(c->cfg.gamma - 1.0), D.NR, nb);
