@@ -556,31 +556,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     beta0[v] = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + tr + 4.0 * (c[3] * c[3] + c[4] * c[4] + c[5] * c[5]) +
                c[6] * c[6] + c[7] * c[7] + c[8] * c[8];
   }
-  // Pass 1: tau = mean |beta_0 - beta_m|.
-  double tau[5] = {0, 0, 0, 0, 0};
-#pragma unroll 1
-  for (int m = 0; m < 24; ++m) {
-    double b[5][3];
-    sub_fit(nb, Ci, qc, m, b);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
-      tau[v] += fabs(beta0[v] - bm);
-    }
-  }
-  // Pass 2: weights and the combination.  With W = sum of all weights,
-  // w0r = omega_0 / gamma_0 and off = w0r Gamma, the combined linear part
-  // is (w0r a + sum_m (omega_m - off) b^m) / W, so one running sum per
-  // variable and component suffices.
-  double S[5], wb[5][3], bnd[5], w0r[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    tau[v] *= 1.0 / 24.0;
-    w0r[v] = 1.0 + tau[v] * d_rcp(beta0[v] + P.eps);
-    S[v] = P.gamma0 * w0r[v];
-    wb[v][0] = wb[v][1] = wb[v][2] = 0.0;
-    bnd[v] = 0.0;
-  }
   // Bounds of the basis magnitudes over the 24 face Gauss points, for the
   // bound of |P_m - Q| used by the fallback pre-test.  The Gauss points
   // are convex combinations of the cell's vertices (bilinear faces), so
@@ -605,6 +580,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     pmax[7] = xm[1] * xm[2] + fabs(Ci.m[4]);
     pmax[8] = xm[0] * xm[2] + fabs(Ci.m[5]);
   }
+  // One pass over the sub-stencils.  With r_m = 1/(beta_m + eps) and
+  // r_0 = 1/(beta_0 + eps) the weights are affine in tau: omega_m =
+  // Gamma (1 + tau r_m), omega_0 / gamma_0 = 1 + tau r_0.  So the weight
+  // sum is gamma_0 (1 + tau r_0) + Gamma (24 + tau sum_m r_m), and the
+  // combined linear part sum_m (omega_m - Gamma omega_0 / gamma_0) b^m =
+  // Gamma tau sum_m (r_m - r_0) b^m.  The pass gathers sum |beta_0 -
+  // beta_m| (tau), sum r_m and sum (r_m - r_0) b^m; tau enters afterwards.
+  double tsum[5], rsum[5], db[5][3], bnd[5], r0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    r0[v] = d_rcp(beta0[v] + P.eps);
+    tsum[v] = rsum[v] = bnd[v] = 0.0;
+    db[v][0] = db[v][1] = db[v][2] = 0.0;
+  }
 #pragma unroll 1
   for (int m = 0; m < 24; ++m) {
     double b[5][3];
@@ -612,13 +601,23 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
-      const double om = P.Gamma * (1.0 + tau[v] * d_rcp(bm + P.eps));
-      S[v] += om;
-      const double cm = om - w0r[v] * P.Gamma;
+      tsum[v] += fabs(beta0[v] - bm);
+      const double rm = d_rcp(bm + P.eps);
+      rsum[v] += rm;
+      const double dr = rm - r0[v];
 #pragma unroll
-      for (int e = 0; e < 3; ++e) wb[v][e] += cm * b[v][e];
+      for (int e = 0; e < 3; ++e) db[v][e] += dr * b[v][e];
       bnd[v] = fmax(bnd[v], fabs(b[v][0]) * pmax[0] + fabs(b[v][1]) * pmax[1] + fabs(b[v][2]) * pmax[2]);
     }
+  }
+  double S[5], wb[5][3], w0r[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double tau = tsum[v] * (1.0 / 24.0);
+    w0r[v] = 1.0 + tau * r0[v];
+    S[v] = P.gamma0 * w0r[v] + P.Gamma * (24.0 + tau * rsum[v]);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) wb[v][e] = P.Gamma * tau * db[v][e];
   }
 #pragma unroll
   for (int v = 0; v < 5; ++v) {

@@ -108,3 +108,43 @@ def test_free_stream_on_moving_mesh(hg, precision):
         ctx.step(dt, 2)
     err = np.abs(ctx.get_state().cpu().numpy() - Q).max()
     assert err < (1e-13 if precision == "fp64" else 1e-5), err
+
+
+def blast_point(X, Y, Z, gamma=oracle.Params().gamma):
+    """A moving sphere of dense high-pressure gas (Sod-type jump 1 : 0.125
+    in density, 1 : 0.1 in pressure): the nonlinear weights and the
+    positivity fallback on a non-coplanar mesh."""
+    r = np.sqrt((X - 0.9) ** 2 + (Y - 1.0) ** 2 + (Z - 1.1) ** 2)
+    inside = r < 0.6
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    zero = np.zeros_like(rho)
+    return wl.conservative(rho, zero + 0.3, zero, zero - 0.2, p, gamma)
+
+
+def test_static_blast_weights_and_fallback(hg):
+    n = (10, 9, 8)
+    verts = wl.sine_mesh_vertices(n, 0.0, amp=0.1, static=True)
+    Q = wl.hex_average(verts, PERIOD, blast_point)
+    prob = oracle.vertex_problem(n, verts, PERIOD)
+    ctx = make(hg, n, verts, Q)
+    dt = oracle.max_dt(prob, Q, 0.35)
+    gpu = ctx.debug_gp_states(dt).cpu().numpy()
+    ref = scheme.gp_states(prob, Q, dt)
+    for k in range(4):
+        e = nerr(gpu[..., k], ref[..., k], axis_var=4)
+        assert e.max() < TOL * (1 if k == 0 else 10), (k, e)
+    mask = scheme.fallback_mask(prob, Q, dt)
+    count = int(sum(bin(int(m)).count("1") for m in mask.ravel()))
+    assert count > 1000
+    assert ctx.check()[1] == count
+    zero_g = np.all(ref[..., 1:] == 0.0, axis=(-1, -2))
+    assert np.array_equal(np.all(gpu[..., 1:] == 0.0, axis=(-1, -2)), zero_g)
+    gf = ctx.debug_face_flux(dt).cpu().numpy()
+    rf = scheme.face_fluxes(prob, Q, dt)
+    for k in range(2):
+        err = np.abs(gf[..., k, :] - rf[..., k, :]).max() / np.abs(rf[..., k, :]).max()
+        assert err < TOL * (1 if k == 0 else 100), (k, err)
+    ref_q = oracle.step(prob, Q, dt)
+    ctx.step(dt, 2)
+    assert nerr(ctx.get_state().cpu().numpy(), ref_q).max() < TOL
