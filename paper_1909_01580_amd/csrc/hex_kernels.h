@@ -46,7 +46,7 @@ struct HexGrid {
   int n[3];
   double period[3];
   const double* x0;  // vertices at t_n, [3][N]
-  const double* x1;  // vertices at t_{n+1}, or null for a static grid
+  const double* x1;  // vertices at t_{n+1}, or null (or x0) for a static grid
   double alpha;      // stage time (t - t_n) / dt
   double inv_dt;
   BoxGrid box;       // the same extents (all periodic) for index splitting and flux block order
@@ -90,17 +90,16 @@ __device__ __forceinline__ void hex_vertex(const HexGrid& H, int i, int j, int k
   }
   const size_t N = (size_t)H.n[0] * H.n[1] * H.n[2];
   const size_t idx = ((size_t)c[2] * H.n[1] + c[1]) * H.n[0] + c[0];
+  // A static grid reads its one vertex array twice (b - a = 0 exactly, so
+  // x = a and u = 0): no branch between the loads, which lets all of them
+  // be in flight at once.
+  const double* __restrict__ x1 = H.x1 ? H.x1 : H.x0;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const double a = H.x0[e * N + idx] + s[e];
-    if (H.x1) {
-      const double b = H.x1[e * N + idx] + s[e];
-      x[e] = a + H.alpha * (b - a);
-      u[e] = (b - a) * H.inv_dt;
-    } else {
-      x[e] = a;
-      u[e] = 0.0;
-    }
+    const double b = x1[e * N + idx] + s[e];
+    x[e] = a + H.alpha * (b - a);
+    u[e] = (b - a) * H.inv_dt;
   }
 }
 
@@ -854,7 +853,11 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     g[16 * kBlock] = Pt.u[0] * adot[0] + Pt.u[1] * adot[1] + Pt.u[2] * adot[2];
     g[17 * kBlock] = 0.25 * (Pt.u[0] * av[0] + Pt.u[1] * av[1] + Pt.u[2] * av[2]);
   }
-  const volatile double* gs = &stash[0][threadIdx.x];
+  // The re-reads are plain LDS loads behind a compiler-only memory fence
+  // (no instruction): the fence keeps the compiler from forwarding the
+  // stored registers, and unlike a volatile access it leaves the loads
+  // free to be issued together with the others.
+  const double* gs = &stash[0][threadIdx.x];
   auto get3 = [&](int k, double (&v)[3]) {
 #pragma unroll
     for (int e = 0; e < 3; ++e) v[e] = gs[(k + e) * kBlock];
@@ -871,6 +874,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   FluxAcc<TC> acc;
   acc_zero(acc);
   {
+    asm volatile("" ::: "memory");
     double x[3], u[3], n0[3], n1[3], n2[3];
     get3(0, x);
     get3(3, u);
@@ -886,6 +890,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   size_t iRt = iR;
   after_left_side(iRt, acc);
   {
+    asm volatile("" ::: "memory");
     double x[3], u[3], n0[3], n1[3], n2[3];
     get3(0, x);
     get3(3, u);
@@ -898,6 +903,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     to_local(val, grad, u, n0, n1, n2, W, dW);
     side_terms<-1>(W, dW, gp, acc);
   }
+  asm volatile("" ::: "memory");
   double u[3], n0[3], n1[3], n2[3];
   get3(3, u);
   get3(6, n0);
