@@ -10,8 +10,54 @@
 
 namespace hgks {
 
+// A double constant in a scalar register pair.  FP64 vector instructions
+// take no 64-bit literal, so a constant whose low word is not zero is
+// otherwise rebuilt by two vector moves at every use; from a scalar pair it
+// is a plain operand (one scalar operand per instruction: the addend or the
+// multiplier of an FMA), built by scalar moves that issue beside the vector
+// work.
+HGKS_FN double sreg(double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm volatile("" : "=s"(r) : "0"(c));
+  return r;
+#else
+  return c;
+#endif
+}
+template <typename T> HGKS_FN T kconst(double c) { return T(c); }
+template <> HGKS_FN double kconst<double>(double c) { return sreg(c); }
+
+// exp(x) in double: Cody and Waite's reduction x = k ln2 + r, k = rint(x /
+// ln2), |r| <= ln2 / 2, with ln2 split as hi + lo (hi has 21 significant
+// bits, so k hi is exact for every k that does not overflow), then the
+// Taylor polynomial of e^r to degree 13 (the first omitted term is below
+// 7e-18 relative) by Horner's rule, scaled by 2^k.  Arguments below -1000
+// are raised to -1000 (the result is 0 either way); NaN passes through.
+constexpr double exp_taylor_coef(int n) {
+  double f = 1.0;
+  for (int k = 2; k <= n; ++k) f /= k;
+  return f;
+}
+HGKS_FN double exp_cw(double x) {
+  x = x < -1000.0 ? -1000.0 : x;
+  const double k = rint(x * kconst<double>(1.4426950408889634));  // 1/ln2
+  double r = fma(-k, 0.693146705627441406250, x);                 // ln2 hi
+  r = fma(-k, kconst<double>(4.7493250390316727e-07), r);          // ln2 lo
+  double p = kconst<double>(exp_taylor_coef(13));
+#pragma unroll
+  for (int n = 12; n >= 0; --n) p = fma(p, r, kconst<double>(exp_taylor_coef(n)));
+  return ldexp(p, (int)k);
+}
+
 template <typename T> HGKS_FN T d_exp(T x);
-template <> HGKS_FN double d_exp<double>(double x) { return exp(x); }
+template <> HGKS_FN double d_exp<double>(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return exp_cw(x);
+#else
+  return exp(x);
+#endif
+}
 template <> HGKS_FN float d_exp<float>(float x) { return expf(x); }
 // erf(x) = (2/sqrt(pi)) sum_n (-1)^n x^(2n+1) / (n! (2n+1)), its Maclaurin
 // series, summed by Horner's rule in x^2 over the first N terms.  For
@@ -28,7 +74,7 @@ HGKS_FN T erf_series(T x) {
   const T t = x * x;
   T s = T(erf_series_coef(N - 1));
 #pragma unroll
-  for (int n = N - 2; n >= 0; --n) s = s * t + T(erf_series_coef(n));
+  for (int n = N - 2; n >= 0; --n) s = s * t + kconst<T>(erf_series_coef(n));
   return s * x;
 }
 

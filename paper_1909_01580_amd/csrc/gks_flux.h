@@ -341,10 +341,10 @@ __device__ __forceinline__ void after_left_side(size_t& idx, const FluxAcc<T>& A
   asm volatile("" : "+v"(idx) : "v"(A.X6[0]), "v"(A.X6[4]), "v"(A.Q0[4]), "v"(A.X4[4]));
 }
 
-// Time integrals over [0, delta] of the five time factors of Eq. (15).
+// Time integrals over [0, delta] of the five time factors of Eq. (15);
+// E = exp(-delta / tau).
 template <typename T>
-HGKS_FN void time_integrals(T delta, T tau, T itau, T (&Tc)[5]) {
-  const T E = d_exp(-delta * itau);
+HGKS_FN void time_integrals(T delta, T tau, T E, T (&Tc)[5]) {
   const T om = T(1) - E;
   Tc[0] = delta - tau * om;
   Tc[1] = T(2) * tau * tau * om - tau * delta * (T(1) + E);
@@ -378,8 +378,10 @@ HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&
   T c[5], d[5];
   {
     T Tf[5], Th[5];
-    time_integrals(dt, tau, itau, Tf);
-    time_integrals(T(0.5) * dt, tau, itau, Th);
+    // exp(-dt / tau) as the square of exp(-dt / (2 tau))
+    const T Eh = d_exp(T(-0.5) * dt * itau);
+    time_integrals(dt, tau, Eh * Eh, Tf);
+    time_integrals(T(0.5) * dt, tau, Eh, Th);
     const T idt2 = T(4) * idt * idt;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
