@@ -26,30 +26,22 @@
 
 namespace hgks {
 
-// Characteristic reconstruction of reconstruction-box cell idx for its face
-// fs = 2 D + s, written into the face array `out` (coefficient layout).
+// LDS tile: kCX x kCY x kCZ reconstruction-box cells (one wave per x-row
+// of 64, so that the coefficient stores of a wave are contiguous) and one
+// layer around them.  The five variables of every tile cell are staged
+// once, boundary images resolved (mirror images with the normal momentum
+// reversed), and serve the six faces of every cell of the tile.
+constexpr int kCX = 64, kCY = 2, kCZ = 2;
+constexpr int kCHX = kCX + 2, kCHY = kCY + 2, kCHZ = kCZ + 2, kCHalo = kCHX * kCHY * kCHZ;
+
+// Characteristic reconstruction of the tile cell at `base` (its index in
+// the tile) for its face fs = 2 D + s, written into the face array `out`
+// (coefficient layout) at reconstruction-box cell idx.
 template <typename TC>
-__device__ __forceinline__ void char_recon_box_cell(const double* __restrict__ q, TC* out, const BoxGrid& G,
-                                                    const WenoParams<TC>& P, double gamma, size_t idx, int D,
-                                                    int side) {
-  int ri, rj, rk;
-  split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
-  const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
-  int ix[3], iy[3], iz[3];
-  double sx[3], sy[3], sz[3];
-#pragma unroll
-  for (int o = 0; o < 3; ++o) {
-    ix[o] = bc_index(G, 0, i + o - 1, sx[o]);
-    iy[o] = bc_index(G, 1, j + o - 1, sy[o]);
-    iz[o] = bc_index(G, 2, k + o - 1, sz[o]);
-  }
-  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
-  // value of variable v in the stencil cell at offset (ox, oy, oz), mirror
-  // images with the normal momentum reversed
-  auto at = [&](int v, int ox, int oy, int oz) -> double {
-    const double s = v == 1 ? sx[ox + 1] : (v == 2 ? sy[oy + 1] : (v == 3 ? sz[oz + 1] : 1.0));
-    return s * q[v * N + iz[oz + 1] * nxy + iy[oy + 1] * nx + ix[ox + 1]];
-  };
+__device__ __forceinline__ void char_recon_tile_cell(const double (&T)[5][kCHalo], int base, TC* out,
+                                                     const WenoParams<TC>& P, double gamma, size_t idx, int D,
+                                                     int side) {
+  auto at = [&](int v, int ox, int oy, int oz) -> double { return T[v][base + (oz * kCHY + oy) * kCHX + ox]; };
   double Qc[5], Qb[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -66,23 +58,20 @@ __device__ __forceinline__ void char_recon_box_cell(const double* __restrict__ q
   }
   CharBasis B;
   char_basis(Qb, D, gamma, B);
-  TC* base = out + coef_cell<TC>(idx);
+  TC* base_out = out + coef_cell<TC>(idx);
 #pragma unroll 1
   for (int f = 0; f < 5; ++f) {
     double l[5];
     char_lrow(B, f, l);
     // d = L_f (Q_s - Q_c) over the 18 stencil cells, one conservative
-    // variable per pass: the memory clobber keeps each pass's 18 loads from
-    // being issued together with the others'.
+    // variable per pass: the memory fence keeps each pass's 18 loads from
+    // being issued together with the others' (their values would all be
+    // live at once).
     double acc[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) acc[t] = 0.0;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      // the stencil indices are re-read by every pass, so that the 90
-      // addresses of a field are not formed once and held in registers
-      asm volatile("" : "+v"(ix[0]), "+v"(ix[1]), "+v"(ix[2]), "+v"(iy[0]), "+v"(iy[1]), "+v"(iy[2]),
-                   "+v"(iz[0]), "+v"(iz[1]), "+v"(iz[2]));
 #pragma unroll
       for (int oz = -1; oz <= 1; ++oz)
 #pragma unroll
@@ -99,26 +88,54 @@ __device__ __forceinline__ void char_recon_box_cell(const double* __restrict__ q
     for (int t = 0; t < 27; ++t) d[t] = TC(acc[t]);
     BoxRecon<TC> r;
     weno_box(d, P, r);
-    TC* cv = base + f * 10 * kCB<TC>;
+    TC* cv = base_out + f * 10 * kCB<TC>;
     cv[0] = TC(Qc[f]);  // the conservative mean of variable f
 #pragma unroll
     for (int m = 0; m < 9; ++m) cv[(m + 1) * kCB<TC>] = r.c[m];
-    // the next field's loads are not hoisted into this field's work
     asm volatile("" ::: "memory");
   }
 }
 
-// One lane per reconstruction-box cell, blockIdx.y = face 2 D + s.
+// One workgroup per tile of the reconstruction box (tiles x-fastest, ntx x
+// nty x ntz of them); every lane reconstructs its cell for the six faces in
+// turn.  Lanes of cells beyond the box only help to stage the tile.
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) k_char_recon_box(const double* __restrict__ q, TC* faces, BoxGrid G,
-                                                           WenoParams<TC> P, double gamma, size_t NR,
-                                                           unsigned nblk) {
+                                                           WenoParams<TC> P, double gamma, unsigned ntx,
+                                                           unsigned nty, unsigned ntiles) {
+  static_assert(kCX * kCY * kCZ == kBlock, "one lane per tile cell");
+  __shared__ double T[5][kCHalo];
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b >= nblk) return;
-  const size_t idx = (size_t)b * kBlock + threadIdx.x;
-  if (idx >= NR) return;
-  const int fs = (int)blockIdx.y;
-  char_recon_box_cell(q, faces + (size_t)fs * G.fs_stride, G, P, gamma, idx, fs >> 1, fs & 1);
+  if (b >= ntiles) return;
+  const int o[3] = {(int)(b % ntx) * kCX, (int)((b / ntx) % nty) * kCY, (int)(b / (ntx * nty)) * kCZ};
+  const size_t nx = G.n[0], nxy = nx * G.n[1], N = nxy * G.n[2];
+  for (int t = threadIdx.x; t < kCHalo; t += kBlock) {
+    const int h[3] = {t % kCHX, (t / kCHX) % kCHY, t / (kCHX * kCHY)};
+    int c[3];
+    double sg[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      // reconstruction-box coordinate, clamped to [-1, nr]: the reach of
+      // the stencils of the box's own cells (tile overhang repeats the edge)
+      const int r = min(max(o[d] + h[d] - 1, -1), G.nr[d]);
+      c[d] = bc_index(G, d, r - G.g[d], sg[d]);
+    }
+    const size_t io = (size_t)c[2] * nxy + (size_t)c[1] * nx + c[0];
+    T[0][t] = q[io];
+    T[1][t] = sg[0] * q[N + io];
+    T[2][t] = sg[1] * q[2 * N + io];
+    T[3][t] = sg[2] * q[3 * N + io];
+    T[4][t] = q[4 * N + io];
+  }
+  __syncthreads();
+  const int l[3] = {(int)threadIdx.x % kCX, ((int)threadIdx.x / kCX) % kCY, (int)threadIdx.x / (kCX * kCY)};
+  const int ri = o[0] + l[0], rj = o[1] + l[1], rk = o[2] + l[2];
+  if (ri >= G.nr[0] || rj >= G.nr[1] || rk >= G.nr[2]) return;
+  const size_t idx = ((size_t)rk * G.nr[1] + rj) * G.nr[0] + ri;
+  const int base = ((l[2] + 1) * kCHY + (l[1] + 1)) * kCHX + (l[0] + 1);
+#pragma unroll 1
+  for (int fs = 0; fs < 6; ++fs)
+    char_recon_tile_cell(T, base, faces + (size_t)fs * G.fs_stride, P, gamma, idx, fs >> 1, fs & 1);
 }
 
 }  // namespace hgks

@@ -304,8 +304,10 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
     if (hgks_status s = launched(c, "positivity")) return s;
     if (c->cfg.characteristic) {
       prof_mark(c, HGKS_PHASE_RECON, true);
-      hipLaunchKernelGGL((k_char_recon_box<TC>), dim3(pad8(nb), 6), dim3(kBlock), 0, c->stream, qin,
-                         face_coef<TC>(c), c->G, P, c->cfg.gamma, D.NR, nb);
+      const unsigned ntx = (unsigned)((c->G.nr[0] + kCX - 1) / kCX), nty = (unsigned)((c->G.nr[1] + kCY - 1) / kCY);
+      const unsigned ntiles = ntx * nty * (unsigned)((c->G.nr[2] + kCZ - 1) / kCZ);
+      hipLaunchKernelGGL((k_char_recon_box<TC>), dim3(pad8(ntiles)), dim3(kBlock), 0, c->stream, qin,
+                         face_coef<TC>(c), c->G, P, c->cfg.gamma, ntx, nty, ntiles);
       prof_mark(c, HGKS_PHASE_RECON, false);
       if (hgks_status s = launched(c, "characteristic recon")) return s;
     }

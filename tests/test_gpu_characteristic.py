@@ -30,6 +30,9 @@ CASES = {
     "mixed_ends": dict(n=(9, 12, 10), L=(0.9, 1.2, 1.0),
                        bc=(("symmetric", "outflow"), "periodic", ("outflow", "symmetric")), mu=0.0,
                        state=lambda n, L: smooth_state(n, L, 5, mach=0.5)),
+    # longer than one 64-cell tile row along x, ragged in every direction
+    "long_x_mixed": dict(n=(67, 5, 3), L=(3.35, 0.5, 0.3), bc=(("outflow", "symmetric"), "periodic", "symmetric"),
+                         mu=5e-4, state=lambda n, L: blast_state(n, L, centre=(1.6, 0.25, 0.0), radius=0.4)),
 }
 
 
