@@ -136,7 +136,9 @@ hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t byte
 hgks_status hgks_destroy(hgks_ctx ctx);
 
 /* Uniform box grid: cell (i,j,k) = origin + [i,i+1]x[j,j+1]x[k,k+1] * h with
- * h = length / n per axis.  Only for contexts with moving = 0. */
+ * h = length / n per axis.  Only for contexts with moving = 0.
+ * HGKS_EINVAL for a non-positive or non-finite length or a non-finite
+ * origin on any axis; a refused call leaves the grid as it was. */
 hgks_status hgks_set_uniform_grid(hgks_ctx ctx, const double origin_host[3],
                                   const double length_host[3]);
 
@@ -158,7 +160,8 @@ hgks_status hgks_get_state(hgks_ctx ctx, double* q_dev_out);
 
 /* dt = cfl * min over cells of h_cell / (|U| + c), h_cell the smallest
  * distance between centres of opposite faces (the paper fixes only
- * CFL = 0.35, Sec. 4).  Synchronises the stream. */
+ * CFL = 0.35, Sec. 4).  Synchronises the stream.  HGKS_EINVAL unless
+ * 0 < cfl < infinity; HGKS_ESTATE before the grid and the state are set. */
 hgks_status hgks_max_dt(hgks_ctx ctx, double cfl, double* dt_host);
 
 /* One time step of size dt: n_stages = 2 is the two-stage fourth-order

@@ -554,9 +554,13 @@ hgks_status hgks_set_uniform_grid(hgks_ctx c, const double origin[3], const doub
   if (hgks_status s = usable(c)) return s;
   if (c->cfg.moving) return fail(HGKS_EINVAL, "context expects vertices (moving = 1)");
   if (!origin || !length) return fail(HGKS_EINVAL, "null origin or length");
+  // all three axes are checked before anything is set: a refused call
+  // leaves the grid as it was
+  for (int d = 0; d < 3; ++d)
+    if (!(length[d] > 0.0) || !std::isfinite(length[d]) || !std::isfinite(origin[d]))
+      return fail(HGKS_EINVAL, "bad box");
   double vol = 1.0;
   for (int d = 0; d < 3; ++d) {
-    if (!(length[d] > 0.0) || !std::isfinite(origin[d])) return fail(HGKS_EINVAL, "bad box");
     const double h = length[d] / c->D.n[d];
     c->G.inv_dx[d] = 1.0 / h;
     vol *= h;
@@ -665,7 +669,7 @@ hgks_status hgks_step_checked(hgks_ctx c, double dt, int32_t n_stages, int32_t m
 
 hgks_status hgks_max_dt(hgks_ctx c, double cfl, double* dt_host) {
   if (hgks_status s = ready(c)) return s;
-  if (!(cfl > 0.0) || !dt_host) return fail(HGKS_EINVAL, "bad cfl or output");
+  if (!(cfl > 0.0) || !std::isfinite(cfl) || !dt_host) return fail(HGKS_EINVAL, "bad cfl or output");
   const unsigned nb = blocks_for(c->D.N);
   double* part = c->red();
   prof_mark(c, HGKS_PHASE_REDUCE, true);
@@ -1046,7 +1050,7 @@ hgks_status hgks_batch_set_uniform_grid(hgks_batch b, int32_t i, const double or
   const int n[3] = {b->cfgs[i].nx, b->cfgs[i].ny, b->cfgs[i].nz};
   double dx[3], vol = 1.0, inv[3];
   for (int d = 0; d < 3; ++d) {
-    if (!(length[d] > 0.0)) return fail(HGKS_EINVAL, "bad box");
+    if (!(length[d] > 0.0) || !std::isfinite(length[d])) return fail(HGKS_EINVAL, "bad box");
     dx[d] = length[d] / n[d];
     inv[d] = 1.0 / dx[d];
     vol *= dx[d];
@@ -1097,7 +1101,7 @@ hgks_status hgks_batch_get_state(hgks_batch b, int32_t i, double* q_dev_out) {
 
 hgks_status hgks_batch_max_dt(hgks_batch b, double cfl, double* dt_dev) {
   if (hgks_status s = batch_ready(b)) return s;
-  if (!(cfl > 0.0)) return fail(HGKS_EINVAL, "bad cfl");
+  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HGKS_EINVAL, "bad cfl");
   double* out = dt_dev ? dt_dev : (double*)(b->ws + b->dt);
   return b->mixed() ? batch_dt<float>(b, cfl, out) : batch_dt<double>(b, cfl, out);
 }
