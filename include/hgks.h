@@ -242,6 +242,9 @@ hgks_status hgks_batch_create(const hgks_config* cfgs, int32_t n, void* workspac
 hgks_status hgks_batch_destroy(hgks_batch b);
 hgks_status hgks_batch_set_uniform_grid(hgks_batch b, int32_t i, const double origin_host[3],
                                         const double length_host[3]);
+/* HGKS_EINVAL for an index outside [0, n), a non-positive or non-finite
+ * length, or a null pointer; HGKS_ESTATE for get_state before set_state.
+ * A refused call changes nothing. */
 hgks_status hgks_batch_set_state(hgks_batch b, int32_t i, const double* q_dev);
 hgks_status hgks_batch_get_state(hgks_batch b, int32_t i, double* q_dev_out);
 /* dt_dev[i] = cfl * min over grid i of h / (|U| + c), as hgks_max_dt;

@@ -1094,6 +1094,7 @@ hgks_status hgks_batch_set_state(hgks_batch b, int32_t i, const double* q_dev) {
 hgks_status hgks_batch_get_state(hgks_batch b, int32_t i, double* q_dev_out) {
   if (hgks_status s = busable(b)) return s;
   if (i < 0 || i >= b->ng || !q_dev_out) return fail(HGKS_EINVAL, "bad grid index or output");
+  if (!b->state_set[i]) return fail(HGKS_ESTATE, "grid %d has no state", i);
   const double* src = (const double*)(b->ws + b->q) + batch_qoff(b, i);
   return bcheck(b, hipMemcpyAsync(q_dev_out, src, 5 * batch_N(b, i) * 8, hipMemcpyDeviceToDevice, b->stream),
                 "copy state out");
@@ -1123,7 +1124,8 @@ hgks_status hgks_batch_set_launch(hgks_batch b, int32_t phase, int32_t workgroup
 
 hgks_status hgks_batch_capture(hgks_batch b, double cfl, int32_t n_steps, int32_t n_stages) {
   if (hgks_status s = batch_ready(b)) return s;
-  if (!(cfl > 0.0) || n_steps < 1 || (n_stages != 1 && n_stages != 2)) return fail(HGKS_EINVAL, "bad arguments");
+  if (!(cfl > 0.0) || !std::isfinite(cfl) || n_steps < 1 || (n_stages != 1 && n_stages != 2))
+    return fail(HGKS_EINVAL, "bad arguments");
   if (b->stream == nullptr) return fail(HGKS_EINVAL, "capture needs a non-default stream");
   if (b->exec) {
     hipGraphExecDestroy(b->exec);

@@ -127,3 +127,46 @@ def test_batch_conservation(hg):
     b.sync()
     t1 = np.array(b.totals())
     assert np.abs(t1 - t0).max() < 1e-13 * np.abs(t0).max()
+
+
+def test_batch_call_order_and_arguments(hg):
+    """Refused batch calls return their status, change nothing, and the
+    batch then steps exactly as a fresh one does."""
+    lib = hg.load()
+    qs = states()
+
+    def refused(status, fn, *args):
+        with pytest.raises(hg.HGKSError) as e:
+            fn(*args)
+        assert e.value.status == status, e.value
+
+    b = hg.Batch(GRIDS, precision="fp64")
+    dt = torch.full((b.n,), 1e-3, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    refused(hg.HGKS_ESTATE, b.step, dt, 2)                 # no states yet
+    refused(hg.HGKS_ESTATE, b.max_dt, 0.35, dt)
+    refused(hg.HGKS_ESTATE, b.get_state, 0)
+    for i, q in enumerate(qs[:-1]):
+        b.set_state(i, torch.tensor(q, device="cuda:0"))
+    refused(hg.HGKS_ESTATE, b.step, dt, 2)                 # one grid still without a state
+    b.set_state(len(qs) - 1, torch.tensor(qs[-1], device="cuda:0"))
+    refused(hg.HGKS_EINVAL, b.step, dt, 3)
+    assert lib.hgks_batch_step(b.h, None, 2) == hg.HGKS_EINVAL
+    for cfl in (0.0, -1.0, float("nan"), float("inf")):
+        refused(hg.HGKS_EINVAL, b.max_dt, cfl, dt)
+        refused(hg.HGKS_EINVAL, b.capture, cfl, 2, 2)
+    refused(hg.HGKS_EINVAL, b.capture, 0.35, 0, 2)
+    refused(hg.HGKS_ESTATE, b.replay)                      # nothing captured
+    for phase, wg in ((-1, 0), (99, 0), (1, 12), (1, 4), (1, 1 << 20)):
+        refused(hg.HGKS_EINVAL, b.set_launch, phase, wg)
+    for i in (-1, b.n):
+        refused(hg.HGKS_EINVAL, hg.hgks_batch_set_state, b.h, i, torch.tensor(qs[0], device="cuda:0"))
+        refused(hg.HGKS_EINVAL, hg.hgks_batch_set_uniform_grid, b.h, i, (0, 0, 0), (1, 1, 1))
+    for length in ((0.0, 1.0, 1.0), (1.0, float("inf"), 1.0), (1.0, 1.0, float("nan"))):
+        refused(hg.HGKS_EINVAL, hg.hgks_batch_set_uniform_grid, b.h, 1, (0, 0, 0), length)
+    fresh = make_batch(hg, "fp64", qs)
+    for bb in (b, fresh):
+        bb.max_dt(0.35, dt)
+        bb.step(dt, 2)
+    for i in range(b.n):
+        assert torch.equal(b.get_state(i), fresh.get_state(i)), i
