@@ -348,8 +348,8 @@ def main():
                     help="also copy this many MiB once (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design, see the documentation)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design only, described in the documentation)", file=sys.stderr)
         sys.exit(2)
     import torch
     n = args.n

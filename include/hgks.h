@@ -48,7 +48,7 @@ typedef enum {
   HGKS_EDEVICE = 3,       /* a HIP call failed (sticky per context)         */
   HGKS_ESTATE = 4,        /* call order: e.g. step before set_state         */
   HGKS_ENONPHYS = 5,      /* rho <= 0 or p <= 0 found by a check            */
-  HGKS_EUNSUPPORTED = 6   /* valid request this build does not provide      */
+  HGKS_EUNSUPPORTED = 6   /* valid request the library does not provide     */
 } hgks_status;
 
 /* Boundary conditions of Sec. 4.  OUTFLOW is the non-reflecting condition:
