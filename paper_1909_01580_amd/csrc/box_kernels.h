@@ -603,19 +603,16 @@ __device__ __forceinline__ void eval_char_gp(const TC* cv, const double (&Qbar)[
   constexpr int A = (D + 1) % 3, B = (D + 2) % 3, CB = kCB<TC>;
   constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
   constexpr int cp[9] = {D, A, B, 3 + D, 3 + A, 3 + B, 6 + D, 6 + A, 6 + B};
-  // FP32: all 45 coefficients are requested before the eigenvectors are
-  // formed (the fence keeps the loads there), so that their latency overlaps
-  // it (7% faster).  In FP64 the registers are not there (values would be
-  // spilled, 4% slower), and each field's loads stay with the field.
-  constexpr bool kEarly = sizeof(TC) == 4;
+  // All 45 coefficients are requested before the eigenvectors are formed
+  // (the fence keeps the loads there), so that their latency overlaps it;
+  // the flux forms both sides' states before any side terms, so the
+  // registers for them are there.
   TC call[5][9];
-  if constexpr (kEarly) {
 #pragma unroll
-    for (int f = 0; f < 5; ++f)
+  for (int f = 0; f < 5; ++f)
 #pragma unroll
-      for (int m = 0; m < 9; ++m) call[f][m] = cv[(f * 10 + cp[m] + 1) * CB];
-    asm volatile("" ::: "memory");
-  }
+    for (int m = 0; m < 9; ++m) call[f][m] = cv[(f * 10 + cp[m] + 1) * CB];
+  asm volatile("" ::: "memory");
   CharBasis Bs;
   char_basis(Qbar, D, gamma, Bs);
   TC val[5], grad[5][3];
@@ -629,7 +626,7 @@ __device__ __forceinline__ void eval_char_gp(const TC* cv, const double (&Qbar)[
     for (int f = 0; f < 5; ++f) {
       TC c[9];
 #pragma unroll
-      for (int m = 0; m < 9; ++m) c[m] = kEarly ? call[f][m] : cv[(f * 10 + cp[m] + 1) * CB];
+      for (int m = 0; m < 9; ++m) c[m] = call[f][m];
       TC du, g[3];
       quad_eval(TC(0), c, xD, xA, xB, du, g[0], g[1], g[2]);
       double r[5];
@@ -705,17 +702,14 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     for (int v = 0; v < 5; ++v)
       Qbar[v] = 0.5 * ((double)coefL[coef_cell<TC>(iL) + v * 10 * kCB<TC>] +
                        (double)coefR[coef_cell<TC>(iR) + v * 10 * kCB<TC>]);
-    {
-      TC W[5], dW[3][5];
-      eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, W, dW);
-      side_terms<+1, PR>(W, dW, gp, acc);
-    }
-    after_left_side(iR, acc);
-    {
-      TC W[5], dW[3][5];
-      eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, W, dW);
-      side_terms<-1, PR>(W, dW, gp, acc);
-    }
+    // Both sides' Gauss-point states are formed before any side terms,
+    // while the flux accumulators are not yet live: there are registers for
+    // each side's 45 coefficient loads to be in flight together.
+    TC WL[5], dWL[3][5], WR[5], dWR[3][5];
+    eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, WL, dWL);
+    eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, WR, dWR);
+    side_terms<+1, PR>(WL, dWL, gp, acc);
+    side_terms<-1, PR>(WR, dWR, gp, acc);
   } else {
     {
       TC W[5], dW[3][5];
