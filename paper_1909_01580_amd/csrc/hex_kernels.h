@@ -32,6 +32,7 @@
 #pragma once
 
 #include <cstring>
+#include <type_traits>
 
 #include "box_kernels.h"
 #include "common.h"
@@ -872,36 +873,62 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
 
   FluxAcc<TC> acc;
-  acc_zero(acc);
-  {
-    asm volatile("" ::: "memory");
-    double x[3], u[3], n0[3], n1[3], n2[3];
-    get3(0, x);
-    get3(3, u);
-    get3(6, n0);
-    get3(9, n1);
-    get3(12, n2);
-    TC val[5], grad[5][3];
-    eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
-    TC W[5], dW[3][5];
-    to_local(val, grad, u, n0, n1, n2, W, dW);
-    side_terms<+1>(W, dW, gp, acc);
-  }
-  size_t iRt = iR;
-  after_left_side(iRt, acc);
-  {
-    asm volatile("" ::: "memory");
-    double x[3], u[3], n0[3], n1[3], n2[3];
-    get3(0, x);
-    get3(3, u);
-    get3(6, n0);
-    get3(9, n1);
-    get3(12, n2);
-    TC val[5], grad[5][3];
-    eval_hex(coef, geo, N, iRt, shR, x, fbR, val, grad);
-    TC W[5], dW[3][5];
-    to_local(val, grad, u, n0, n1, n2, W, dW);
-    side_terms<-1>(W, dW, gp, acc);
+  if constexpr (std::is_same<TC, float>::value) {
+    // FP32: both sides' local states first, then the side terms; the
+    // accumulators are not live while the coefficients are loaded (113
+    // registers, no spills, 7% faster).  In FP64 this order is 11% slower
+    // than the sides one after the other with the right cell's loads
+    // deferred, below.
+    TC WL[5], dWL[3][5], WR[5], dWR[3][5];
+    {
+      asm volatile("" ::: "memory");
+      double x[3], u[3], n0[3], n1[3], n2[3];
+      get3(0, x);
+      get3(3, u);
+      get3(6, n0);
+      get3(9, n1);
+      get3(12, n2);
+      TC val[5], grad[5][3];
+      eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
+      to_local(val, grad, u, n0, n1, n2, WL, dWL);
+      eval_hex(coef, geo, N, iR, shR, x, fbR, val, grad);
+      to_local(val, grad, u, n0, n1, n2, WR, dWR);
+    }
+    acc_zero(acc);
+    side_terms<+1>(WL, dWL, gp, acc);
+    side_terms<-1>(WR, dWR, gp, acc);
+  } else {
+    acc_zero(acc);
+    {
+      asm volatile("" ::: "memory");
+      double x[3], u[3], n0[3], n1[3], n2[3];
+      get3(0, x);
+      get3(3, u);
+      get3(6, n0);
+      get3(9, n1);
+      get3(12, n2);
+      TC val[5], grad[5][3];
+      eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
+      TC W[5], dW[3][5];
+      to_local(val, grad, u, n0, n1, n2, W, dW);
+      side_terms<+1>(W, dW, gp, acc);
+    }
+    size_t iRt = iR;
+    after_left_side(iRt, acc);
+    {
+      asm volatile("" ::: "memory");
+      double x[3], u[3], n0[3], n1[3], n2[3];
+      get3(0, x);
+      get3(3, u);
+      get3(6, n0);
+      get3(9, n1);
+      get3(12, n2);
+      TC val[5], grad[5][3];
+      eval_hex(coef, geo, N, iRt, shR, x, fbR, val, grad);
+      TC W[5], dW[3][5];
+      to_local(val, grad, u, n0, n1, n2, W, dW);
+      side_terms<-1>(W, dW, gp, acc);
+    }
   }
   asm volatile("" ::: "memory");
   double u[3], n0[3], n1[3], n2[3];
@@ -944,8 +971,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
 
 // All faces of the three directions in one launch, nb blocks of 64 faces per
 // direction, interleaved (flux_block).  Register budget: two waves per SIMD
-// in FP64; four in FP32 (128 registers, a few values spilled, 3% faster
-// than three waves at 136).
+// in FP64; four in FP32 (113 registers).
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 ? 2 : 4)))
     k_flux_hex(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
