@@ -31,7 +31,11 @@ the oracle and the GPU agree on them by construction only:
 
 * the epsilon of the nonlinear weights (Eq. (3)), default 1e-8;
 * the time-step rule (only the CFL number is printed);
-* the Prandtl number: the BGK flux as written has Pr = 1, no correction;
+* the mechanism that sets the Prandtl number: the BGK flux as written has
+  Pr = 1 and the paper states Pr = 0.71 without saying how; the oracle's
+  heat-flux correction (the one of the gas-kinetic literature) is pinned by
+  its Navier-Stokes limit (Fourier flux with kappa = c_p mu / Pr), not by a
+  printed value;
 * the moving-mesh conservation mechanism (Remark 2) as such, though its
   consequences (free stream to round-off, volume equal to the geometric
   volume) are pinned;
