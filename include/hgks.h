@@ -67,9 +67,12 @@ typedef enum {
 
 typedef enum {
   HGKS_FP64 = 0,  /* every step of the stage in double                        */
-  HGKS_MIXED = 1  /* reconstruction and gas-kinetic flux in float; stencil
-                     differences, face sums, stage accumulation, geometry and
-                     totals in double                                         */
+  HGKS_MIXED = 1  /* reconstruction and gas-kinetic flux in float, and the
+                     face sums (F_p, dF_p) stored in float; in double: the
+                     stencil differences, the stage accumulation of the state,
+                     the hexahedral geometry and least-squares reconstruction
+                     (its quadratics then stored in float), the moving-mesh
+                     volume and its rates, and all totals                     */
 } hgks_prec;
 
 typedef struct {
@@ -107,8 +110,8 @@ typedef struct {
                              is the BGK flux as it stands; otherwise (1/Pr - 1)
                              times the heat flux relative to the interface
                              velocity is added to the energy flux (Sec. 4
-                             gives Pr = 0.71).  Both on box grids only, not
-                             in batches                                      */
+                             gives Pr = 0.71).  Both on box and hexahedral
+                             grids and in batches (per grid)                  */
   int32_t stencil;        /* 0 (default): the big stencil S and 24
                              sub-stencils of Sec. 2; 1: the alternative of
                              Remark 1 (S plus the cells two steps away along
@@ -166,7 +169,11 @@ hgks_status hgks_max_dt(hgks_ctx ctx, double cfl, double* dt_host);
 
 /* One time step of size dt: n_stages = 2 is the two-stage fourth-order
  * scheme of Sec. 3; n_stages = 1 the one-stage update Q + dt L + dt^2/2 dL.
- * Asynchronous. */
+ * Asynchronous: it never waits for the device, so it cannot see the state it
+ * produces and never returns HGKS_ENONPHYS.  A non-physical result is
+ * reported by the next hgks_max_dt (HGKS_ENONPHYS; every CFL-driven loop
+ * calls it before each step), by hgks_check, and by hgks_step_checked,
+ * which rejects such a step. */
 hgks_status hgks_step(hgks_ctx ctx, double dt, int32_t n_stages);
 
 /* hgks_step with step rejection, for static grids: the step is taken with
@@ -192,6 +199,14 @@ hgks_status hgks_totals(hgks_ctx ctx, double out_host[5]);
  * first-order fallback of Sec. 4.  Synchronises the stream. */
 hgks_status hgks_check(hgks_ctx ctx, int64_t* nonphysical_host, int64_t* fallback_host);
 
+/* Volume-averaged kinetic energy of the Taylor-Green test (Sec. 4),
+ * E_k = (1 / (rho0 |Omega|)) int rho |U|^2 / 2, taken on the cell averages:
+ * *ek_host = sum_i |Omega_i| |M_i|^2 / (2 rho_i) / (rho0 sum_i |Omega_i|),
+ * both sums in a fixed order (deterministic), in double.  Its dissipation
+ * rate -dE_k/dt is the difference of two calls over the time between them.
+ * HGKS_EINVAL unless 0 < rho0 < infinity.  Synchronises the stream. */
+hgks_status hgks_kinetic_energy(hgks_ctx ctx, double rho0, double* ek_host);
+
 /* Parity hooks.  Both run one stage-1 reconstruction (and flux) of the
  * current state with time step dt, without changing the state.
  * gp states: [nz][ny][nx][24][5][4] = (value, d/dx, d/dy, d/dz) of each
@@ -201,6 +216,13 @@ hgks_status hgks_check(hgks_ctx ctx, int64_t* nonphysical_host, int64_t* fallbac
  *   face of each cell along x, y, z (Eq. (11) with its time derivative). */
 hgks_status hgks_debug_gp_states(hgks_ctx ctx, double dt, double* dev_out);
 hgks_status hgks_debug_face_flux(hgks_ctx ctx, double dt, double* dev_out);
+
+/* Parity hook of the limiter (Sec. 4): runs one stage-1 reconstruction of
+ * the current state like the hooks above and writes, per cell
+ * ([nz][ny][nx], uint32, device), the fallback word: bit 4*face + g set
+ * where Gauss point g of that face (numbered as in hgks_debug_gp_states)
+ * takes the cell mean and zero gradient; bits 24-31 are zero. */
+hgks_status hgks_debug_fallback_mask(hgks_ctx ctx, double dt, uint32_t* mask_dev_out);
 
 /* Kernel timing by phase.  Between hgks_profile_begin and hgks_profile_end
  * the context records a pair of HIP events on its stream around every
@@ -231,9 +253,11 @@ hgks_status hgks_sync(hgks_ctx ctx);
  * every grid, each grid with its own time step read from device memory, so
  * whole steps can be captured in a HIP graph and replayed.
  *
- * cfgs[i] describes grid i (sizes, mu); every grid must be a uniform box
- * (moving = 0) with all axes periodic, and gamma, weno_Gamma, weno_eps,
- * tau_eps, tau_C and precision must equal those of cfgs[0].  The stream
+ * cfgs[i] describes grid i (sizes, mu, and the viscosity law and Prandtl
+ * number, mu_T0, mu_exponent, prandtl); every grid must be a uniform box
+ * (moving = 0, component-wise reconstruction on the stencils of Sec. 2)
+ * with all axes periodic, and gamma, weno_Gamma, weno_eps, tau_eps, tau_C
+ * and precision must equal those of cfgs[0].  The stream
  * of cfgs[0] is used; it must not be the legacy default stream when
  * hgks_batch_capture is used.  Grid i's state is [5][nz_i][ny_i][nx_i]. */
 hgks_status hgks_batch_workspace_size(const hgks_config* cfgs, int32_t n, size_t* bytes);
@@ -248,24 +272,41 @@ hgks_status hgks_batch_set_uniform_grid(hgks_batch b, int32_t i, const double or
 hgks_status hgks_batch_set_state(hgks_batch b, int32_t i, const double* q_dev);
 hgks_status hgks_batch_get_state(hgks_batch b, int32_t i, double* q_dev_out);
 /* dt_dev[i] = cfl * min over grid i of h / (|U| + c), as hgks_max_dt;
- * asynchronous, dt_dev is a device array of n doubles. */
+ * asynchronous, dt_dev is a device array of n doubles (NULL: the batch's
+ * own array).  A grid with a cell whose density or pressure is not
+ * positive (or not a number) gets dt_dev[i] = 0 and sets the batch's
+ * device status word, which the next hgks_batch_dt or hgks_batch_sync
+ * reports (HGKS_ENONPHYS) and clears. */
 hgks_status hgks_batch_max_dt(hgks_batch b, double cfl, double* dt_dev);
 /* One step of every grid i with time step dt_dev[i] (device array);
- * asynchronous. */
+ * asynchronous.  A grid whose dt_dev[i] is not positive is not advanced
+ * (its state is left as it was). */
 hgks_status hgks_batch_step(hgks_batch b, const double* dt_dev, int32_t n_stages);
 /* Workgroups of the persistent launch of a phase (hgks_phase; a multiple
  * of 8 between 8 and 65536; 0 restores one workgroup per tile). */
 hgks_status hgks_batch_set_launch(hgks_batch b, int32_t phase, int32_t workgroups);
+/* Tile shapes of the batch (the autotuner's second dimension beside the
+ * workgroup counts).  Cell tiles (reconstruction, fallback test, update,
+ * time-step reduction): tile_x = tile_y = tile_z = 0 for 256 consecutive
+ * cells (x fastest, the default), else a tile_x x tile_y x tile_z box of
+ * cells, powers of two with product 256.  Flux tiles are 64 faces of one
+ * direction in the banded cell order; flux_band is its band height in rows
+ * along y (1..256, default 16; capped at each grid's y extent).  Results do
+ * not depend on either.  A captured graph is discarded (capture again). */
+hgks_status hgks_batch_set_tiles(hgks_batch b, int32_t tile_x, int32_t tile_y, int32_t tile_z, int32_t flux_band);
 /* Captures n_steps steps, each preceded by the per-grid time-step
  * reduction into the batch's own dt array, into a HIP graph (replacing a
  * previous one); hgks_batch_replay launches it.  Nothing runs at capture. */
 hgks_status hgks_batch_capture(hgks_batch b, double cfl, int32_t n_steps, int32_t n_stages);
 hgks_status hgks_batch_replay(hgks_batch b);
 /* The batch's own dt array (last reduction of a replayed graph or of
- * hgks_batch_max_dt with dt_dev = NULL); synchronises. */
+ * hgks_batch_max_dt with dt_dev = NULL); synchronises.  Returns
+ * HGKS_ENONPHYS (after filling dt_host) when a reduction since the last
+ * report found a non-physical grid: its dt is 0 and it was not advanced. */
 hgks_status hgks_batch_dt(hgks_batch b, double* dt_host);
 /* out_host[5 i + v] = sum over grid i of |Omega| Q_v; synchronises. */
 hgks_status hgks_batch_totals(hgks_batch b, double* out_host);
+/* Waits for the batch's stream; HGKS_ENONPHYS as hgks_batch_dt. */
 hgks_status hgks_batch_sync(hgks_batch b);
 
 /* Message of the last failing call on this thread ("" if none). */

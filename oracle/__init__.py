@@ -53,5 +53,5 @@ library layout ``[5][nz][ny][nx]`` and transpose at the edge.
 
 from .scheme import (  # noqa: F401
     Params, Problem, uniform_problem, vertex_problem, residual, step,
-    s2o4, max_dt, totals, gp_states, face_fluxes, physical, checked_step,
+    s2o4, max_dt, totals, gp_states, face_fluxes, physical, checked_step, kinetic_energy,
 )

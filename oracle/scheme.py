@@ -436,6 +436,17 @@ def totals(prob, Q_lib):
     return np.array([np.sum(V * Q_lib[v]) for v in range(5)])
 
 
+def kinetic_energy(prob, Q_lib, rho0=1.0):
+    """Volume-averaged kinetic energy of the Taylor-Green test (Sec. 4),
+    E_k = (1 / (rho0 |Omega|)) int rho |U|^2 / 2 dOmega, with the integrand
+    taken on the cell averages: sum_i |Omega_i| |M_i|^2 / (2 rho_i) divided
+    by rho0 sum_i |Omega_i|."""
+    V = stage_volumes(prob)
+    Q = np.asarray(Q_lib, float)
+    ke = 0.5 * (Q[1] ** 2 + Q[2] ** 2 + Q[3] ** 2) / Q[0]
+    return float(np.sum(V * ke) / (rho0 * np.sum(V)))
+
+
 def max_dt(prob, Q_lib, cfl):
     Q = _to_ijk(np.asarray(Q_lib, float))
     P = prob.params

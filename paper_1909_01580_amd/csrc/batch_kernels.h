@@ -4,7 +4,11 @@
 // device memory, so that whole steps can be captured in a HIP graph.
 //
 // Work is cut into tiles of 256 items (cells, or 64 faces x 4 Gauss
-// points); every grid owns a contiguous range of tiles.  A persistent
+// points); every grid owns a contiguous range of tiles.  A cell tile is
+// either 256 consecutive cells (x fastest) or a tx x ty x tz box of cells
+// (tx ty tz = 256), the tile shape the autotuner chooses; a flux tile is 64
+// consecutive faces of one direction in the banded cell order, whose band
+// height is tunable too.  A persistent
 // launch of P workgroups (P a multiple of 8) gives each of the eight XCDs
 // one contiguous eighth of the tile range, walked by its P/8 workgroups
 // with stride P/8, so that neighbouring tiles of a grid share an L2.
@@ -28,7 +32,27 @@ struct BatchGrid {
   unsigned t_flux;     // first flux tile
   unsigned nt_cell;    // cell tiles
   unsigned nt_flux[3]; // flux tiles per direction
+  int ct[3];           // cell tile shape; ct[0] = 0: 256 consecutive cells
+  int nct[3];          // cell tiles per axis (box tiles)
 };
+
+// Cell of lane `lane` in cell tile lt (counted from the grid's first):
+// false for lanes past the grid's extent.
+template <typename TC>
+__device__ __forceinline__ bool batch_cell(const BatchGrid<TC>& b, unsigned lt, unsigned lane, size_t& idx) {
+  if (b.ct[0] == 0) {
+    idx = (size_t)lt * kBlock + lane;
+    return idx < b.N;
+  }
+  const unsigned bx = lt % (unsigned)b.nct[0], r = lt / (unsigned)b.nct[0];
+  const unsigned by = r % (unsigned)b.nct[1], bz = r / (unsigned)b.nct[1];
+  const int i = (int)(bx * b.ct[0] + lane % b.ct[0]);
+  const int j = (int)(by * b.ct[1] + (lane / b.ct[0]) % b.ct[1]);
+  const int k = (int)(bz * b.ct[2] + lane / (b.ct[0] * b.ct[1]));
+  if (i >= b.G.n[0] || j >= b.G.n[1] || k >= b.G.n[2]) return false;
+  idx = ((size_t)k * b.G.n[1] + j) * b.G.n[0] + i;
+  return true;
+}
 
 // Grid owning tile t (binary search over the first-tile table).
 template <typename TC, bool FLUX>
@@ -78,8 +102,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __r
                                                         uint32_t* __restrict__ mask, TC margin, TC gm1) {
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, false>(B, ng, t);
-    const size_t idx = (size_t)(t - B[g].t_cell) * kBlock + threadIdx.x;
-    if (idx < B[g].N)
+    size_t idx;
+    if (batch_cell(B[g], t - B[g].t_cell, threadIdx.x, idx))
       recon_box_cell(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin, gm1,
                      B[g].N, idx);
   });
@@ -91,19 +115,22 @@ __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __r
                                                         TC gm1) {
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, false>(B, ng, t);
-    const size_t idx = (size_t)(t - B[g].t_cell) * kBlock + threadIdx.x;
-    if (idx < B[g].N && mask[B[g].mask_off + idx] == kNeedsCheck)
+    size_t idx;
+    if (batch_cell(B[g], t - B[g].t_cell, threadIdx.x, idx) && mask[B[g].mask_off + idx] == kNeedsCheck)
       posit_exact_box_cell(q + B[g].q_off, mask + B[g].mask_off, B[g].G, gm1, idx);
   });
 }
 
-template <typename TC, bool LOOP>
+// PR: the extended viscous model (viscosity law, Prandtl correction), per
+// grid through its gas parameters (trivial for grids that use neither).
+template <typename TC, bool LOOP, bool PR = false>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
     k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles, const TC* __restrict__ coef,
                  const uint32_t* __restrict__ mask, TC* __restrict__ face, const double* __restrict__ dt) {
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, true>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
+    if (!(dt[g] > 0.0)) return;  // a grid without a time step is not advanced
     unsigned lt;
     const TC dtg = TC(dt[g]);
     const TC idtg = TC(1.0 / dt[g]);
@@ -112,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
     const unsigned nb[3] = {b.nt_flux[0], b.nt_flux[1], b.nt_flux[2]};
     int D;
     flux_block(t - b.t_flux, nb, D, lt);
-    flux_box_face(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D);
+    flux_box_face<TC, PR>(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D);
   });
 }
 
@@ -124,8 +151,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_update(const BatchGrid<TC>* __
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, false>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
-    const size_t idx = (size_t)(t - b.t_cell) * kBlock + threadIdx.x;
-    if (idx < b.N)
+    size_t idx;
+    if (batch_cell(b, t - b.t_cell, threadIdx.x, idx) && dt[g] > 0.0)
       update_box_cell(q + b.q_off, qs + b.q_off, acc + b.q_off, face + b.face_off[0], face + b.face_off[1],
                       face + b.face_off[2], b.G, dt[g], mode, b.N, idx);
   });
@@ -140,9 +167,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_dt_part(const BatchGrid<TC>* _
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, false>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
-    const size_t idx = (size_t)(t - b.t_cell) * kBlock + threadIdx.x;
+    size_t idx;
     double v = 1e300;
-    if (idx < b.N) {
+    if (batch_cell(b, t - b.t_cell, threadIdx.x, idx)) {
       const double* qg = q + b.q_off;
       const size_t N = b.N;
       const double rho = qg[idx];
@@ -159,16 +186,23 @@ __global__ void __launch_bounds__(kBlock) k_batch_dt_part(const BatchGrid<TC>* _
   });
 }
 
+// A grid with a non-physical cell (density or pressure not positive, or
+// NaN: the per-cell bound is then -1) gets dt = 0, which the flux and update
+// kernels take as "do not advance", and sets bit 0 of *status.
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) k_batch_dt_final(const BatchGrid<TC>* __restrict__ B,
                                                            const double* __restrict__ part, double cfl,
-                                                           double* __restrict__ dt) {
+                                                           double* __restrict__ dt, uint32_t* __restrict__ status) {
   __shared__ double sh[kBlock];
   const int g = blockIdx.x;
   double v = 1e300;
   for (unsigned t = threadIdx.x; t < B[g].nt_cell; t += kBlock) v = fmin(v, part[B[g].t_cell + t]);
   const double r = block_reduce(v, sh, MinOp());
-  if (threadIdx.x == 0) dt[g] = cfl * r;
+  if (threadIdx.x == 0) {
+    const bool ok = r > 0.0;
+    dt[g] = ok ? cfl * r : 0.0;
+    if (!ok) atomicOr(status, 1u);
+  }
 }
 
 // sum |Omega| Q_v per grid, fixed order.

@@ -70,14 +70,15 @@ HGKS_FN void split_index(uint32_t k, int e0, int e1, double i0, double i1, int& 
 // band * n0 cells earlier in that order, close enough to be found in L2.
 constexpr int kFluxBand = 16;
 
-// Fills the reciprocals of a grid whose extents are set.
-inline void set_index_split(BoxGrid& G) {
+// Fills the reciprocals of a grid whose extents are set; `band` rows per
+// band of the flux block order (at most the grid's y extent).
+inline void set_index_split(BoxGrid& G, int band = kFluxBand) {
   for (int a = 0; a < 2; ++a) {
     G.inv_n[a] = div_inv(G.n[a]);
     G.inv_nr[a] = div_inv(G.nr[a]);
     for (int d = 0; d < 3; ++d) G.inv_nf[d][a] = div_inv(G.nf[d][a]);
   }
-  G.band = G.n[1] < kFluxBand ? G.n[1] : kFluxBand;
+  G.band = G.n[1] < band ? G.n[1] : band;
   G.band_full = G.n[1] / G.band;
   G.band_tail = G.n[1] - G.band_full * G.band;
   G.inv_band[0] = div_inv(G.n[0] * G.band * G.n[2]);
@@ -901,6 +902,29 @@ __global__ void __launch_bounds__(kBlock) k_totals_box(const double* __restrict_
   }
 }
 
+// Kinetic energy of the cell averages, sum |Omega_i| |M_i|^2 / (2 rho_i)
+// (the integrand of the volume-averaged kinetic energy of Sec. 4, Taylor-
+// Green vortex, taken on the cell averages), and the volume sum |Omega_i|,
+// per block in a fixed order.  geo = null: every cell has volume vol; else
+// the hexahedral geometry record, whose first row is the cell volume.
+__global__ void __launch_bounds__(kBlock) k_kinetic(const double* __restrict__ q, const double* __restrict__ geo,
+                                                    double vol, double* __restrict__ part, size_t N, int nblk) {
+  __shared__ double sh[kBlock];
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  double e = 0.0, v = 0.0;
+  if (idx < N) {
+    const double V = geo ? geo[idx] : vol;
+    const double m2 = q[N + idx] * q[N + idx] + q[2 * N + idx] * q[2 * N + idx] + q[3 * N + idx] * q[3 * N + idx];
+    e = V * 0.5 * m2 / q[idx];
+    v = V;
+  }
+  const double r1 = block_reduce(e, sh, SumOp());
+  if (threadIdx.x == 0) part[blockIdx.x] = r1;
+  __syncthreads();
+  const double r2 = block_reduce(v, sh, SumOp());
+  if (threadIdx.x == 0) part[(size_t)nblk + blockIdx.x] = r2;
+}
+
 __global__ void __launch_bounds__(kBlock) k_sum_final(const double* __restrict__ part, int n, int nvec,
                                                       double* __restrict__ out) {
   __shared__ double sh[kBlock];
@@ -1014,6 +1038,23 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_box(const TC* __restrict__ 
       o[3] = (double)g[2] * G.inv_dx[2];
     }
   }
+}
+
+// Fallback mask words of the real cells, [nz][ny][nx]: bit 4 f + g set where
+// Gauss point g of face f took the first-order fallback (the "needs the
+// exact test" bit is clear after a stage).  rec = 1: box grid (masks over
+// the reconstruction box); rec = 0: one mask per cell (hexahedral grids).
+__global__ void __launch_bounds__(kBlock) k_debug_mask(const uint32_t* __restrict__ mask, BoxGrid G, int rec,
+                                                       size_t N, uint32_t* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= N) return;
+  size_t r = idx;
+  if (rec) {
+    const int c0 = (int)(idx % G.n[0]), c1 = (int)((idx / G.n[0]) % G.n[1]);
+    const int c2 = (int)(idx / ((size_t)G.n[0] * G.n[1]));
+    r = ((size_t)(c2 + G.g[2]) * G.nr[1] + (c1 + G.g[1])) * G.nr[0] + (c0 + G.g[0]);
+  }
+  out[idx] = mask[r] & 0x00FFFFFFu;
 }
 
 template <typename TF>

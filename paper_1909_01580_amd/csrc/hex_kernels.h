@@ -41,7 +41,10 @@
 namespace hgks {
 
 constexpr int kHexGeo = 12;
-constexpr int kHexFace = 12;  // F (5), dF (5), R_V, dR_V
+// Face record: F (5) and dF (5) in the compute type; the volume rates R_V
+// and dR_V in double in a side array of their own (the moving-mesh volume
+// stays FP64 in every precision mode).
+constexpr int kHexFace = 10;
 
 struct HexGrid {
   int n[3];
@@ -806,11 +809,13 @@ __device__ __forceinline__ void to_global(const double (&f)[5], const double (&u
 // One lane = one Gauss point of one face normal to axis D (uniform over the
 // workgroup); lane l of block lb takes Gauss point l % 4 of face slot l / 4
 // in the flux block order of the box kernels (face_of_block).
-template <typename TC>
+// PR: the extended viscous model (viscosity law, Prandtl correction).
+template <typename TC, bool PR = false>
 __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __restrict__ coef,
                                               const double* __restrict__ geo, const uint32_t* __restrict__ mask,
-                                              TC* __restrict__ face, const GasParams<TC>& gp, TC dt, TC idt, size_t N,
-                                              unsigned lb, int D, double (&stash)[18][kBlock]) {
+                                              TC* __restrict__ face, double* __restrict__ vface,
+                                              const GasParams<TC>& gp, TC dt, TC idt, size_t N, unsigned lb, int D,
+                                              double (&stash)[18][kBlock]) {
   const int gpi = (int)(threadIdx.x & 3);
   int c[3];
   size_t f;
@@ -895,8 +900,8 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       to_local(val, grad, u, n0, n1, n2, WR, dWR);
     }
     acc_zero(acc);
-    side_terms<+1>(WL, dWL, gp, acc);
-    side_terms<-1>(WR, dWR, gp, acc);
+    side_terms<+1, PR>(WL, dWL, gp, acc);
+    side_terms<-1, PR>(WR, dWR, gp, acc);
   } else {
     acc_zero(acc);
     {
@@ -911,7 +916,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
       TC W[5], dW[3][5];
       to_local(val, grad, u, n0, n1, n2, W, dW);
-      side_terms<+1>(W, dW, gp, acc);
+      side_terms<+1, PR>(W, dW, gp, acc);
     }
     size_t iRt = iR;
     after_left_side(iRt, acc);
@@ -927,7 +932,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       eval_hex(coef, geo, N, iRt, shR, x, fbR, val, grad);
       TC W[5], dW[3][5];
       to_local(val, grad, u, n0, n1, n2, W, dW);
-      side_terms<-1>(W, dW, gp, acc);
+      side_terms<-1, PR>(W, dW, gp, acc);
     }
   }
   asm volatile("" ::: "memory");
@@ -938,7 +943,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   get3(12, n2);
   const double area2 = gs[15 * kBlock], rate = gs[16 * kBlock], vrate = gs[17 * kBlock];
   TC Fl[5], dFl[5];
-  finish_flux(acc, gp, dt, idt, Fl, dFl);
+  finish_flux<PR>(acc, gp, dt, idt, Fl, dFl);
   double fl[5], dfl[5], q0l[5];
 #pragma unroll
   for (int e = 0; e < 5; ++e) {
@@ -965,18 +970,21 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   }
   if (live && gpi == 0) {
 #pragma unroll
-    for (int e = 0; e < 12; ++e) face[(size_t)e * N + f] = TC(out[e]);
+    for (int e = 0; e < 10; ++e) face[(size_t)e * N + f] = TC(out[e]);
+    vface[f] = out[10];
+    vface[N + f] = out[11];
   }
 }
 
 // All faces of the three directions in one launch, nb blocks of 64 faces per
 // direction, interleaved (flux_block).  Register budget: two waves per SIMD
 // in FP64; four in FP32 (113 registers).
-template <typename TC>
+template <typename TC, bool PR = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 ? 2 : 4)))
     k_flux_hex(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
                const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
-               GasParams<TC> gp, TC dt, TC idt, size_t N, unsigned nb) {
+               double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz, GasParams<TC> gp, TC dt,
+               TC idt, size_t N, unsigned nb) {
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= 3 * nb) return;
   const unsigned nbs[3] = {nb, nb, nb};
@@ -984,8 +992,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
   unsigned lb;
   flux_block(b, nbs, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
+  double* vface = D == 0 ? vx : (D == 1 ? vy : vz);
   __shared__ double stash[18][kBlock];
-  flux_hex_face(H, coef, geo, mask, face, gp, dt, idt, N, lb, D, stash);
+  flux_hex_face<TC, PR>(H, coef, geo, mask, face, vface, gp, dt, idt, N, lb, D, stash);
 }
 
 // ---------------------------------------------------------------- K4
@@ -997,12 +1006,14 @@ __global__ void __launch_bounds__(kBlock) k_update_hex(HexGrid H, double* __rest
                                                        double* __restrict__ acc, double* __restrict__ vacc,
                                                        const double* __restrict__ geo, const TF* __restrict__ fx,
                                                        const TF* __restrict__ fy, const TF* __restrict__ fz,
-                                                       double dt, int mode, size_t N) {
+                                                       const double* __restrict__ vx, const double* __restrict__ vy,
+                                                       const double* __restrict__ vz, double dt, int mode, size_t N) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
   int c[3];
   split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], c[0], c[1], c[2]);
   const TF* fs[3] = {fx, fy, fz};
+  const double* vs[3] = {vx, vy, vz};
   double R[12];
 #pragma unroll
   for (int e = 0; e < 12; ++e) R[e] = 0.0;
@@ -1013,8 +1024,8 @@ __global__ void __launch_bounds__(kBlock) k_update_hex(HexGrid H, double* __rest
     const size_t hi_i = ((size_t)hi[2] * H.n[1] + hi[1]) * H.n[0] + hi[0];
 #pragma unroll
     for (int e = 0; e < 10; ++e) R[e] -= (double)fs[d][e * N + hi_i] - (double)fs[d][e * N + idx];
-    R[10] += (double)fs[d][10 * N + hi_i] - (double)fs[d][10 * N + idx];
-    R[11] += (double)fs[d][11 * N + hi_i] - (double)fs[d][11 * N + idx];
+    R[10] += vs[d][hi_i] - vs[d][idx];
+    R[11] += vs[d][N + hi_i] - vs[d][N + idx];
   }
   if (mode == 2) {
     const double Vn = vacc[idx] + dt * dt / 3.0 * R[11];

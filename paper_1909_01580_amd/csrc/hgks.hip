@@ -3,6 +3,7 @@
 // fourth-order scheme).  The C ABI is declared in include/hgks.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -39,7 +40,7 @@ unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 unsigned pad8(unsigned nb) { return (nb + 7u) & ~7u; }
 
 struct Layout {
-  size_t q, qs, acc, back, coef, mask, plist, face[3], red, geo, verts, vnext, vol, vacc, total;
+  size_t q, qs, acc, back, coef, mask, plist, face[3], vface[3], red, geo, verts, vnext, vol, vacc, total;
 };
 
 struct Dims {
@@ -69,8 +70,6 @@ bool valid_config(const hgks_config* c) {
   if (c->characteristic && c->moving) return false;
   if (!(c->mu_T0 > 0.0) || !std::isfinite(c->mu_exponent) || !(c->prandtl > 0.0) || !std::isfinite(c->prandtl))
     return false;
-  // the viscosity law and the Prandtl correction are offered on box grids
-  if (c->moving && (c->mu_exponent != 0.0 || c->prandtl != 1.0)) return false;
   // the stencils of Remark 1: box grids, component-wise reconstruction; a
   // mirror two cells past the ghost layer needs three cells on that axis
   if (c->stencil != 0 && c->stencil != 1) return false;
@@ -131,8 +130,9 @@ Layout make_layout(const hgks_config* c, const Dims& D) {
   L.mask = take(D.NR * sizeof(uint32_t));
   // list of the cells the exact positivity test examines, and its counter
   L.plist = c->moving ? 0 : take((D.NR + 64) * sizeof(uint32_t));
-  const size_t nface = c->moving ? 12 : 10;
-  for (int d = 0; d < 3; ++d) L.face[d] = take(nface * D.NF[d] * tc);
+  for (int d = 0; d < 3; ++d) L.face[d] = take(10 * D.NF[d] * tc);
+  // volume rates R_V, dR_V of the moving faces, double in every mode
+  for (int d = 0; d < 3; ++d) L.vface[d] = c->moving ? take(2 * D.NF[d] * sizeof(double)) : 0;
   L.red = take(D.nred * sizeof(double));
   if (c->moving) {
     L.geo = take((size_t)kHexGeo * D.N * sizeof(double));
@@ -175,6 +175,7 @@ struct hgks_ctx_s {
   uint32_t* mask() { return (uint32_t*)(ws + L.mask); }
   uint32_t* plist() { return (uint32_t*)(ws + L.plist); }
   void* face(int d) { return ws + L.face[d]; }
+  double* vface(int d) { return (double*)(ws + L.vface[d]); }
   double* red() { return (double*)(ws + L.red); }
   double* geo() { return (double*)(ws + L.geo); }
   double* verts() { return (double*)(ws + L.verts); }
@@ -394,9 +395,15 @@ hgks_status hex_stage(hgks_ctx c, const double* qin, double dt, double alpha) {
   if (hgks_status s = launched(c, "positivity")) return s;
   const unsigned nb = blocks_for(4 * N);
   prof_mark(c, HGKS_PHASE_FLUX, true);
-  hipLaunchKernelGGL((k_flux_hex<TC>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H, (const TC*)c->coef(),
-                     c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), gp, TC(dt),
-                     TC(1.0 / dt), N, nb);
+  // the extended viscous model is a compile-time variant
+  if (c->cfg.prandtl != 1.0 || c->cfg.mu_exponent != 0.0)
+    hipLaunchKernelGGL((k_flux_hex<TC, true>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H,
+                       (const TC*)c->coef(), c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2),
+                       c->vface(0), c->vface(1), c->vface(2), gp, TC(dt), TC(1.0 / dt), N, nb);
+  else
+    hipLaunchKernelGGL((k_flux_hex<TC>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H, (const TC*)c->coef(),
+                       c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->vface(0),
+                       c->vface(1), c->vface(2), gp, TC(dt), TC(1.0 / dt), N, nb);
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
@@ -407,7 +414,7 @@ hgks_status hex_update(hgks_ctx c, double dt, int mode) {
   prof_mark(c, HGKS_PHASE_UPDATE, true);
   hipLaunchKernelGGL((k_update_hex<TF>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H, c->q(), c->qs(),
                      c->acc(), c->vacc(), c->geo(), (const TF*)c->face(0), (const TF*)c->face(1),
-                     (const TF*)c->face(2), dt, mode, c->D.N);
+                     (const TF*)c->face(2), c->vface(0), c->vface(1), c->vface(2), dt, mode, c->D.N);
   prof_mark(c, HGKS_PHASE_UPDATE, false);
   return launched(c, "update");
 }
@@ -472,6 +479,48 @@ hgks_status hex_debug_face(hgks_ctx c, double dt, double* out) {
   return launched(c, "debug face");
 }
 
+// Context fields from a valid configuration and a workspace base (no
+// device work, no device allocation).
+void init_ctx(hgks_ctx c, const hgks_config* cfg, char* ws) {
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)cfg->stream;
+  c->D = make_dims(cfg);
+  c->L = make_layout(cfg, c->D);
+  c->ws = ws;
+  std::memset(&c->G, 0, sizeof c->G);
+  for (int d = 0; d < 3; ++d) {
+    c->G.n[d] = c->D.n[d];
+    c->G.g[d] = c->D.g[d];
+    c->G.nr[d] = c->D.nr[d];
+    c->G.per[d] = c->D.per[d];
+    c->G.sym[d][0] = c->D.sym[d][0];
+    c->G.sym[d][1] = c->D.sym[d][1];
+    for (int e = 0; e < 3; ++e) c->G.nf[d][e] = c->D.nf[d][e];
+  }
+  set_index_split(c->G);
+  if (cfg->characteristic) c->G.fs_stride = coef_elems(c->D.NR, c->mixed() ? sizeof(float) : sizeof(double));
+  std::memset(&c->H, 0, sizeof c->H);
+}
+
+// Uniform box geometry; all three axes are checked before anything is set,
+// so a refused call leaves the grid as it was.
+hgks_status set_box(hgks_ctx c, const double origin[3], const double length[3]) {
+  if (!origin || !length) return fail(HGKS_EINVAL, "null origin or length");
+  for (int d = 0; d < 3; ++d)
+    if (!(length[d] > 0.0) || !std::isfinite(length[d]) || !std::isfinite(origin[d]))
+      return fail(HGKS_EINVAL, "bad box");
+  double vol = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    const double h = length[d] / c->D.n[d];
+    c->G.inv_dx[d] = 1.0 / h;
+    vol *= h;
+  }
+  for (int d = 0; d < 3; ++d) c->G.wface[d] = 0.25 * vol * c->G.inv_dx[d];
+  c->G.vol = vol;
+  c->grid_set = true;
+  return HGKS_OK;
+}
+
 hgks_status sync_copy(hgks_ctx c, void* dst, const void* src, size_t bytes) {
   if (hgks_status s = check_hip(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream), "copy"))
     return s;
@@ -516,28 +565,12 @@ hgks_status hgks_create(const hgks_config* cfg, void* workspace_dev, size_t byte
   if (!workspace_dev || ((uintptr_t)workspace_dev & 255u)) return fail(HGKS_EINVAL, "workspace must be 256-byte aligned");
   hgks_ctx c = new (std::nothrow) hgks_ctx_s;
   if (!c) return fail(HGKS_ENOMEM, "host allocation failed");
-  c->cfg = *cfg;
-  c->stream = (hipStream_t)cfg->stream;
-  c->D = make_dims(cfg);
-  c->L = make_layout(cfg, c->D);
+  init_ctx(c, cfg, (char*)workspace_dev);
   if (bytes < c->L.total) {
+    const size_t need = c->L.total;
     delete c;
-    return fail(HGKS_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, c->L.total);
+    return fail(HGKS_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, need);
   }
-  c->ws = (char*)workspace_dev;
-  std::memset(&c->G, 0, sizeof c->G);
-  for (int d = 0; d < 3; ++d) {
-    c->G.n[d] = c->D.n[d];
-    c->G.g[d] = c->D.g[d];
-    c->G.nr[d] = c->D.nr[d];
-    c->G.per[d] = c->D.per[d];
-    c->G.sym[d][0] = c->D.sym[d][0];
-    c->G.sym[d][1] = c->D.sym[d][1];
-    for (int e = 0; e < 3; ++e) c->G.nf[d][e] = c->D.nf[d][e];
-  }
-  set_index_split(c->G);
-  if (cfg->characteristic) c->G.fs_stride = coef_elems(c->D.NR, c->mixed() ? sizeof(float) : sizeof(double));
-  std::memset(&c->H, 0, sizeof c->H);
   *out = c;
   return HGKS_OK;
 }
@@ -553,22 +586,7 @@ hgks_status hgks_destroy(hgks_ctx ctx) {
 hgks_status hgks_set_uniform_grid(hgks_ctx c, const double origin[3], const double length[3]) {
   if (hgks_status s = usable(c)) return s;
   if (c->cfg.moving) return fail(HGKS_EINVAL, "context expects vertices (moving = 1)");
-  if (!origin || !length) return fail(HGKS_EINVAL, "null origin or length");
-  // all three axes are checked before anything is set: a refused call
-  // leaves the grid as it was
-  for (int d = 0; d < 3; ++d)
-    if (!(length[d] > 0.0) || !std::isfinite(length[d]) || !std::isfinite(origin[d]))
-      return fail(HGKS_EINVAL, "bad box");
-  double vol = 1.0;
-  for (int d = 0; d < 3; ++d) {
-    const double h = length[d] / c->D.n[d];
-    c->G.inv_dx[d] = 1.0 / h;
-    vol *= h;
-  }
-  for (int d = 0; d < 3; ++d) c->G.wface[d] = 0.25 * vol * c->G.inv_dx[d];
-  c->G.vol = vol;
-  c->grid_set = true;
-  return HGKS_OK;
+  return set_box(c, origin, length);
 }
 
 hgks_status hgks_set_vertices(hgks_ctx c, const double* xyz_dev, const double period[3]) {
@@ -719,6 +737,40 @@ hgks_status hgks_check(hgks_ctx c, int64_t* nonphys, int64_t* fallback) {
   return HGKS_OK;
 }
 
+hgks_status hgks_kinetic_energy(hgks_ctx c, double rho0, double* ek_host) {
+  if (hgks_status s = ready(c)) return s;
+  if (!ek_host || !(rho0 > 0.0) || !std::isfinite(rho0)) return fail(HGKS_EINVAL, "bad rho0 or output");
+  const unsigned nb = blocks_for(c->D.N);
+  double* part = c->red();
+  const double* geo = nullptr;
+  if (c->cfg.moving) {
+    // the geometry record of the current vertices
+    if (hgks_status s = hex_geometry(c, hex_grid(c, 0.0, 0.0, false))) return s;
+    geo = c->geo();
+  }
+  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), geo, c->G.vol, part, c->D.N, (int)nb);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, c->stream, part, (int)nb, 2, part + c->D.nred - 8);
+  if (hgks_status s = launched(c, "kinetic energy")) return s;
+  double r[2];
+  if (hgks_status s = sync_copy(c, r, part + c->D.nred - 8, 2 * sizeof(double))) return s;
+  *ek_host = r[0] / (rho0 * r[1]);
+  return HGKS_OK;
+}
+
+hgks_status hgks_debug_fallback_mask(hgks_ctx c, double dt, uint32_t* mask_dev_out) {
+  if (hgks_status s = ready(c)) return s;
+  if (!mask_dev_out || !(dt > 0.0) || !std::isfinite(dt)) return fail(HGKS_EINVAL, "bad arguments");
+  hgks_status s;
+  if (c->cfg.moving)
+    s = c->mixed() ? hex_stage<float>(c, c->q(), dt, 0.0) : hex_stage<double>(c, c->q(), dt, 0.0);
+  else
+    s = c->mixed() ? box_stage<float>(c, c->q(), dt) : box_stage<double>(c, c->q(), dt);
+  if (s) return s;
+  hipLaunchKernelGGL(k_debug_mask, dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, c->mask(), c->G,
+                     c->cfg.moving ? 0 : 1, c->D.N, mask_dev_out);
+  return launched(c, "debug mask");
+}
+
 hgks_status hgks_debug_gp_states(hgks_ctx c, double dt, double* out) {
   if (hgks_status s = ready(c)) return s;
   if (!out || !(dt > 0.0)) return fail(HGKS_EINVAL, "bad arguments");
@@ -804,9 +856,13 @@ struct hgks_batch_s {
   int ng = 0;
   hipStream_t stream;
   char* ws = nullptr;
-  size_t desc = 0, q = 0, qs = 0, acc = 0, coef = 0, mask = 0, face = 0, part = 0, dt = 0, tot = 0, total = 0;
+  size_t desc = 0, q = 0, qs = 0, acc = 0, coef = 0, mask = 0, face = 0, part = 0, dt = 0, tot = 0, status = 0,
+         total = 0;
   size_t tc = 8;
   unsigned tiles_cell = 0, tiles_flux = 0;
+  int ct[3] = {0, 0, 0};   // cell tile shape (0: 256 consecutive cells)
+  int band = kFluxBand;    // rows per band of the flux block order
+  bool ext = false;  // some grid uses the viscosity law or the Prandtl correction
   std::vector<BatchGrid<double>> gd;  // host copies of the descriptors
   std::vector<BatchGrid<float>> gf;
   std::vector<bool> grid_set, state_set;
@@ -832,8 +888,7 @@ hgks_status busable(hgks_batch b) {
 }
 
 bool batch_compatible(const hgks_config& a, const hgks_config& c) {
-  if (!valid_config(&c) || c.moving || c.characteristic || c.mu_exponent != 0.0 || c.prandtl != 1.0 || c.stencil)
-    return false;
+  if (!valid_config(&c) || c.moving || c.characteristic || c.stencil) return false;
   for (int d = 0; d < 3; ++d)
     if (c.bc[d] != HGKS_BC_PERIODIC) return false;
   return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&
@@ -842,11 +897,67 @@ bool batch_compatible(const hgks_config& a, const hgks_config& c) {
 
 // Offsets of every arena and the per-grid descriptors (without the grid
 // spacing, set later).
+// Cell tiles of a grid of extents n for tile shape ct (ct[0] = 0: 256
+// consecutive cells); nct receives the tiles per axis of a box shape.
+unsigned cell_tiles(const int n[3], const int ct[3], int nct[3]) {
+  if (ct[0] == 0) {
+    nct[0] = nct[1] = nct[2] = 0;
+    return blocks_for((size_t)n[0] * n[1] * n[2]);
+  }
+  for (int d = 0; d < 3; ++d) nct[d] = (n[d] + ct[d] - 1) / ct[d];
+  return (unsigned)nct[0] * nct[1] * nct[2];
+}
+
+// A valid cell tile shape: 0 x 0 x 0 (consecutive cells) or powers of two
+// with tx ty tz = 256.
+bool valid_tile(const int ct[3]) {
+  if (ct[0] == 0 && ct[1] == 0 && ct[2] == 0) return true;
+  for (int d = 0; d < 3; ++d)
+    if (ct[d] < 1 || ct[d] > kBlock || (ct[d] & (ct[d] - 1))) return false;
+  return ct[0] * ct[1] * ct[2] == kBlock;
+}
+
+// Largest cell-tile count of a grid over every valid shape (the size of the
+// per-tile reduction scratch).
+unsigned max_cell_tiles(const int n[3]) {
+  int ct[3] = {0, 0, 0}, nct[3];
+  unsigned m = cell_tiles(n, ct, nct);
+  for (int a = 1; a <= kBlock; a *= 2)
+    for (int c = 1; a * c <= kBlock; c *= 2) {
+      const int sh[3] = {a, c, kBlock / (a * c)};
+      m = std::max(m, cell_tiles(n, sh, nct));
+    }
+  return m;
+}
+
+// Cell and flux tiles of every grid for the batch's tile shape and flux
+// band height (descriptors on the host; the caller uploads them).
+template <typename TC>
+void batch_tiles(std::vector<BatchGrid<TC>>& G, const int ct[3], int band, unsigned& tiles_cell,
+                 unsigned& tiles_flux) {
+  unsigned tc = 0, tf = 0;
+  for (auto& g : G) {
+    set_index_split(g.G, band);
+    for (int d = 0; d < 3; ++d) g.ct[d] = ct[d];
+    g.t_cell = tc;
+    g.nt_cell = cell_tiles(g.G.n, ct, g.nct);
+    tc += g.nt_cell;
+    g.t_flux = tf;
+    unsigned nb[3];
+    flux_block_counts(g.G, nb);
+    for (int d = 0; d < 3; ++d) {
+      g.nt_flux[d] = nb[d];
+      tf += nb[d];
+    }
+  }
+  tiles_cell = tc;
+  tiles_flux = tf;
+}
+
 template <typename TC>
 size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<BatchGrid<TC>>& G) {
   G.assign(n, BatchGrid<TC>());
-  size_t N = 0, F = 0, C = 0;
-  unsigned tc = 0, tf = 0;
+  size_t N = 0, F = 0, C = 0, tmax = 0;
   for (int i = 0; i < n; ++i) {
     const Dims D = make_dims(&cfgs[i]);
     BatchGrid<TC>& g = G[i];
@@ -858,24 +969,16 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
       g.G.per[d] = 1;
       for (int e = 0; e < 3; ++e) g.G.nf[d][e] = D.nf[d][e];
     }
-    set_index_split(g.G);
     g.N = D.N;
     g.q_off = 5 * N;
     g.coef_off = C;
     g.mask_off = N;
-    g.t_cell = tc;
-    g.t_flux = tf;
-    g.nt_cell = blocks_for(D.N);
-    unsigned nb[3];
-    flux_block_counts(g.G, nb);
     for (int d = 0; d < 3; ++d) {
       g.NF[d] = D.NF[d];
       g.face_off[d] = F;
       F += 10 * D.NF[d];
-      g.nt_flux[d] = nb[d];
-      tf += g.nt_flux[d];
     }
-    tc += g.nt_cell;
+    tmax += max_cell_tiles(D.n);
     N += D.N;
     C += coef_elems(D.N, sizeof(TC));
     g.gp = gas_params<TC>(cfgs[i]);
@@ -886,17 +989,22 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
     off += align256(bytes);
     return o;
   };
-  if (b) {
-    b->tiles_cell = tc;
-    b->tiles_flux = tf;
+  {
+    const int lin[3] = {0, 0, 0};
+    unsigned tc, tf;
+    batch_tiles(G, b ? b->ct : lin, b ? b->band : kFluxBand, tc, tf);
+    if (b) {
+      b->tiles_cell = tc;
+      b->tiles_flux = tf;
+    }
   }
   const size_t desc = take(n * sizeof(BatchGrid<TC>));
   const size_t q = take(5 * N * 8), qs = take(5 * N * 8), acc = take(5 * N * 8);
   const size_t coef = take(C * sizeof(TC)), mask = take(N * 4), face = take(F * sizeof(TC));
-  const size_t part = take((size_t)tc * 8), dt = take(n * 8), tot = take(5 * n * 8);
+  const size_t part = take(tmax * 8), dt = take(n * 8), tot = take(5 * n * 8), status = take(4);
   if (b) {
     b->desc = desc; b->q = q; b->qs = qs; b->acc = acc; b->coef = coef; b->mask = mask; b->face = face;
-    b->part = part; b->dt = dt; b->tot = tot; b->total = off;
+    b->part = part; b->dt = dt; b->tot = tot; b->status = status; b->total = off;
   }
   return off;
 }
@@ -942,7 +1050,8 @@ hgks_status batch_dt(hgks_batch b, double cfl, double* dt_dev) {
   HGKS_BATCH_LAUNCH(k_batch_dt_part, TC, batch_loop(b, HGKS_PHASE_REDUCE),
                     batch_wg(b, HGKS_PHASE_REDUCE, b->tiles_cell), b->stream, D, b->ng, b->tiles_cell,
                     (const double*)(b->ws + b->q), b->base.gamma, part);
-  hipLaunchKernelGGL((k_batch_dt_final<TC>), dim3(b->ng), dim3(kBlock), 0, b->stream, D, part, cfl, dt_dev);
+  hipLaunchKernelGGL((k_batch_dt_final<TC>), dim3(b->ng), dim3(kBlock), 0, b->stream, D, part, cfl, dt_dev,
+                     (uint32_t*)(b->ws + b->status));
   return bcheck(b, hipGetLastError(), "batch dt");
 }
 
@@ -958,9 +1067,14 @@ hgks_status batch_stage(hgks_batch b, const double* qin, const double* dt_dev) {
   HGKS_BATCH_LAUNCH(k_batch_posit, TC, batch_loop(b, HGKS_PHASE_FALLBACK),
                     batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell), b->stream, D, b->ng, b->tiles_cell, qin, mask,
                     gm1);
-  HGKS_BATCH_LAUNCH(k_batch_flux, TC, batch_loop(b, HGKS_PHASE_FLUX), batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux),
-                    b->stream, D, b->ng, b->tiles_flux, (const TC*)coef, (const uint32_t*)mask,
-                    (TC*)(b->ws + b->face), dt_dev);
+  {
+    const bool loop = batch_loop(b, HGKS_PHASE_FLUX);
+    const dim3 grid(batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux));
+    auto flux = loop ? (b->ext ? k_batch_flux<TC, true, true> : k_batch_flux<TC, true, false>)
+                     : (b->ext ? k_batch_flux<TC, false, true> : k_batch_flux<TC, false, false>);
+    hipLaunchKernelGGL(flux, grid, dim3(kBlock), 0, b->stream, D, b->ng, b->tiles_flux, (const TC*)coef,
+                       (const uint32_t*)mask, (TC*)(b->ws + b->face), dt_dev);
+  }
   return bcheck(b, hipGetLastError(), "batch stage");
 }
 
@@ -990,6 +1104,22 @@ hgks_status batch_ready(hgks_batch b) {
     if (!b->state_set[i]) return fail(HGKS_ESTATE, "grid %d has no state", i);
   }
   return HGKS_OK;
+}
+
+// Reads and clears the device status word the time-step reduction sets for
+// a grid with a non-physical cell; synchronises the stream.
+hgks_status batch_status(hgks_batch b) {
+  uint32_t* st = (uint32_t*)(b->ws + b->status);
+  uint32_t h = 0;
+  if (hgks_status s = bcheck(b, hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, b->stream), "copy status"))
+    return s;
+  if (hgks_status s = bcheck(b, hipStreamSynchronize(b->stream), "synchronise")) return s;
+  if (h == 0) return HGKS_OK;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, b->stream, st);
+  if (hgks_status s = bcheck(b, hipGetLastError(), "clear status")) return s;
+  if (hgks_status s = bcheck(b, hipStreamSynchronize(b->stream), "synchronise")) return s;
+  return fail(HGKS_ENONPHYS, "a time-step reduction found a non-physical cell (its grid got dt = 0 and was not "
+                             "advanced)");
 }
 
 }  // namespace
@@ -1029,8 +1159,14 @@ hgks_status hgks_batch_create(const hgks_config* cfgs, int32_t n, void* ws, size
     batch_layout<float>(cfgs, n, b, b->gf);
   else
     batch_layout<double>(cfgs, n, b, b->gd);
+  for (int i = 0; i < n; ++i) b->ext = b->ext || cfgs[i].prandtl != 1.0 || cfgs[i].mu_exponent != 0.0;
   b->grid_set.assign(n, false);
   b->state_set.assign(n, false);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, b->stream, (uint32_t*)(b->ws + b->status));
+  if (hipGetLastError() != hipSuccess) {
+    delete b;
+    return fail(HGKS_EDEVICE, "clear status");
+  }
   *out = b;
   return HGKS_OK;
 }
@@ -1122,6 +1258,34 @@ hgks_status hgks_batch_set_launch(hgks_batch b, int32_t phase, int32_t workgroup
   return HGKS_OK;
 }
 
+hgks_status hgks_batch_set_tiles(hgks_batch b, int32_t tile_x, int32_t tile_y, int32_t tile_z, int32_t flux_band) {
+  if (hgks_status s = busable(b)) return s;
+  const int ct[3] = {tile_x, tile_y, tile_z};
+  if (!valid_tile(ct)) return fail(HGKS_EINVAL, "cell tile must be 0 x 0 x 0 or powers of two with product 256");
+  if (flux_band < 1 || flux_band > 256) return fail(HGKS_EINVAL, "flux band must be in [1, 256]");
+  for (int d = 0; d < 3; ++d) b->ct[d] = ct[d];
+  b->band = flux_band;
+  hgks_status s;
+  if (b->mixed()) {
+    batch_tiles(b->gf, b->ct, b->band, b->tiles_cell, b->tiles_flux);
+    s = batch_upload<float>(b);
+  } else {
+    batch_tiles(b->gd, b->ct, b->band, b->tiles_cell, b->tiles_flux);
+    s = batch_upload<double>(b);
+  }
+  if (s) return s;
+  // a captured graph holds the old launch shapes
+  if (b->exec) {
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return HGKS_OK;
+}
+
 hgks_status hgks_batch_capture(hgks_batch b, double cfl, int32_t n_steps, int32_t n_stages) {
   if (hgks_status s = batch_ready(b)) return s;
   if (!(cfl > 0.0) || !std::isfinite(cfl) || n_steps < 1 || (n_stages != 1 && n_stages != 2))
@@ -1166,7 +1330,7 @@ hgks_status hgks_batch_dt(hgks_batch b, double* dt_host) {
   if (hgks_status s = bcheck(b, hipMemcpyAsync(dt_host, b->ws + b->dt, b->ng * 8, hipMemcpyDeviceToHost, b->stream),
                              "copy dt"))
     return s;
-  return bcheck(b, hipStreamSynchronize(b->stream), "synchronise");
+  return batch_status(b);
 }
 
 hgks_status hgks_batch_totals(hgks_batch b, double* out_host) {
@@ -1188,7 +1352,7 @@ hgks_status hgks_batch_totals(hgks_batch b, double* out_host) {
 
 hgks_status hgks_batch_sync(hgks_batch b) {
   if (hgks_status s = busable(b)) return s;
-  return bcheck(b, hipStreamSynchronize(b->stream), "synchronise");
+  return batch_status(b);
 }
 
 }  // extern "C"

@@ -32,6 +32,8 @@ EXPORTS = [
     "hgks_batch_set_uniform_grid", "hgks_batch_set_state", "hgks_batch_get_state",
     "hgks_batch_max_dt", "hgks_batch_step", "hgks_batch_set_launch", "hgks_batch_capture",
     "hgks_batch_replay", "hgks_batch_dt", "hgks_batch_totals", "hgks_batch_sync",
+    "hgks_kinetic_energy", "hgks_debug_fallback_mask",
+    "hgks_batch_set_tiles",
 ]
 PHASES = ("recon", "fallback", "flux", "update", "reduce")
 
@@ -100,11 +102,14 @@ def load():
         "hgks_batch_max_dt": [P, D, P],
         "hgks_batch_step": [P, P, I32],
         "hgks_batch_set_launch": [P, I32, I32],
+        "hgks_batch_set_tiles": [P, I32, I32, I32, I32],
         "hgks_batch_capture": [P, D, I32, I32],
         "hgks_batch_replay": [P],
         "hgks_batch_dt": [P, DP],
         "hgks_batch_totals": [P, DP],
         "hgks_batch_sync": [P],
+        "hgks_kinetic_energy": [P, D, DP],
+        "hgks_debug_fallback_mask": [P, D, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -205,6 +210,16 @@ def hgks_check(h):
     return a.value, b.value
 
 
+def hgks_kinetic_energy(h, rho0=1.0):
+    ek = ctypes.c_double()
+    _check(load().hgks_kinetic_energy(h, rho0, ctypes.byref(ek)))
+    return ek.value
+
+
+def hgks_debug_fallback_mask(h, dt, out):
+    _check(load().hgks_debug_fallback_mask(h, dt, _dptr(out, dtype=torch.int32)))
+
+
 def hgks_debug_gp_states(h, dt, out):
     _check(load().hgks_debug_gp_states(h, dt, _dptr(out)))
 
@@ -230,6 +245,31 @@ def hgks_profile_end(h):
 
 
 # ------------------------------------------------------------ wrapper
+def make_config(n, bc=("periodic",) * 3, gamma=1.4, mu=0.0, weno_Gamma=0.0025, weno_eps=1e-8, tau_eps=0.01,
+                tau_C=1.0, precision="fp64", moving=False, characteristic=False, mu_T0=1.0, mu_exponent=0.0,
+                prandtl=1.0, stencil="S", stream=None):
+    """An hgks_config for an n = (nx, ny, nz) grid.  ``bc`` gives per axis
+    one of 'periodic', 'outflow', 'symmetric', or a pair (low end, high
+    end) of the last two; ``stream`` is a torch stream (None: the default
+    stream)."""
+    cfg = hgks_default_config(*[int(x) for x in n])
+    for d in range(3):
+        # one condition for the axis, or (low end, high end)
+        lo, hi = (bc[d], "same") if isinstance(bc[d], str) else bc[d]
+        cfg.bc[d] = BC[lo]
+        cfg.bc_hi[d] = BC[hi]
+    cfg.gamma, cfg.mu = gamma, mu
+    cfg.weno_Gamma, cfg.weno_eps = weno_Gamma, weno_eps
+    cfg.tau_eps, cfg.tau_C = tau_eps, tau_C
+    cfg.precision = PREC[precision]
+    cfg.moving = 1 if moving else 0
+    cfg.characteristic = 1 if characteristic else 0
+    cfg.mu_T0, cfg.mu_exponent, cfg.prandtl = mu_T0, mu_exponent, prandtl
+    cfg.stencil = STENCIL[stencil]
+    cfg.stream = ctypes.c_void_p(None if stream is None else stream.cuda_stream)
+    return cfg
+
+
 class Context:
     """One HGKS context with its workspace held as a torch tensor.
 
@@ -242,25 +282,14 @@ class Context:
                  stream=None):
         self.n = tuple(int(x) for x in n)
         self.device = torch.device(device)
-        cfg = hgks_default_config(*self.n)
-        for d in range(3):
-            # one condition for the axis, or (low end, high end)
-            lo, hi = (bc[d], "same") if isinstance(bc[d], str) else bc[d]
-            cfg.bc[d] = BC[lo]
-            cfg.bc_hi[d] = BC[hi]
-        cfg.gamma, cfg.mu = gamma, mu
-        cfg.weno_Gamma, cfg.weno_eps = weno_Gamma, weno_eps
-        cfg.tau_eps, cfg.tau_C = tau_eps, tau_C
-        cfg.precision = PREC[precision]
-        cfg.moving = 1 if moving else 0
-        cfg.characteristic = 1 if characteristic else 0
-        cfg.mu_T0, cfg.mu_exponent, cfg.prandtl = mu_T0, mu_exponent, prandtl
-        cfg.stencil = STENCIL[stencil]
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        cfg.stream = ctypes.c_void_p(stream.cuda_stream)
-        self.cfg = cfg
+        self.cfg = make_config(self.n, bc=bc, gamma=gamma, mu=mu, weno_Gamma=weno_Gamma, weno_eps=weno_eps,
+                               tau_eps=tau_eps, tau_C=tau_C, precision=precision, moving=moving,
+                               characteristic=characteristic, mu_T0=mu_T0, mu_exponent=mu_exponent,
+                               prandtl=prandtl, stencil=stencil, stream=stream)
+        cfg = self.cfg
         nbytes = hgks_workspace_size(cfg)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
@@ -310,6 +339,16 @@ class Context:
 
     def check(self):
         return hgks_check(self.h)
+
+    def kinetic_energy(self, rho0=1.0):
+        return hgks_kinetic_energy(self.h, rho0)
+
+    def debug_fallback_mask(self, dt):
+        """Fallback words [nz][ny][nx] (uint32 bit patterns held in int32)."""
+        nx, ny, nz = self.n
+        out = torch.empty((nz, ny, nx), dtype=torch.int32, device=self.device)
+        hgks_debug_fallback_mask(self.h, dt, out)
+        return out
 
     def debug_gp_states(self, dt):
         nx, ny, nz = self.n
@@ -377,6 +416,10 @@ def hgks_batch_set_launch(h, phase, workgroups):
     _check(load().hgks_batch_set_launch(h, phase, workgroups))
 
 
+def hgks_batch_set_tiles(h, tile, flux_band):
+    _check(load().hgks_batch_set_tiles(h, int(tile[0]), int(tile[1]), int(tile[2]), int(flux_band)))
+
+
 def hgks_batch_capture(h, cfl, n_steps, n_stages=2):
     _check(load().hgks_batch_capture(h, cfl, n_steps, n_stages))
 
@@ -441,9 +484,11 @@ class Batch:
         return (5, nz, ny, nx)
 
     def set_state(self, i, q):
-        # q was produced on the caller's stream; the batch copies on its own.
+        # q was produced on the caller's stream; the batch copies on its own,
+        # and the allocator must not reuse q's memory before that copy ran.
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         hgks_batch_set_state(self.h, i, q)
+        q.record_stream(self.stream)
 
     def get_state(self, i):
         out = torch.empty(self.shape(i), dtype=torch.float64, device=self.device)
@@ -459,6 +504,11 @@ class Batch:
 
     def set_launch(self, phase, workgroups):
         hgks_batch_set_launch(self.h, phase, workgroups)
+
+    def set_tiles(self, tile=(0, 0, 0), flux_band=16):
+        """Cell tile shape (0, 0, 0: 256 consecutive cells) and flux band
+        height; discards a captured graph."""
+        hgks_batch_set_tiles(self.h, tile, flux_band)
 
     def capture(self, cfl, n_steps, n_stages=2):
         hgks_batch_capture(self.h, cfl, n_steps, n_stages)

@@ -118,6 +118,38 @@ def test_persistent_workgroups_do_not_change_results(hg, wg):
         assert np.array_equal(ref.get_state(i).cpu().numpy(), alt.get_state(i).cpu().numpy())
 
 
+@pytest.mark.parametrize("tile,band", [((64, 4, 1), 16), ((16, 16, 1), 4), ((8, 8, 4), 32), ((256, 1, 1), 1)])
+def test_tile_shapes_do_not_change_results(hg, tile, band):
+    """Cell tiles as boxes of cells and other flux band heights (the
+    autotuner's choices) give the same state bit for bit, eager and in a
+    graph captured after the change."""
+    qs = states()
+    ref = make_batch(hg, "fp64", qs)
+    alt = make_batch(hg, "fp64", qs)
+    alt.set_tiles(tile, band)
+    for phase in (0, 3):
+        alt.set_launch(phase, 64)            # persistent walk over box tiles too
+    dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
+    for b in (ref, alt):
+        b.max_dt(0.35, dt)
+        b.step(dt, 2)
+        b.sync()
+    for i in range(len(GRIDS)):
+        assert np.array_equal(ref.get_state(i).cpu().numpy(), alt.get_state(i).cpu().numpy()), i
+    ref.capture(0.35, 2, 2)
+    alt.capture(0.35, 2, 2)
+    for b in (ref, alt):
+        b.replay()
+        b.sync()
+    assert ref.dt() == alt.dt()
+    for i in range(len(GRIDS)):
+        assert np.array_equal(ref.get_state(i).cpu().numpy(), alt.get_state(i).cpu().numpy()), i
+    with pytest.raises(hg.HGKSError):
+        alt.set_tiles((16, 16, 2), 16)       # product is not 256
+    with pytest.raises(hg.HGKSError):
+        alt.set_tiles((0, 0, 0), 0)
+
+
 def test_batch_conservation(hg):
     qs = states()
     b = make_batch(hg, "fp64", qs)

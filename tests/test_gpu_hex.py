@@ -138,6 +138,8 @@ def test_static_blast_weights_and_fallback(hg):
     count = int(sum(bin(int(m)).count("1") for m in mask.ravel()))
     assert count > 1000
     assert ctx.check()[1] == count
+    gpu_mask = ctx.debug_fallback_mask(dt).cpu().numpy().astype(np.uint32)
+    assert np.array_equal(gpu_mask, mask), int(np.sum(gpu_mask != mask))
     zero_g = np.all(ref[..., 1:] == 0.0, axis=(-1, -2))
     assert np.array_equal(np.all(gpu[..., 1:] == 0.0, axis=(-1, -2)), zero_g)
     gf = ctx.debug_face_flux(dt).cpu().numpy()

@@ -74,9 +74,12 @@ def test_gp_states(hg, case):
     for k in range(4):
         e = nerr(gpu[..., k], ref[..., k], axis_var=4)
         assert e.max() < TOL * (1 if k == 0 else 10), (k, e)
-    # Fallback decisions: same number of (cell, Gauss point) pairs; the
-    # discontinuous case exercises them.
+    # Fallback decisions: the mask words bit for bit (the same FP64
+    # decision on both sides) and their count; the discontinuous cases
+    # exercise them.
     mask = scheme.fallback_mask(prob, Q, dt)
+    gpu_mask = ctx.debug_fallback_mask(dt).cpu().numpy().astype(np.uint32)
+    assert np.array_equal(gpu_mask, mask), int(np.sum(gpu_mask != mask))
     count = int(sum(bin(int(m)).count("1") for m in mask.ravel()))
     _, gpu_count = ctx.check()
     assert gpu_count == count

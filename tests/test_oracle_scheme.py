@@ -140,3 +140,55 @@ def test_golden_tables_are_consistent():
     for name, orders in printed.items():
         t = np.loadtxt(os.path.join(g, name))
         assert np.allclose(np.log2(t[:-1, 1] / t[1:, 1]), orders, atol=2e-4)
+
+
+def test_kinetic_energy_uniform_flow_on_deformed_grid():
+    """A uniform stream has E_k = rho |U|^2 / (2 rho0) exactly, whatever
+    the cell volumes (Sec. 4, Taylor-Green diagnostics)."""
+    n = (6, 5, 7)
+    verts = wl.sine_mesh_vertices(n, 0.0, amp=0.1)
+    prob = oracle.vertex_problem(n, verts, (2.0, 2.0, 2.0))
+    rho, U = 1.3, np.array([0.4, -0.2, 0.7])
+    one = np.ones(n[::-1])
+    Q = wl.conservative(rho * one, U[0] * one, U[1] * one, U[2] * one, 2.0 * one)
+    ek = oracle.kinetic_energy(prob, Q, rho0=0.5)
+    assert abs(ek - rho * (U @ U) / (2 * 0.5)) < 1e-14
+
+
+def test_kinetic_energy_volume_weighting():
+    """Cells of unequal volume: the average weights each cell by its volume.
+    On a box stretched along x a field that is constant in each x-layer
+    gives the plain layer mean (equal volumes), and a two-cell grid of
+    unequal cells the weighted mean computed by hand."""
+    prob = oracle.uniform_problem((2, 1, 1), (0, 0, 0), (2.0, 1.0, 1.0))
+    Q = wl.conservative(np.array([[[1.0, 2.0]]]), np.array([[[1.0, 0.5]]]), np.zeros((1, 1, 2)),
+                        np.zeros((1, 1, 2)), np.ones((1, 1, 2)))
+    assert abs(oracle.kinetic_energy(prob, Q) - 0.5 * (0.5 * 1.0 + 0.5 * 2.0 * 0.25)) < 1e-15
+    # a periodic grid stretched along x (x = xi + 0.15 sin(pi xi) on
+    # [0, 2]): the weights are the cell volumes of the geometry
+    n = (4, 3, 5)
+    h = 2.0 / np.array(n)
+    Z, Y, X = np.meshgrid(np.arange(n[2]) * h[2], np.arange(n[1]) * h[1], np.arange(n[0]) * h[0], indexing="ij")
+    verts = np.stack([X + 0.15 * np.sin(np.pi * X), Y, Z])
+    vp = oracle.vertex_problem(n, verts, (2.0, 2.0, 2.0))
+    V = scheme.stage_volumes(vp)
+    assert np.abs(V - V.mean()).max() > 1e-3          # really unequal
+    rng = np.random.default_rng(3)
+    rho = 1 + 0.1 * rng.random(n[::-1])
+    u = rng.standard_normal(n[::-1])
+    Qd = wl.conservative(rho, u, 0 * u, 0 * u, 2 + 0 * u)
+    ref = sum(V.ravel()[i] * 0.5 * rho.ravel()[i] * u.ravel()[i] ** 2 for i in range(u.size)) / V.sum()
+    assert abs(oracle.kinetic_energy(vp, Qd) - ref) < 1e-14 * ref
+
+
+def test_kinetic_energy_taylor_green_initial_value():
+    """The Taylor-Green field of Sec. 4 has E_k = 1/8 at t = 0 (the density
+    variation integrates against |U|^2 to zero); from cell averages the
+    value converges to it at second order."""
+    errs = []
+    for n in (16, 32):
+        q = wl.tgv_state(n)
+        prob = oracle.uniform_problem((n,) * 3, (-np.pi,) * 3, (2 * np.pi,) * 3)
+        errs.append(abs(oracle.kinetic_energy(prob, q) - 0.125))
+    assert errs[1] < 2e-3
+    assert errs[0] / errs[1] > 3.5
