@@ -116,10 +116,10 @@ typedef struct {
                              sub-stencils of Sec. 2; 1: the alternative of
                              Remark 1 (S plus the cells two steps away along
                              the axes, 8 octant sub-stencils, linear weights
-                             1 - 8 Gamma and Gamma).  Box grids,
-                             component-wise reconstruction, not in batches;
-                             a symmetric end needs at least 3 cells on its
-                             axis                                            */
+                             1 - 8 Gamma and Gamma).  Box and hexahedral
+                             grids, component-wise reconstruction, not in
+                             batches; a symmetric end needs at least 3 cells
+                             on its axis                                     */
 } hgks_config;
 
 /* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,

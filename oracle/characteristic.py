@@ -14,9 +14,12 @@ back with R.  The positivity test of Sec. 4 is unchanged: it looks at the
 25 conservative polynomials.
 
 Readings: R is taken at the arithmetic mean of the two cell averages that
-share the face, and the two tangential (shear) eigenvectors are the frame's
-n_y and n_z of Sec. 3 (on a box face normal to axis d, the axes d+1 and d+2
-in cyclic order).  The reconstruction is in the laboratory frame.
+share the face, along the frame (n_x, n_y, n_z) of Sec. 3 at the face's
+centre, the two tangential (shear) eigenvectors being n_y and n_z (on a box
+face normal to axis d, the axes d+1 and d+2 in cyclic order, the frame of
+every Gauss point of the face; on a bilinear face of a hexahedral grid the
+one projection serves the face's four Gauss points).  The reconstruction is
+in the laboratory frame.
 """
 
 import numpy as np
@@ -113,7 +116,7 @@ def _project(M, arr, vaxis):
 def point_states(sel, x, Qbar, frame, Gamma, eps, gamma):
     """Value (5,...) and physical gradient (3,5,...) of the characteristic
     reconstruction of the selected cells at points x, for faces whose mean
-    state is Qbar and local frame is (n, t1, t2)."""
+    state is Qbar and whose projection frame is (n, t1, t2)."""
     R, L, _ = eigensystem(Qbar, *frame, gamma)
     selU = dict(sel)
     selU["Q"] = _project(L, sel["Q"], 0)

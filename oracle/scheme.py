@@ -193,6 +193,10 @@ def _faces(prob, rec, vp, vdot, d, dt, chunk=2048):
     xG = face_array(fg["x"], (3, 4))
     aG = face_array(fg["a"], (3, 4))
     xb = face_array(fg["xb"], (3, 4))
+    # the frame at the face centre (characteristic projection: one per face)
+    _, xa_c, xb_c = geo.bilinear(fc, 0.0, 0.0)
+    a_c = face_array(np.cross(xa_c, xb_c, axis=0), (3,))
+    xb_c = face_array(xb_c, (3,))
     ug = face_array(fg["ug"], (3, 4)) if vdot is not None else None
     adot = face_array(fg["adot"], (3, 4)) if vdot is not None else None
 
@@ -225,12 +229,14 @@ def _faces(prob, rec, vp, vdot, d, dt, chunk=2048):
         sels = {side: weno.select(rec, idx[None, :]) for side, idx in (("L", IL[sl]), ("R", IR[sl]))}
         if P.characteristic:
             Qbar = 0.5 * (sels["L"]["Q"] + sels["R"]["Q"])
+            cframe = tuple(v[:, None] for v in geo.local_frame(a_c[:, sl], xb_c[:, sl]))
         states = []
         for side in ("L", "R"):
             sel = sels[side]
             vals, grads = weno.eval_polys(sel, x)
             if P.characteristic:
-                val, grad = characteristic.point_states(sel, x, Qbar, frame, P.weno_Gamma, P.weno_eps, P.gamma)
+                val, grad = characteristic.point_states(sel, x, Qbar, cframe, P.weno_Gamma, P.weno_eps,
+                                                        P.gamma)
             else:
                 val, grad = weno.combine(sel, vals, grads)
             trig = weno.positivity_trigger(vals, P.gamma)

@@ -341,21 +341,12 @@ __global__ void __launch_bounds__(kBlock) k_recon_box(const double* __restrict__
 
 // Exact fallback test (Sec. 4): for every Gauss point of the cell, any of
 // the 25 polynomials (9 with the stencils of Remark 1) with rho <= 0 or
-// p < 0 marks the point.  posit_poly_bits: the 24 point bits of polynomial
-// m of cell idx (m = 0 the big stencil's, then the sub-stencils').
-template <typename TC, bool WIDE = false>
-__device__ __forceinline__ uint32_t posit_poly_bits(const double* __restrict__ q, const BoxGrid& G, TC gm1, size_t idx,
-                                                    int m) {
-  int ri, rj, rk;
-  split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
-  const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
-  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
-  auto at = [&](int v, int ox, int oy, int oz) -> double {
-    double s[3];
-    const int a = bc_index(G, 0, i + ox, s[0]), bb = bc_index(G, 1, j + oy, s[1]), c = bc_index(G, 2, k + oz, s[2]);
-    const double val = q[v * N + c * nxy + bb * nx + a];
-    return v == 1 ? s[0] * val : (v == 2 ? s[1] * val : (v == 3 ? s[2] * val : val));
-  };
+// p < 0 marks the point.  poly_bits: the 24 point bits of polynomial m
+// (m = 0 the big stencil's, then the sub-stencils') of a cell whose
+// stencil values at(v, ox, oy, oz) (variable v of the cell at that offset,
+// boundary images and mirror signs applied) the accessor gives.
+template <typename TC, bool WIDE, typename AT>
+__device__ __forceinline__ uint32_t poly_bits(const AT& at, TC gm1, int m) {
   TC qc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) qc[v] = TC(at(v, 0, 0, 0));
@@ -463,6 +454,23 @@ __device__ __forceinline__ uint32_t posit_poly_bits(const double* __restrict__ q
   }
 }
 
+// poly_bits of reconstruction-box cell idx, its stencil read from the state.
+template <typename TC, bool WIDE = false>
+__device__ __forceinline__ uint32_t posit_poly_bits(const double* __restrict__ q, const BoxGrid& G, TC gm1, size_t idx,
+                                                    int m) {
+  int ri, rj, rk;
+  split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
+  const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
+  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
+  auto at = [&](int v, int ox, int oy, int oz) -> double {
+    double s[3];
+    const int a = bc_index(G, 0, i + ox, s[0]), bb = bc_index(G, 1, j + oy, s[1]), c = bc_index(G, 2, k + oz, s[2]);
+    const double val = q[v * N + c * nxy + bb * nx + a];
+    return v == 1 ? s[0] * val : (v == 2 ? s[1] * val : (v == 3 ? s[2] * val : val));
+  };
+  return poly_bits<TC, WIDE>(at, gm1, m);
+}
+
 template <bool WIDE>
 constexpr int kPosPolys = WIDE ? 9 : 25;
 
@@ -475,11 +483,8 @@ __device__ __forceinline__ void posit_exact_box_cell(const double* __restrict__ 
 }
 
 // The exact test runs on a list of the flagged cells: k_posit_compact
-// appends them (one counter add per wave), then a fixed grid walks the
-// (flagged cell, polynomial) pairs, polynomial fastest, or-ing point bits
-// into the mask word; its "needs the test" bit stays set until
-// k_posit_finalize clears it, so every pair sees the flag.  counter[0] must
-// be zero before k_posit_compact.
+// appends them (one counter add per wave), then k_posit_group_box tests each
+// listed cell.  counter[0] must be zero before k_posit_compact.
 __global__ void __launch_bounds__(kBlock) k_posit_compact(const uint32_t* __restrict__ mask, size_t NR,
                                                           uint32_t* __restrict__ list, uint32_t* __restrict__ counter) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -497,25 +502,81 @@ __global__ void __launch_bounds__(kBlock) k_posit_compact(const uint32_t* __rest
   }
 }
 
-template <typename TC, bool WIDE = false>
-__global__ void __launch_bounds__(kBlock) k_posit_exact_box(const double* __restrict__ q, uint32_t* __restrict__ mask,
-                                                            BoxGrid G, TC gm1, const uint32_t* __restrict__ list,
-                                                            const uint32_t* __restrict__ counter) {
-  const size_t total = (size_t)counter[0] * kPosPolys<WIDE>;
-  for (size_t w = (size_t)blockIdx.x * kBlock + threadIdx.x; w < total; w += (size_t)gridDim.x * kBlock) {
-    const size_t e = w / kPosPolys<WIDE>;
-    const int m = (int)(w - e * kPosPolys<WIDE>);
-    const size_t idx = list[e];
-    const uint32_t bits = posit_poly_bits<TC, WIDE>(q, G, gm1, idx, m);
-    if (bits) atomicOr(&mask[idx], bits);
+// Stencil points of the exact test: the 27 cells of the 3x3x3 block, then
+// (Remark 1 only) the six cells two steps away along the axes.
+template <bool WIDE>
+constexpr int kPosPoints = WIDE ? 33 : 27;
+
+HGKS_FN void pos_point(int t, int& ox, int& oy, int& oz) {
+  if (t < 27) {
+    ox = t % 3 - 1;
+    oy = (t / 3) % 3 - 1;
+    oz = t / 9 - 1;
+  } else {
+    const int a = (t - 27) >> 1, s = ((t - 27) & 1) ? 2 : -2;
+    ox = a == 0 ? s : 0;
+    oy = a == 1 ? s : 0;
+    oz = a == 2 ? s : 0;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_posit_finalize(uint32_t* __restrict__ mask,
-                                                           const uint32_t* __restrict__ list,
-                                                           uint32_t* __restrict__ counter) {
-  const uint32_t n = counter[0];
-  for (uint32_t w = blockIdx.x * kBlock + threadIdx.x; w < n; w += gridDim.x * kBlock) mask[list[w]] &= ~kNeedsCheck;
+HGKS_FN int pos_slot(int ox, int oy, int oz) {
+  if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) return (oz + 1) * 9 + (oy + 1) * 3 + ox + 1;
+  const int a = ox != 0 ? 0 : (oy != 0 ? 1 : 2);
+  const int s = ox + oy + oz;
+  return 27 + 2 * a + (s > 0 ? 1 : 0);
+}
+
+// The exact test on the list of flagged cells, one 32-lane group per cell:
+// the group stages the cell's stencil (boundary images and mirror signs
+// applied) in LDS once, then lane m tests polynomial m; the lanes' point
+// bits are or-ed across the group and written as the cell's mask word,
+// which also clears its "needs the test" bit.  The pass loop is uniform
+// over the workgroup (its bound depends on the block only), so the
+// barriers are reached by every lane.
+constexpr int kPosGroups = kBlock / 32;
+
+template <typename TC, bool WIDE = false>
+__global__ void __launch_bounds__(kBlock) k_posit_group_box(const double* __restrict__ q,
+                                                            uint32_t* __restrict__ mask, BoxGrid G, TC gm1,
+                                                            const uint32_t* __restrict__ list,
+                                                            const uint32_t* __restrict__ counter) {
+  constexpr int NP = kPosPoints<WIDE>;
+  __shared__ double st[kPosGroups][5][NP];
+  const uint32_t count = counter[0];
+  const int grp = (int)(threadIdx.x >> 5), lane = (int)(threadIdx.x & 31u);
+  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
+  for (uint32_t base = blockIdx.x * kPosGroups; base < count; base += gridDim.x * kPosGroups) {
+    const uint32_t e = base + (uint32_t)grp;
+    const bool live = e < count;
+    const size_t idx = list[live ? e : base];
+    int ri, rj, rk;
+    split_index((uint32_t)idx, G.nr[0], G.nr[1], G.inv_nr[0], G.inv_nr[1], ri, rj, rk);
+    const int i = ri - G.g[0], j = rj - G.g[1], k = rk - G.g[2];
+    // NP may exceed the group's 32 lanes (33 points with Remark 1)
+    for (int t = lane; t < NP; t += 32) {
+      int ox, oy, oz;
+      pos_point(t, ox, oy, oz);
+      double s[3];
+      const int a = bc_index(G, 0, i + ox, s[0]), b = bc_index(G, 1, j + oy, s[1]), c = bc_index(G, 2, k + oz, s[2]);
+      const size_t o = (size_t)c * nxy + (size_t)b * nx + a;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double val = q[v * N + o];
+        st[grp][v][t] = v == 1 ? s[0] * val : (v == 2 ? s[1] * val : (v == 3 ? s[2] * val : val));
+      }
+    }
+    __syncthreads();
+    uint32_t bits = 0;
+    if (live && lane < kPosPolys<WIDE>) {
+      auto at = [&](int v, int ox, int oy, int oz) -> double { return st[grp][v][pos_slot(ox, oy, oz)]; };
+      bits = poly_bits<TC, WIDE>(at, gm1, lane);
+    }
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) bits |= __shfl_xor(bits, o);
+    if (live && lane == 0) mask[idx] = bits;
+    __syncthreads();
+  }
 }
 
 __global__ void k_zero_u32(uint32_t* __restrict__ p) { p[threadIdx.x] = 0u; }

@@ -367,19 +367,29 @@ __device__ __forceinline__ void sub_offsets(int m, int (&o)[4][3]) {
   o[3][ec] = sc;
 }
 
-// Linear least squares of sub-stencil m for all five variables of cell
-// i: b[v][3] in the scaled basis.
-template <typename NB>
-__device__ __forceinline__ void sub_fit(const NB& nb, const HexCell& Ci, const double (&qc)[5], int m,
-                                        double (&b)[5][3]) {
-  int o[4][3];
-  sub_offsets(m, o);
+// The eight sub-stencils of Remark 1: the face neighbours s_x e_x, s_y e_y,
+// s_z e_z of one sign octant (s_x fastest, + first).
+__device__ __forceinline__ void sub_offsets_wide(int m, int (&o)[3][3]) {
+  const int sx = (m & 1) ? -1 : 1, sy = (m & 2) ? -1 : 1, sz = (m & 4) ? -1 : 1;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) o[q][0] = o[q][1] = o[q][2] = 0;
+  o[0][0] = sx;
+  o[1][1] = sy;
+  o[2][2] = sz;
+}
+
+// Linear least squares of a sub-stencil with NR neighbour rows at offsets
+// o for all five variables of cell i: b[v][3] in the scaled basis (NR = 4:
+// Sec. 2; NR = 3: Remark 1, where the square system is solved exactly).
+template <int NR, typename NB>
+__device__ __forceinline__ void sub_fit_rows(const NB& nb, const HexCell& Ci, const double (&qc)[5],
+                                             const int (&o)[NR][3], double (&b)[5][3]) {
   double A[6] = {0, 0, 0, 0, 0, 0};  // xx, yy, zz, xy, yz, xz
   double r[5][3];
 #pragma unroll
   for (int v = 0; v < 5; ++v) r[v][0] = r[v][1] = r[v][2] = 0.0;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < NR; ++s) {
     double d[3], mo[6], dq[5];
     nb.template get<false>(o[s][0], o[s][1], o[s][2], Ci, qc, d, mo, dq);
     A[0] += d[0] * d[0];
@@ -410,11 +420,32 @@ __device__ __forceinline__ void sub_fit(const NB& nb, const HexCell& Ci, const d
   }
 }
 
+// Linear fit of sub-stencil m of the stencil family (WIDE: Remark 1).
+template <bool WIDE, typename NB>
+__device__ __forceinline__ void sub_fit(const NB& nb, const HexCell& Ci, const double (&qc)[5], int m,
+                                        double (&b)[5][3]) {
+  if constexpr (WIDE) {
+    int o[3][3];
+    sub_offsets_wide(m, o);
+    sub_fit_rows<3>(nb, Ci, qc, o, b);
+  } else {
+    int o[4][3];
+    sub_offsets(m, o);
+    sub_fit_rows<4>(nb, Ci, qc, o, b);
+  }
+}
+
+// Sub-stencils of the family: 24 (Sec. 2) or 8 (Remark 1).
+template <bool WIDE>
+constexpr int kHexSubs = WIDE ? 8 : 24;
+
 // Quadratic least squares of the big stencil for all five variables: the
 // row of neighbour o is the mean over o of (X, X_x^2 - m_xx, ...,
-// X_x X_z - m_xz) in the scaled basis of cell i.
-template <typename NB>
-__device__ __forceinline__ void big_fit(const NB& nb, const HexCell& Ci, const double (&qc)[5],
+// X_x X_z - m_xz) in the scaled basis of cell i.  The 18 rows of S come
+// from nb; with WIDE (Remark 1) six more, the cells two steps away along
+// the axes, from far.
+template <bool WIDE, typename NB, typename NF>
+__device__ __forceinline__ void big_fit(const NB& nb, const NF& far, const HexCell& Ci, const double (&qc)[5],
                                         double (&a)[5][9]) {
   double L[45];
 #pragma unroll
@@ -423,13 +454,7 @@ __device__ __forceinline__ void big_fit(const NB& nb, const HexCell& Ci, const d
   for (int v = 0; v < 5; ++v)
 #pragma unroll
     for (int e = 0; e < 9; ++e) a[v][e] = 0.0;
-#pragma unroll 1
-  for (int s = 0; s < 27; ++s) {
-    const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = s / 9 - 1;
-    const int nz = (ox != 0) + (oy != 0) + (oz != 0);
-    if (nz == 0 || nz == 3) continue;
-    double d[3], mo[6], dq[5];
-    nb.template get<true>(ox, oy, oz, Ci, qc, d, mo, dq);
+  auto add_row = [&](const double (&d)[3], const double (&mo)[6], const double (&dq)[5]) {
     double r[9];
     r[0] = d[0];
     r[1] = d[1];
@@ -448,6 +473,24 @@ __device__ __forceinline__ void big_fit(const NB& nb, const HexCell& Ci, const d
     for (int v = 0; v < 5; ++v) {
 #pragma unroll
       for (int e = 0; e < 9; ++e) a[v][e] += r[e] * dq[v];
+    }
+  };
+#pragma unroll 1
+  for (int s = 0; s < 27; ++s) {
+    const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = s / 9 - 1;
+    const int nz = (ox != 0) + (oy != 0) + (oz != 0);
+    if (nz == 0 || nz == 3) continue;
+    double d[3], mo[6], dq[5];
+    nb.template get<true>(ox, oy, oz, Ci, qc, d, mo, dq);
+    add_row(d, mo, dq);
+  }
+  if constexpr (WIDE) {
+#pragma unroll 1
+    for (int s = 0; s < 6; ++s) {
+      const int ax = s >> 1, sg = (s & 1) ? 2 : -2;
+      double d[3], mo[6], dq[5];
+      far.template get<true>(ax == 0 ? sg : 0, ax == 1 ? sg : 0, ax == 2 ? sg : 0, Ci, qc, d, mo, dq);
+      add_row(d, mo, dq);
     }
   }
   chol9(L);
@@ -484,27 +527,12 @@ __device__ __forceinline__ double pbasis(int n, const double (&X)[3], const doub
   }
 }
 
-// WENO-AO reconstruction on a hexahedral cell (always in double): the
-// combined quadratic in the scaled basis, written as (mean, 9 coefficients)
-// per variable, and the fallback pre-test.
-//
-// One workgroup per kTX x kTY x kTZ tile of cells (tiles x-fastest): the
-// tile and one layer around it are staged in LDS first, so that the 18
-// big-stencil rows and the 2 x 24 sub-stencil fits of every cell read their
-// neighbours from LDS instead of issuing some 1,800 global loads per cell.
-// Grid extents need not be multiples of the tile: the lanes of cells beyond
-// the grid only help to fill the tile.
-template <typename TS>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_recon_hex(HexGrid H, const double* __restrict__ geo,
-                                                      const double* __restrict__ q, TS* __restrict__ coef,
-                                                      uint32_t* __restrict__ mask, WenoParams<double> P, double gm1,
-                                                      size_t N, unsigned ntx, unsigned nty, unsigned ntiles) {
-  static_assert(kTX * kTY * kTZ == kBlock, "one lane per tile cell");
-  __shared__ HexTile T;
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b >= ntiles) return;
-  const int tx = (int)(b % ntx), ty = (int)((b / ntx) % nty), tz = (int)(b / (ntx * nty));
-  const int o0 = tx * kTX, o1 = ty * kTY, o2 = tz * kTZ;
+// Stages the reconstruction tile with origin (o0, o1, o2) and one layer
+// around it in LDS: per tile cell the centroid of its periodic image (shift
+// included), the central second moments and the five variables.
+__device__ __forceinline__ void stage_hex_tile(const HexGrid& H, const double* __restrict__ geo,
+                                               const double* __restrict__ q, size_t N, int o0, int o1, int o2,
+                                               HexTile& T) {
   for (int t = threadIdx.x; t < kHalo; t += kBlock) {
     const int g[3] = {o0 + t % kHX - 1, o1 + (t / kHX) % kHY - 1, o2 + t / (kHX * kHY) - 1};
     int c[3];
@@ -524,41 +552,70 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
     for (int v = 0; v < 5; ++v) T.q[v][t] = q[v * N + io];
   }
+}
+
+// beta_0 of Eq. (4) in the scaled basis for the quadratic with coefficients
+// c: mean |grad P|^2 over the cell (second moments m) plus the squared
+// second derivatives, each multi-index once.
+__device__ __forceinline__ double hex_beta0(const double (&c)[9], const HexCell& Ci) {
+  const double Hs[3][3] = {{2 * c[3], c[6], c[8]}, {c[6], 2 * c[4], c[7]}, {c[8], c[7], 2 * c[5]}};
+  const double Mm[3][3] = {{Ci.m[0], Ci.m[3], Ci.m[5]}, {Ci.m[3], Ci.m[1], Ci.m[4]}, {Ci.m[5], Ci.m[4], Ci.m[2]}};
+  double tr = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double hh = 0.0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) hh += Hs[t][r] * Hs[t][s];
+      tr += hh * Mm[s][r];
+    }
+  return c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + tr + 4.0 * (c[3] * c[3] + c[4] * c[4] + c[5] * c[5]) +
+         c[6] * c[6] + c[7] * c[7] + c[8] * c[8];
+}
+
+// WENO-AO reconstruction on a hexahedral cell (always in double): the
+// combined quadratic in the scaled basis, written as (mean, 9 coefficients)
+// per variable, and the fallback pre-test.
+//
+// One workgroup per kTX x kTY x kTZ tile of cells (tiles x-fastest): the
+// tile and one layer around it are staged in LDS first, so that the 18
+// big-stencil rows and the 2 x 24 sub-stencil fits of every cell read their
+// neighbours from LDS instead of issuing some 1,800 global loads per cell.
+// Grid extents need not be multiples of the tile: the lanes of cells beyond
+// the grid only help to fill the tile.
+// WIDE: the stencils of Remark 1 (the six far cells of the big stencil are
+// read from global memory, the tile holds one layer).
+template <typename TS, bool WIDE = false>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_recon_hex(HexGrid H, const double* __restrict__ geo,
+                                                      const double* __restrict__ q, TS* __restrict__ coef,
+                                                      uint32_t* __restrict__ mask, WenoParams<double> P, double gm1,
+                                                      size_t N, unsigned ntx, unsigned nty, unsigned ntiles) {
+  static_assert(kTX * kTY * kTZ == kBlock, "one lane per tile cell");
+  __shared__ HexTile T;
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= ntiles) return;
+  const int tx = (int)(b % ntx), ty = (int)((b / ntx) % nty), tz = (int)(b / (ntx * nty));
+  const int o0 = tx * kTX, o1 = ty * kTY, o2 = tz * kTZ;
+  stage_hex_tile(H, geo, q, N, o0, o1, o2, T);
   __syncthreads();
   const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
   const int i = o0 + lx, j = o1 + ly, k = o2 + lz;
   if (i >= H.n[0] || j >= H.n[1] || k >= H.n[2]) return;
   const size_t idx = ((size_t)k * H.n[1] + j) * H.n[0] + i;
   const NbrTile nb{T, ((lz + 1) * kHY + (ly + 1)) * kHX + (lx + 1)};
+  const NbrGlobal far{H, geo, q, N, i, j, k};
   HexCell Ci;
   load_cell(geo, N, idx, Ci);
   double qc[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) qc[v] = q[v * N + idx];
   double a[5][9];
-  big_fit(nb, Ci, qc, a);
+  big_fit<WIDE>(nb, far, Ci, qc, a);
 
-  // beta_0 in the scaled basis: mean |grad P|^2 over the cell (second
-  // moments m) plus the squared second derivatives, each multi-index once.
   double beta0[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const double* c = a[v];
-    const double Hs[3][3] = {{2 * c[3], c[6], c[8]}, {c[6], 2 * c[4], c[7]}, {c[8], c[7], 2 * c[5]}};
-    const double Mm[3][3] = {{Ci.m[0], Ci.m[3], Ci.m[5]}, {Ci.m[3], Ci.m[1], Ci.m[4]}, {Ci.m[5], Ci.m[4], Ci.m[2]}};
-    double tr = 0.0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        double hh = 0.0;
-#pragma unroll
-        for (int t = 0; t < 3; ++t) hh += Hs[t][r] * Hs[t][s];
-        tr += hh * Mm[s][r];
-      }
-    beta0[v] = c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + tr + 4.0 * (c[3] * c[3] + c[4] * c[4] + c[5] * c[5]) +
-               c[6] * c[6] + c[7] * c[7] + c[8] * c[8];
-  }
+  for (int v = 0; v < 5; ++v) beta0[v] = hex_beta0(a[v], Ci);
   // Bounds of the basis magnitudes over the 24 face Gauss points, for the
   // bound of |P_m - Q| used by the fallback pre-test.  The Gauss points
   // are convex combinations of the cell's vertices (bilinear faces), so
@@ -598,9 +655,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     db[v][0] = db[v][1] = db[v][2] = 0.0;
   }
 #pragma unroll 1
-  for (int m = 0; m < 24; ++m) {
+  for (int m = 0; m < kHexSubs<WIDE>; ++m) {
     double b[5][3];
-    sub_fit(nb, Ci, qc, m, b);
+    sub_fit<WIDE>(nb, Ci, qc, m, b);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
@@ -616,9 +673,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   double S[5], wb[5][3], w0r[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double tau = tsum[v] * (1.0 / 24.0);
+    const double tau = tsum[v] * (1.0 / kHexSubs<WIDE>);
     w0r[v] = 1.0 + tau * r0[v];
-    S[v] = P.gamma0 * w0r[v] + P.Gamma * (24.0 + tau * rsum[v]);
+    S[v] = P.gamma0 * w0r[v] + P.Gamma * (double(kHexSubs<WIDE>) + tau * rsum[v]);
 #pragma unroll
     for (int e = 0; e < 3; ++e) wb[v][e] = P.Gamma * tau * db[v][e];
   }
@@ -656,6 +713,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 }
 
 // Exact fallback test of Sec. 4 for the cells the pre-test flagged.
+template <bool WIDE = false>
 __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const double* __restrict__ geo,
                                                             const double* __restrict__ q, uint32_t* __restrict__ mask,
                                                             double gm1, size_t N) {
@@ -670,13 +728,13 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
   for (int v = 0; v < 5; ++v) qc[v] = q[v * N + idx];
   const NbrGlobal nb{H, geo, q, N, i, j, k};
   double a[5][9];
-  big_fit(nb, Ci, qc, a);
+  big_fit<WIDE>(nb, nb, Ci, qc, a);
   uint32_t bits = 0;
   for (int bit = 0; bit < 24; ++bit) {
     double X[3];
     cell_gp(H, Ci, i, j, k, bit, X);
     bool bad = false;
-    for (int m = 0; m <= 24 && !bad; ++m) {
+    for (int m = 0; m <= kHexSubs<WIDE> && !bad; ++m) {
       double val[5];
       if (m == 0) {
         for (int v = 0; v < 5; ++v) {
@@ -686,7 +744,7 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
         }
       } else {
         double b[5][3];
-        sub_fit(nb, Ci, qc, m - 1, b);
+        sub_fit<WIDE>(nb, Ci, qc, m - 1, b);
         for (int v = 0; v < 5; ++v) val[v] = qc[v] + b[v][0] * X[0] + b[v][1] * X[1] + b[v][2] * X[2];
       }
       bad = !(val[0] > 0.0);

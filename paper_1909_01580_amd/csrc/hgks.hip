@@ -73,7 +73,7 @@ bool valid_config(const hgks_config* c) {
   // the stencils of Remark 1: box grids, component-wise reconstruction; a
   // mirror two cells past the ghost layer needs three cells on that axis
   if (c->stencil != 0 && c->stencil != 1) return false;
-  if (c->stencil && (c->moving || c->characteristic || !(c->weno_Gamma < 1.0 / 24.0))) return false;
+  if (c->stencil && (c->characteristic || !(c->weno_Gamma < 1.0 / 24.0))) return false;
   if (c->stencil) {
     const int n[3] = {c->nx, c->ny, c->nz};
     for (int d = 0; d < 3; ++d)
@@ -288,19 +288,18 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
     prof_mark(c, HGKS_PHASE_RECON, false);
     if (hgks_status s = launched(c, "recon")) return s;
     prof_mark(c, HGKS_PHASE_FALLBACK, true);
-    // flagged cells to a list, then the (cell, polynomial) pairs on a
+    // flagged cells to a list, then one 32-lane group per listed cell on a
     // fixed grid of 8 workgroups per compute unit
     uint32_t* counter = c->plist() + D.NR;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, c->stream, counter);
     hipLaunchKernelGGL(k_posit_compact, dim3(nb), dim3(kBlock), 0, c->stream, c->mask(), D.NR, c->plist(), counter);
     const unsigned pg = 2048;
     if (c->cfg.stencil)
-      hipLaunchKernelGGL((k_posit_exact_box<TC, true>), dim3(pg), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+      hipLaunchKernelGGL((k_posit_group_box<TC, true>), dim3(pg), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
                          TC(c->cfg.gamma - 1.0), c->plist(), counter);
     else
-      hipLaunchKernelGGL((k_posit_exact_box<TC, false>), dim3(pg), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
+      hipLaunchKernelGGL((k_posit_group_box<TC, false>), dim3(pg), dim3(kBlock), 0, c->stream, qin, c->mask(), c->G,
                          TC(c->cfg.gamma - 1.0), c->plist(), counter);
-    hipLaunchKernelGGL(k_posit_finalize, dim3(pg), dim3(kBlock), 0, c->stream, c->mask(), c->plist(), counter);
     prof_mark(c, HGKS_PHASE_FALLBACK, false);
     if (hgks_status s = launched(c, "positivity")) return s;
     if (c->cfg.characteristic) {
@@ -384,13 +383,21 @@ hgks_status hex_stage(hgks_ctx c, const double* qin, double dt, double alpha) {
   prof_mark(c, HGKS_PHASE_RECON, true);
   const unsigned ntx = (unsigned)((c->D.n[0] + kTX - 1) / kTX), nty = (unsigned)((c->D.n[1] + kTY - 1) / kTY);
   const unsigned ntiles = ntx * nty * (unsigned)((c->D.n[2] + kTZ - 1) / kTZ);
-  hipLaunchKernelGGL((k_recon_hex<TC>), dim3(pad8(ntiles)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
-                     (TC*)c->coef(), c->mask(), P, c->cfg.gamma - 1.0, N, ntx, nty, ntiles);
+  if (c->cfg.stencil)
+    hipLaunchKernelGGL((k_recon_hex<TC, true>), dim3(pad8(ntiles)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                       (TC*)c->coef(), c->mask(), P, c->cfg.gamma - 1.0, N, ntx, nty, ntiles);
+  else
+    hipLaunchKernelGGL((k_recon_hex<TC>), dim3(pad8(ntiles)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                       (TC*)c->coef(), c->mask(), P, c->cfg.gamma - 1.0, N, ntx, nty, ntiles);
   prof_mark(c, HGKS_PHASE_RECON, false);
   if (hgks_status s = launched(c, "recon")) return s;
   prof_mark(c, HGKS_PHASE_FALLBACK, true);
-  hipLaunchKernelGGL(k_posit_exact_hex, dim3(blocks_for(N)), dim3(kBlock), 0, c->stream, H, c->geo(), qin, c->mask(),
-                     c->cfg.gamma - 1.0, N);
+  if (c->cfg.stencil)
+    hipLaunchKernelGGL((k_posit_exact_hex<true>), dim3(blocks_for(N)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                       c->mask(), c->cfg.gamma - 1.0, N);
+  else
+    hipLaunchKernelGGL((k_posit_exact_hex<false>), dim3(blocks_for(N)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                       c->mask(), c->cfg.gamma - 1.0, N);
   prof_mark(c, HGKS_PHASE_FALLBACK, false);
   if (hgks_status s = launched(c, "positivity")) return s;
   const unsigned nb = blocks_for(4 * N);

@@ -13,6 +13,7 @@ import torch
 
 import oracle
 from oracle import scheme
+from paper_1909_01580_amd import workloads as wl
 from tests.helpers import blast_state, nerr, smooth_state
 
 pytestmark = pytest.mark.gpu
@@ -103,3 +104,56 @@ def test_mixed_precision_close_to_fp64(hg):
         c32.step(dt, 2)
     a, b = c64.get_state().cpu().numpy()[0], c32.get_state().cpu().numpy()[0]
     assert np.abs(a - b).sum() / np.abs(a).sum() < 1e-5
+
+
+# ------------------------------------------------------------ hexahedral grids
+HEX_PERIOD = (2.0, 2.0, 2.0)
+
+
+def hex_blast(X, Y, Z, gamma=1.4):
+    r = np.sqrt((X - 0.9) ** 2 + (Y - 1.0) ** 2 + (Z - 1.1) ** 2)
+    inside = r < 0.6
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    zero = np.zeros_like(rho)
+    return wl.conservative(rho, zero + 0.3, zero, zero - 0.2, p, gamma)
+
+
+@pytest.mark.parametrize("kind", ["static_smooth", "static_blast", "moving_smooth"])
+def test_hex_wide_stencil(hg, kind):
+    """S' on the non-coplanar static mesh and on the moving mesh: Gauss-point
+    states and fallback words (bit for bit), face fluxes and a two-stage
+    step against the oracle, FP64, 1e-12."""
+    n = (10, 9, 8)
+    moving = kind.startswith("moving")
+    t, dt = 0.1, 0.03
+    v0 = wl.sine_mesh_vertices(n, t, amp=0.1, omega=np.pi, static=not moving)
+    v1 = wl.sine_mesh_vertices(n, t + dt, amp=0.1, omega=np.pi) if moving else None
+    Q = wl.hex_average(v0, HEX_PERIOD, hex_blast if kind == "static_blast" else wl.pulse_point)
+    params = oracle.Params(stencil="S_prime")
+    ctx = hg.Context(n, moving=True, stencil="S_prime")
+    ctx.set_vertices(torch.tensor(v0, device="cuda:0"), HEX_PERIOD)
+    ctx.set_state(torch.tensor(Q, device="cuda:0"))
+    static = oracle.vertex_problem(n, v0, HEX_PERIOD, params=params)
+    if kind == "static_blast":
+        dt = oracle.max_dt(static, Q, 0.35)
+    gpu = ctx.debug_gp_states(dt).cpu().numpy()
+    ref = scheme.gp_states(static, Q, dt)
+    for k in range(4):
+        e = nerr(gpu[..., k], ref[..., k], axis_var=4)
+        assert e.max() < TOL * (1 if k == 0 else 10), (k, e)
+    mask = scheme.fallback_mask(static, Q, dt)
+    assert np.array_equal(ctx.debug_fallback_mask(dt).cpu().numpy().astype(np.uint32), mask)
+    if kind == "static_blast":
+        assert int(sum(bin(int(m)).count("1") for m in mask.ravel())) > 500
+    gf = ctx.debug_face_flux(dt).cpu().numpy()
+    rf = scheme.face_fluxes(static, Q, dt)
+    for k in range(2):
+        err = np.abs(gf[..., k, :] - rf[..., k, :]).max() / np.abs(rf[..., k, :]).max()
+        assert err < TOL * (1 if k == 0 else 100), (k, err)
+    prob = oracle.vertex_problem(n, v0, HEX_PERIOD, params=params, verts_next=v1)
+    if moving:
+        ctx.set_next_vertices(torch.tensor(v1, device="cuda:0"))
+    ctx.step(dt, 2)
+    e = nerr(ctx.get_state().cpu().numpy(), oracle.step(prob, Q, dt))
+    assert e.max() < TOL, e

@@ -130,14 +130,17 @@ def test_viscosity_law_and_prandtl_limits(lib):
 
 
 def test_wide_stencil_limits(lib):
-    """The stencils of Remark 1: box grids with component-wise
+    """The stencils of Remark 1: box and hexahedral grids with component-wise
     reconstruction, not in batches; a symmetric end needs 3 cells."""
     from paper_1909_01580_amd import hgks
     cfg = hgks.hgks_default_config(8, 8, 8)
     assert cfg.stencil == 0
     cfg.stencil = 1
     assert hgks.hgks_workspace_size(cfg) > 0
-    for field, value in (("moving", 1), ("characteristic", 1), ("stencil", 2)):
+    hexa = hgks.hgks_default_config(8, 8, 8)
+    hexa.stencil, hexa.moving = 1, 1
+    assert hgks.hgks_workspace_size(hexa) > 0
+    for field, value in (("characteristic", 1), ("stencil", 2)):
         bad = hgks.hgks_default_config(8, 8, 8)
         bad.stencil = 1
         setattr(bad, field, value)
