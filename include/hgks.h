@@ -309,6 +309,24 @@ hgks_status hgks_batch_totals(hgks_batch b, double* out_host);
 /* Waits for the batch's stream; HGKS_ENONPHYS as hgks_batch_dt. */
 hgks_status hgks_batch_sync(hgks_batch b);
 
+/* ------------------------------------------------- allocation-free step
+ * For callers that cannot allocate device memory or hand the library a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): one step of hgks_step on a box grid (moving = 0)
+ * without a context.  cfg, origin and length are as for hgks_create and
+ * hgks_set_uniform_grid; q_dev ([5][nz][ny][nx] double, device) is read and
+ * overwritten with the state after the step, on cfg->stream,
+ * asynchronously.  Every intermediate array lives in one static device
+ * array of hgks_noalloc_capacity() bytes (64 MiB) per device, held until
+ * the process ends; the call allocates nothing.  HGKS_EINVAL when the grid
+ * needs more (hgks_workspace_size(cfg) > the capacity; about 87,000 cells in
+ * FP64), HGKS_EUNSUPPORTED for moving = 1.  Calls on one device share the
+ * array: calls that overlap (other streams or threads) race and must not be
+ * issued. */
+hgks_status hgks_step_noalloc(const hgks_config* cfg, const double origin_host[3], const double length_host[3],
+                              double* q_dev, double dt, int32_t n_stages);
+size_t hgks_noalloc_capacity(void);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* hgks_last_error(void);
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -853,6 +854,74 @@ hgks_status hgks_profile_end(hgks_ctx c, double ms[5], int64_t launches[5]) {
 }
 
 const char* hgks_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------ allocation-free step
+// hgks_step_noalloc keeps its whole workspace (intermediate state, stage
+// accumulator, reconstruction coefficients, fallback masks and list, face
+// sums, reduction scratch) in this file-scope device array; every device the
+// library runs on holds its own copy until the process ends.  Host code uses
+// the array only through the per-device address hipGetSymbolAddress gives.
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) on the first call there.
+hgks_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(HGKS_EDEVICE, "no usable current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(HGKS_EDEVICE, "scratch address: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hgks_noalloc_capacity(void) { return kScratchBytes; }
+
+hgks_status hgks_step_noalloc(const hgks_config* cfg, const double origin[3], const double length[3], double* q_dev,
+                              double dt, int32_t n_stages) {
+  if (!valid_config(cfg)) return fail(HGKS_EINVAL, "invalid configuration");
+  if (cfg->moving) return fail(HGKS_EUNSUPPORTED, "the allocation-free step takes box grids (moving = 0)");
+  if (!q_dev) return fail(HGKS_EINVAL, "null state");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HGKS_EINVAL, "dt must be positive");
+  if (n_stages != 1 && n_stages != 2) return fail(HGKS_EINVAL, "n_stages must be 1 or 2");
+  const size_t need = make_layout(cfg, make_dims(cfg)).total;
+  if (need > kScratchBytes)
+    return fail(HGKS_EINVAL, "grid needs %zu bytes of scratch; the allocation-free step holds at most %zu", need,
+                kScratchBytes);
+  void* base = nullptr;
+  if (hgks_status s = scratch_address(&base)) return s;
+  hgks_ctx_s ctx;
+  hgks_ctx c = &ctx;
+  init_ctx(c, cfg, (char*)base);
+  if (hgks_status s = set_box(c, origin, length)) return s;
+  const size_t bytes = 5 * c->D.N * sizeof(double);
+  if (hgks_status s = check_hip(c, hipMemcpyAsync(c->q(), q_dev, bytes, hipMemcpyDeviceToDevice, c->stream),
+                                "copy state in"))
+    return s;
+  c->state_set = true;
+  if (hgks_status s = c->mixed() ? box_step<float>(c, dt, n_stages) : box_step<double>(c, dt, n_stages)) return s;
+  return check_hip(c, hipMemcpyAsync(q_dev, c->q(), bytes, hipMemcpyDeviceToDevice, c->stream), "copy state out");
+}
 
 }  // extern "C"
 

@@ -33,7 +33,7 @@ EXPORTS = [
     "hgks_batch_max_dt", "hgks_batch_step", "hgks_batch_set_launch", "hgks_batch_capture",
     "hgks_batch_replay", "hgks_batch_dt", "hgks_batch_totals", "hgks_batch_sync",
     "hgks_kinetic_energy", "hgks_debug_fallback_mask",
-    "hgks_batch_set_tiles",
+    "hgks_batch_set_tiles", "hgks_step_noalloc", "hgks_noalloc_capacity",
 ]
 PHASES = ("recon", "fallback", "flux", "update", "reduce")
 
@@ -110,6 +110,7 @@ def load():
         "hgks_batch_sync": [P],
         "hgks_kinetic_energy": [P, D, DP],
         "hgks_debug_fallback_mask": [P, D, P],
+        "hgks_step_noalloc": [ctypes.POINTER(hgks_config), DP, DP, P, D, I32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -117,6 +118,8 @@ def load():
         fn.restype = ctypes.c_int
     L.hgks_last_error.argtypes = []
     L.hgks_last_error.restype = ctypes.c_char_p
+    L.hgks_noalloc_capacity.argtypes = []
+    L.hgks_noalloc_capacity.restype = ctypes.c_size_t
     _lib = L
     return L
 
@@ -218,6 +221,14 @@ def hgks_kinetic_energy(h, rho0=1.0):
 
 def hgks_debug_fallback_mask(h, dt, out):
     _check(load().hgks_debug_fallback_mask(h, dt, _dptr(out, dtype=torch.int32)))
+
+
+def hgks_step_noalloc(cfg, origin, length, q, dt, n_stages=2):
+    _check(load().hgks_step_noalloc(ctypes.byref(cfg), _arr3(origin), _arr3(length), _dptr(q), dt, n_stages))
+
+
+def hgks_noalloc_capacity():
+    return load().hgks_noalloc_capacity()
 
 
 def hgks_debug_gp_states(h, dt, out):
