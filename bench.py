@@ -204,7 +204,7 @@ def run_explosion(n, precision, t_end=0.1, cfl=0.35, t_early=0.02):
             "tot_early": tot_early}
 
 
-def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2):
+def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2, prandtl=1.0):
     """48 independent periodic problems of uneven sizes (32..96 per axis,
     about 1.0e7 cells): autotuned persistent launches, a HIP graph of
     ``steps`` steps (per-grid dt reduction inside), timed by replay."""
@@ -213,7 +213,10 @@ def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2):
     from paper_1909_01580_amd import workloads as wl
 
     problems = wl.batch_problems()
-    grids = [{"n": p["n"], "length": p["length"], "mu": p["mu"]} for p in problems]
+    # the Prandtl number of the viscous grids (heat-flux correction); the
+    # inviscid ones keep the BGK flux
+    grids = [{"n": p["n"], "length": p["length"], "mu": p["mu"], "prandtl": prandtl if p["mu"] > 0 else 1.0}
+             for p in problems]
     cells = sum(int(np.prod(g["n"])) for g in grids)
     b = hgks.Batch(grids, precision=precision)
     for i, p in enumerate(problems):
@@ -277,7 +280,7 @@ def moving_initial(n):
     return v0, wl.hex_average(v0, (2.0, 2.0, 2.0), wl.pulse_point)
 
 
-def run_moving(n, steps, warmup, precision, v0, q0, cfl=0.35):
+def run_moving(n, steps, warmup, precision, v0, q0, cfl=0.35, **options):
     """Moving hexahedral mesh on [0,2]^3 (periodic): nodes
     x = xi + 0.05 sin(2 pi t) sin(pi xi) sin(pi eta) sin(pi zeta) on every
     component, grid velocity the secant over each step, a density pulse on a
@@ -293,7 +296,7 @@ def run_moving(n, steps, warmup, precision, v0, q0, cfl=0.35):
     xi = torch.tensor(wl.sine_mesh_vertices(n, 0.0, amp=0.0, static=True), device="cuda:0")
     shape = torch.tensor(wl.sine_mesh_vertices(n, 0.0, amp=1.0, static=True), device="cuda:0") - xi
     nxt = torch.empty_like(xi)
-    ctx = hgks.Context((n, n, n), moving=True, precision=precision)
+    ctx = hgks.Context((n, n, n), moving=True, precision=precision, **options)
     ctx.set_vertices(torch.tensor(v0, device="cuda:0"), P)
     ctx.set_state(torch.tensor(q0, device="cuda:0"))
     tot0 = np.array(ctx.totals())
@@ -578,6 +581,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--no-moving", action="store_true")
     ap.add_argument("--moving-steps", type=int, default=10)
+    ap.add_argument("--no-moving-options", action="store_true")
     ap.add_argument("--no-octant", action="store_true")
     ap.add_argument("--no-characteristic", action="store_true")
     ap.add_argument("--no-turbulence", action="store_true")
@@ -733,6 +737,12 @@ def main():
             "conservation_rel_drift": {"mixed": bm["drift"], "fp64": b64["drift"]},
             "launch_table": bm["launch_table"],
         }
+        bp = run_batched(args.batched_steps, "mixed", tune=False, unbatched_steps=0, prandtl=0.72)
+        out["batched"]["prandtl_0.72"] = {
+            "workload": "the same batch, its viscous grids at Prandtl number 0.72 (heat-flux correction, the "
+                        "extended flux instantiation for the whole batch), default launch shapes",
+            "value": bp["value"], "ms_per_step": bp["ms"] / bp["steps"],
+            "conservation_rel_drift": bp["drift"]}
     if not args.no_moving:
         v0, q0m = moving_initial(args.n)
         mv = {p: run_moving(args.n, args.moving_steps, 2, p, v0, q0m) for p in ("fp64", "mixed")}
@@ -751,6 +761,28 @@ def main():
             "max_norm_error_mixed_vs_fp64": err["max_norm_per_variable"],
             "conservation_rel_drift": {p: mv[p]["drift"] for p in mv},
         }
+    if not args.no_moving and not args.no_moving_options:
+        v0, q0m = moving_initial(args.n)
+        ms = args.moving_steps // 2 or 1
+        opts = {"characteristic": {"characteristic": True}, "wide_stencil": {"stencil": "S_prime"}}
+        out["moving_options"] = {}
+        for name, o in opts.items():
+            mo = {p: run_moving(args.n, ms, 1, p, v0, q0m, **o) for p in ("fp64", "mixed")}
+            err = state_errors(mo["mixed"]["state"], mo["fp64"]["state"])
+            out["moving_options"][name] = {
+                "workload": f"the {n}^3 moving-mesh steps with " + (
+                    "reconstruction in characteristic variables (six per-face quadratics per cell, projection "
+                    "frame at each face centre)" if name == "characteristic" else
+                    "the stencils of Remark 1 (S' with the cells two steps away along the axes, eight octant "
+                    "sub-stencils)"),
+                "value": cells * 2 * ms / (mo["fp64"]["ms"] / 1e3), "unit": "cell-stage updates/s", "dtype": "f64",
+                "ms_per_step": mo["fp64"]["ms"] / ms,
+                "phases_ms_per_step": {k: v[0] / ms for k, v in mo["fp64"]["prof"].items()},
+                "mixed_value": cells * 2 * ms / (mo["mixed"]["ms"] / 1e3),
+                "l1_rho_rel_error_mixed_vs_fp64": err["l1_rho_rel"],
+                "max_norm_error_mixed_vs_fp64": err["max_norm_per_variable"],
+                "conservation_rel_drift": {p: mo[p]["drift"] for p in mo},
+            }
     if not args.no_octant:
         oc = {p: run_octant(args.n, args.octant_steps, 2, p) for p in ("fp64", "mixed")}
         err = state_errors(oc["mixed"]["state"], oc["fp64"]["state"])

@@ -98,10 +98,12 @@ typedef struct {
   int32_t bc_hi[3];       /* hgks_bc at the high end of each axis, or
                              HGKS_BC_SAME (the default): as bc[d]             */
   int32_t characteristic; /* 1: reconstruct in characteristic variables (Sec.
-                             4): per face, Euler eigenvectors along the normal
-                             at the mean of the two cell averages; box grids
-                             (moving = 0) only, not in batches.  0: the
-                             conservative variables component-wise (default) */
+                             4): per face, Euler eigenvectors along the face
+                             frame at the face centre (the normal and the two
+                             tangential axes) at the mean of the two cell
+                             averages; box and hexahedral grids, not in
+                             batches.  0: the conservative variables
+                             component-wise (default)                        */
   double mu_T0;           /* viscosity law mu (T / mu_T0)^mu_exponent with T =
                              p / rho of the interface equilibrium state, as in
                              the isotropic-turbulence test of Sec. 4 (0.76);  */

@@ -44,7 +44,13 @@ the oracle and the GPU agree on them by construction only:
 * the step-rejection rule ``checked_step`` (halve dt while the step gives a
   non-physical state): a control rule the paper does not state, needed for
   the singular start of its Sedov problem.  Pinned only to its own
-  definition (minimal halving, result equal to a plain step).
+  definition (minimal halving, result equal to a plain step);
+* the state and frame of the characteristic projection (Sec. 4 names the
+  characteristic variables only as an option, without the state): the
+  eigenvectors at the mean of the two cell averages sharing the face, along
+  the face frame of Sec. 3 at the face centre.  Pinned through their
+  consequences (eigen-decomposition of the Jacobian, linear weights giving
+  the component-wise scheme, the entropy wave), not by a printed value.
 
 Array convention inside the oracle: spatial axes are ordered (i, j, k) =
 (x, y, z).  The public helpers in ``scheme`` accept and return states in the

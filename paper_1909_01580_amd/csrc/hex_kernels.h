@@ -35,6 +35,7 @@
 #include <type_traits>
 
 #include "box_kernels.h"
+#include "char_basis.h"
 #include "common.h"
 #include "gks_flux.h"
 
@@ -648,12 +649,24 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   // Gamma tau sum_m (r_m - r_0) b^m.  The pass gathers sum |beta_0 -
   // beta_m| (tau), sum r_m and sum (r_m - r_0) b^m; tau enters afterwards.
   double tsum[5], rsum[5], db[5][3], bnd[5], r0[5];
+  TS* const cout = coef + coef_cell<TS>(idx);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     r0[v] = d_rcp(beta0[v] + P.eps);
-    tsum[v] = rsum[v] = bnd[v] = 0.0;
+    tsum[v] = rsum[v] = 0.0;
     db[v][0] = db[v][1] = db[v][2] = 0.0;
+    // the bound of |P_0 - Q| starts the bound over all polynomials
+    double b0 = 0.0;
+#pragma unroll
+    for (int n = 0; n < 9; ++n) b0 += fabs(a[v][n]) * pmax[n];
+    bnd[v] = b0;
+    // P_0 is parked in this cell's coefficient rows (read back by this lane
+    // below), so that its 45 values do not hold registers through the pass
+    TS* cv = cout + v * 10 * kCB<TS>;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) cv[(e + 1) * kCB<TS>] = TS(a[v][e]);
   }
+  asm volatile("" ::: "memory");
 #pragma unroll 1
   for (int m = 0; m < kHexSubs<WIDE>; ++m) {
     double b[5][3];
@@ -683,16 +696,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   for (int v = 0; v < 5; ++v) {
     const double iS = d_rcp(S[v]);
     const double w0g = w0r[v] * iS;  // wbar_0 / gamma_0
+    TS* cv = cout + v * 10 * kCB<TS>;
     double c[9];
 #pragma unroll
-    for (int e = 0; e < 3; ++e) c[e] = w0g * a[v][e] + iS * wb[v][e];
+    for (int e = 0; e < 9; ++e) c[e] = (double)cv[(e + 1) * kCB<TS>];
 #pragma unroll
-    for (int e = 3; e < 9; ++e) c[e] = w0g * a[v][e];
-    double b0 = 0.0;
+    for (int e = 0; e < 3; ++e) c[e] = w0g * c[e] + iS * wb[v][e];
 #pragma unroll
-    for (int n = 0; n < 9; ++n) b0 += fabs(a[v][n]) * pmax[n];
-    bnd[v] = fmax(bnd[v], b0);
-    TS* cv = coef + coef_cell<TS>(idx) + v * 10 * kCB<TS>;
+    for (int e = 3; e < 9; ++e) c[e] = w0g * c[e];
     cv[0] = TS(qc[v]);
 #pragma unroll
     for (int e = 0; e < 9; ++e) cv[(e + 1) * kCB<TS>] = TS(c[e]);
@@ -799,6 +810,80 @@ __device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const doub
   }
 }
 
+// Frame of Sec. 3 at the face point P: n along X_a x X_b, t2 along X_b,
+// t1 = t2 x n (the arithmetic of the face flux's Gauss-point frame).
+__device__ __forceinline__ void face_frame(const FacePoint& P, double (&n)[3], double (&t1)[3], double (&t2)[3]) {
+  double av[3];
+  cross3(P.xa, P.xb, av);
+  const double ia = d_rcp(sqrt(av[0] * av[0] + av[1] * av[1] + av[2] * av[2]));
+  const double ib = d_rcp(sqrt(P.xb[0] * P.xb[0] + P.xb[1] * P.xb[1] + P.xb[2] * P.xb[2]));
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    n[e] = av[e] * ia;
+    t2[e] = P.xb[e] * ib;
+  }
+  cross3(t2, n, t1);
+}
+
+// Frame at the centre of the face normal to D on vertex plane c (its lowest
+// vertex), at the stage time of H.
+__device__ __forceinline__ void face_centre_frame(const HexGrid& H, int D, int c0, int c1, int c2, double (&n)[3],
+                                                  double (&t1)[3], double (&t2)[3]) {
+  double cx[4][3], cu[4][3];
+  face_corners(H, D, c0, c1, c2, cx, cu);
+  FacePoint P;
+  face_point(cx, cu, 0.0, 0.0, P);
+  face_frame(P, n, t1, t2);
+}
+
+// Value and physical gradient of the five conservative variables at the
+// physical point x of the cell reconstructed in characteristic variables:
+// cv points at the cell in its face array, B holds the face's eigenvectors.
+// A first-order fallback point gives the cell mean and zero gradient.
+template <typename TC>
+__device__ __forceinline__ void eval_char_hex(const TC* __restrict__ cv, const double* __restrict__ geo, size_t N,
+                                              size_t idx, const double (&shift)[3], const double (&x)[3], bool fb,
+                                              const CharFrame& B, TC (&val)[5], TC (&grad)[5][3]) {
+  HexCell C;
+  load_cell(geo, N, idx, C);
+  TC X[3], m[6];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) X[e] = TC((x[e] - C.c[e] - shift[e]) * C.ih);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) m[e] = TC(C.m[e]);
+  const TC ih = TC(C.ih);
+  constexpr int CB = kCB<TC>;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    val[v] = cv[10 * v * CB];
+    grad[v][0] = grad[v][1] = grad[v][2] = TC(0);
+  }
+  if (fb) return;
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    const TC* ck = cv + 10 * f * CB;
+    TC c[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) c[e] = ck[(e + 1) * CB];
+    const TC du = c[0] * X[0] + c[1] * X[1] + c[2] * X[2] + c[3] * (X[0] * X[0] - m[0]) +
+                  c[4] * (X[1] * X[1] - m[1]) + c[5] * (X[2] * X[2] - m[2]) + c[6] * (X[0] * X[1] - m[3]) +
+                  c[7] * (X[1] * X[2] - m[4]) + c[8] * (X[0] * X[2] - m[5]);
+    TC g[3];
+    g[0] = (c[0] + TC(2) * c[3] * X[0] + c[6] * X[1] + c[8] * X[2]) * ih;
+    g[1] = (c[1] + TC(2) * c[4] * X[1] + c[6] * X[0] + c[7] * X[2]) * ih;
+    g[2] = (c[2] + TC(2) * c[5] * X[2] + c[8] * X[0] + c[7] * X[1]) * ih;
+    double r[5];
+    char_rcol(B, f, r);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const TC rv = TC(r[v]);
+      val[v] += rv * du;
+#pragma unroll
+      for (int e = 0; e < 3; ++e) grad[v][e] += rv * g[e];
+    }
+  }
+}
+
 // Conservative variables seen from a frame moving with u (one vector, also
 // applied to the gradients), then rotated into the frame (nx, ny, nz); in
 // the compute type.
@@ -864,16 +949,24 @@ __device__ __forceinline__ void to_global(const double (&f)[5], const double (&u
   g[4] = f[4] + (M[0] * u[0] + M[1] * u[1] + M[2] * u[2]) + 0.5 * uu * f[0];
 }
 
+// Rows of the flux kernel's per-lane LDS slot: the Gauss point's geometry
+// (18), and with per-face reconstructions (characteristic variables) the
+// face-centre frame (9) and the face's mean state (5).
+template <bool FS>
+constexpr int kHexStash = FS ? 32 : 18;
+
 // One lane = one Gauss point of one face normal to axis D (uniform over the
 // workgroup); lane l of block lb takes Gauss point l % 4 of face slot l / 4
 // in the flux block order of the box kernels (face_of_block).
-// PR: the extended viscous model (viscosity law, Prandtl correction).
-template <typename TC, bool PR = false>
+// PR: the extended viscous model (viscosity law, Prandtl correction); FS:
+// per-face coefficient arrays (reconstruction in characteristic variables),
+// H.box.fs_stride elements apart.
+template <typename TC, bool PR = false, bool FS = false>
 __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __restrict__ coef,
                                               const double* __restrict__ geo, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, double* __restrict__ vface,
                                               const GasParams<TC>& gp, TC dt, TC idt, size_t N, unsigned lb, int D,
-                                              double (&stash)[18][kBlock]) {
+                                              double (&stash)[kHexStash<FS>][kBlock]) {
   const int gpi = (int)(threadIdx.x & 3);
   int c[3];
   size_t f;
@@ -916,6 +1009,20 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     g[15 * kBlock] = area;
     g[16 * kBlock] = Pt.u[0] * adot[0] + Pt.u[1] * adot[1] + Pt.u[2] * adot[2];
     g[17 * kBlock] = 0.25 * (Pt.u[0] * av[0] + Pt.u[1] * av[1] + Pt.u[2] * av[2]);
+    if constexpr (FS) {
+      // the frame at the face centre, the projection frame of both cells'
+      // reconstructions for this face
+      FacePoint Pc;
+      face_point(cx, cu, 0.0, 0.0, Pc);
+      double fn[3], f1[3], f2[3];
+      face_frame(Pc, fn, f1, f2);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        g[(18 + e) * kBlock] = fn[e];
+        g[(21 + e) * kBlock] = f1[e];
+        g[(24 + e) * kBlock] = f2[e];
+      }
+    }
   }
   // The re-reads are plain LDS loads behind a compiler-only memory fence
   // (no instruction): the fence keeps the compiler from forwarding the
@@ -934,6 +1041,37 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   const size_t iR = hex_index(H, c[0], c[1], c[2], shR);
   const bool fbL = (mask[iL] >> (4 * (2 * D + 1) + gpi)) & 1u;
   const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
+  // the left cell's reconstruction for its high face, the right cell's for
+  // its low face (one array unless the faces have their own)
+  const TC* coefL = FS ? coef + (size_t)(2 * D + 1) * H.box.fs_stride : coef;
+  const TC* coefR = FS ? coef + (size_t)(2 * D) * H.box.fs_stride : coef;
+  if constexpr (FS) {
+    // the face's mean state: the two cells' conservative means
+    constexpr int CB = kCB<TC>;
+    const TC* mL = coefL + coef_cell<TC>(iL);
+    const TC* mR = coefR + coef_cell<TC>(iR);
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      stash[27 + v][threadIdx.x] = 0.5 * ((double)mL[10 * v * CB] + (double)mR[10 * v * CB]);
+  }
+  auto eval_side = [&](const TC* cf, size_t icell, const double (&sh)[3], const double (&x)[3], bool fb,
+                       TC (&val)[5], TC (&grad)[5][3]) {
+    if constexpr (FS) {
+      CharFrame B;
+      {
+        double fn[3], f1[3], f2[3], Qb[5];
+        get3(18, fn);
+        get3(21, f1);
+        get3(24, f2);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Qb[v] = gs[(27 + v) * kBlock];
+        char_frame(Qb, fn, f1, f2, gp.gamma, B);
+      }
+      eval_char_hex(cf + coef_cell<TC>(icell), geo, N, icell, sh, x, fb, B, val, grad);
+    } else {
+      eval_hex(cf, geo, N, icell, sh, x, fb, val, grad);
+    }
+  };
 
   FluxAcc<TC> acc;
   if constexpr (std::is_same<TC, float>::value) {
@@ -952,9 +1090,9 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       get3(9, n1);
       get3(12, n2);
       TC val[5], grad[5][3];
-      eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
+      eval_side(coefL, iL, shL, x, fbL, val, grad);
       to_local(val, grad, u, n0, n1, n2, WL, dWL);
-      eval_hex(coef, geo, N, iR, shR, x, fbR, val, grad);
+      eval_side(coefR, iR, shR, x, fbR, val, grad);
       to_local(val, grad, u, n0, n1, n2, WR, dWR);
     }
     acc_zero(acc);
@@ -971,7 +1109,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       get3(9, n1);
       get3(12, n2);
       TC val[5], grad[5][3];
-      eval_hex(coef, geo, N, iL, shL, x, fbL, val, grad);
+      eval_side(coefL, iL, shL, x, fbL, val, grad);
       TC W[5], dW[3][5];
       to_local(val, grad, u, n0, n1, n2, W, dW);
       side_terms<+1, PR>(W, dW, gp, acc);
@@ -987,7 +1125,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       get3(9, n1);
       get3(12, n2);
       TC val[5], grad[5][3];
-      eval_hex(coef, geo, N, iRt, shR, x, fbR, val, grad);
+      eval_side(coefR, iRt, shR, x, fbR, val, grad);
       TC W[5], dW[3][5];
       to_local(val, grad, u, n0, n1, n2, W, dW);
       side_terms<-1, PR>(W, dW, gp, acc);
@@ -1037,7 +1175,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
 // All faces of the three directions in one launch, nb blocks of 64 faces per
 // direction, interleaved (flux_block).  Register budget: two waves per SIMD
 // in FP64; four in FP32 (113 registers).
-template <typename TC, bool PR = false>
+template <typename TC, bool PR = false, bool FS = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 ? 2 : 4)))
     k_flux_hex(HexGrid H, const TC* __restrict__ coef, const double* __restrict__ geo,
                const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy, TC* __restrict__ fz,
@@ -1051,8 +1189,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
   flux_block(b, nbs, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
   double* vface = D == 0 ? vx : (D == 1 ? vy : vz);
-  __shared__ double stash[18][kBlock];
-  flux_hex_face<TC, PR>(H, coef, geo, mask, face, vface, gp, dt, idt, N, lb, D, stash);
+  __shared__ double stash[kHexStash<FS>][kBlock];
+  flux_hex_face<TC, PR, FS>(H, coef, geo, mask, face, vface, gp, dt, idt, N, lb, D, stash);
 }
 
 // ---------------------------------------------------------------- K4
@@ -1159,11 +1297,14 @@ __global__ void __launch_bounds__(kBlock) k_totals_hex(const double* __restrict_
 }
 
 // ---------------------------------------------------------------- debug
+// Gauss-point states of every cell (parity hook).  fs_stride != 0: per-face
+// reconstructions in characteristic variables (arrays fs_stride apart),
+// projected back with the face's eigenvectors.
 template <typename TC>
 __global__ void __launch_bounds__(kBlock) k_debug_gp_hex(HexGrid H, const TC* __restrict__ coef,
                                                          const double* __restrict__ geo,
-                                                         const uint32_t* __restrict__ mask, size_t N,
-                                                         double* __restrict__ out) {
+                                                         const uint32_t* __restrict__ mask, size_t N, double gamma,
+                                                         size_t fs_stride, double* __restrict__ out) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
   int i, j, k;
@@ -1178,7 +1319,28 @@ __global__ void __launch_bounds__(kBlock) k_debug_gp_hex(HexGrid H, const TC* __
     FacePoint P;
     face_point(cx, cu, (gp >> 1) ? kGaussNode : -kGaussNode, (gp & 1) ? kGaussNode : -kGaussNode, P);
     TC val[5], grad[5][3];
-    eval_hex(coef, geo, N, idx, zero, P.x, (mask[idx] >> bit) & 1u, val, grad);
+    const bool fb = (mask[idx] >> bit) & 1u;
+    if (fs_stride) {
+      // the neighbour across face f and its reconstruction for that face
+      int nc[3] = {i, j, k};
+      nc[d] += (f & 1) ? 1 : -1;
+      double sh[3];
+      const size_t in = hex_index(H, nc[0], nc[1], nc[2], sh);
+      constexpr int CB = kCB<TC>;
+      const TC* cv = coef + (size_t)f * fs_stride + coef_cell<TC>(idx);
+      const TC* cn = coef + (size_t)(f ^ 1) * fs_stride + coef_cell<TC>(in);
+      double Qb[5];
+      for (int v = 0; v < 5; ++v) Qb[v] = 0.5 * ((double)cv[10 * v * CB] + (double)cn[10 * v * CB]);
+      FacePoint Pc;
+      face_point(cx, cu, 0.0, 0.0, Pc);
+      double fn[3], f1[3], f2[3];
+      face_frame(Pc, fn, f1, f2);
+      CharFrame B;
+      char_frame(Qb, fn, f1, f2, gamma, B);
+      eval_char_hex(cv, geo, N, idx, zero, P.x, fb, B, val, grad);
+    } else {
+      eval_hex(coef, geo, N, idx, zero, P.x, fb, val, grad);
+    }
     for (int v = 0; v < 5; ++v) {
       double* o = out + ((idx * 24 + bit) * 5 + v) * 4;
       o[0] = val[v];

@@ -18,6 +18,7 @@
 #include "hex_kernels.h"
 #include "batch_kernels.h"
 #include "char_box.h"
+#include "char_hex.h"
 
 using namespace hgks;
 
@@ -68,7 +69,6 @@ bool valid_config(const hgks_config* c) {
   if (c->precision != HGKS_FP64 && c->precision != HGKS_MIXED) return false;
   if (c->moving != 0 && c->moving != 1) return false;
   if (c->characteristic != 0 && c->characteristic != 1) return false;
-  if (c->characteristic && c->moving) return false;
   if (!(c->mu_T0 > 0.0) || !std::isfinite(c->mu_exponent) || !(c->prandtl > 0.0) || !std::isfinite(c->prandtl))
     return false;
   // the stencils of Remark 1: box grids, component-wise reconstruction; a
@@ -401,17 +401,35 @@ hgks_status hex_stage(hgks_ctx c, const double* qin, double dt, double alpha) {
                        c->mask(), c->cfg.gamma - 1.0, N);
   prof_mark(c, HGKS_PHASE_FALLBACK, false);
   if (hgks_status s = launched(c, "positivity")) return s;
+  const bool fs = c->cfg.characteristic != 0;
+  if (fs) {
+    // six per-face reconstructions in characteristic variables; the
+    // component-wise one above supplies the fallback mask
+    prof_mark(c, HGKS_PHASE_RECON, true);
+    hipLaunchKernelGGL((k_char_recon_hex<TC>), dim3(pad8(ntiles)), dim3(kBlock), 0, c->stream, H, c->geo(), qin,
+                       (TC*)c->coef() + c->G.fs_stride, c->G.fs_stride, P, c->cfg.gamma, N, ntx, nty, ntiles);
+    prof_mark(c, HGKS_PHASE_RECON, false);
+    if (hgks_status s = launched(c, "characteristic recon")) return s;
+  }
   const unsigned nb = blocks_for(4 * N);
   prof_mark(c, HGKS_PHASE_FLUX, true);
-  // the extended viscous model is a compile-time variant
-  if (c->cfg.prandtl != 1.0 || c->cfg.mu_exponent != 0.0)
-    hipLaunchKernelGGL((k_flux_hex<TC, true>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H,
-                       (const TC*)c->coef(), c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2),
-                       c->vface(0), c->vface(1), c->vface(2), gp, TC(dt), TC(1.0 / dt), N, nb);
+  // the extended viscous model and the per-face arrays are compile-time
+  // variants
+  const bool ext = c->cfg.prandtl != 1.0 || c->cfg.mu_exponent != 0.0;
+  const TC* fc = (const TC*)c->coef() + (fs ? c->G.fs_stride : 0);
+#define HGKS_HEX_FLUX(E, F)                                                                                      \
+  hipLaunchKernelGGL((k_flux_hex<TC, E, F>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H, fc, c->geo(),    \
+                     c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->vface(0), c->vface(1),     \
+                     c->vface(2), gp, TC(dt), TC(1.0 / dt), N, nb)
+  if (ext && fs)
+    HGKS_HEX_FLUX(true, true);
+  else if (ext)
+    HGKS_HEX_FLUX(true, false);
+  else if (fs)
+    HGKS_HEX_FLUX(false, true);
   else
-    hipLaunchKernelGGL((k_flux_hex<TC>), dim3(pad8(3 * nb)), dim3(kBlock), 0, c->stream, H, (const TC*)c->coef(),
-                       c->geo(), c->mask(), (TC*)c->face(0), (TC*)c->face(1), (TC*)c->face(2), c->vface(0),
-                       c->vface(1), c->vface(2), gp, TC(dt), TC(1.0 / dt), N, nb);
+    HGKS_HEX_FLUX(false, false);
+#undef HGKS_HEX_FLUX
   prof_mark(c, HGKS_PHASE_FLUX, false);
   return launched(c, "flux");
 }
@@ -464,12 +482,13 @@ hgks_status hex_debug_gp(hgks_ctx c, double dt, double* out) {
   hgks_status s = c->mixed() ? hex_stage<float>(c, c->q(), dt, 0.0) : hex_stage<double>(c, c->q(), dt, 0.0);
   if (s) return s;
   const HexGrid H = hex_grid(c, dt, 0.0, true);
+  const size_t fs = c->cfg.characteristic ? c->G.fs_stride : 0;
   if (c->mixed())
     hipLaunchKernelGGL((k_debug_gp_hex<float>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H,
-                       (const float*)c->coef(), c->geo(), c->mask(), c->D.N, out);
+                       (const float*)c->coef() + fs, c->geo(), c->mask(), c->D.N, c->cfg.gamma, fs, out);
   else
     hipLaunchKernelGGL((k_debug_gp_hex<double>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, H,
-                       (const double*)c->coef(), c->geo(), c->mask(), c->D.N, out);
+                       (const double*)c->coef() + fs, c->geo(), c->mask(), c->D.N, c->cfg.gamma, fs, out);
   return launched(c, "debug gp");
 }
 
@@ -609,6 +628,7 @@ hgks_status hgks_set_vertices(hgks_ctx c, const double* xyz_dev, const double pe
     return s;
   for (int d = 0; d < 3; ++d) c->period[d] = period[d];
   hex_setup(c->H, c->D.n, period);
+  c->H.box.fs_stride = c->G.fs_stride;  // per-face arrays (characteristic variables)
   c->grid_set = true;
   c->next_set = false;
   return HGKS_OK;

@@ -457,7 +457,9 @@ def hgks_batch_sync(h):
 
 class Batch:
     """Independent periodic box grids advanced together.  ``grids`` is a
-    list of dicts with keys n (nx, ny, nz), length (Lx, Ly, Lz) and mu."""
+    list of dicts with keys n (nx, ny, nz), length (Lx, Ly, Lz) and mu, and
+    optionally the grid's own viscosity law and Prandtl number (mu_T0,
+    mu_exponent, prandtl); keyword arguments set a field for every grid."""
 
     def __init__(self, grids, gamma=1.4, precision="mixed", device="cuda:0", stream=None, **kw):
         self.device = torch.device(device)
@@ -471,6 +473,9 @@ class Batch:
             cfg.precision = PREC[precision]
             for k, v in kw.items():
                 setattr(cfg, k, v)
+            for k in ("mu_T0", "mu_exponent", "prandtl"):
+                if k in g:
+                    setattr(cfg, k, g[k])
             cfg.stream = ctypes.c_void_p(stream.cuda_stream)
             cfgs.append(cfg)
         self.cfgs = cfgs

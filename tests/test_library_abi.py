@@ -93,17 +93,16 @@ def test_step_checked_workspace(lib):
 
 def test_characteristic_workspace_and_limits(lib):
     """Characteristic mode keeps six per-face coefficient arrays beside the
-    cell array; it is offered on box grids only, not in batches."""
+    cell array, on box and hexahedral grids; not in batches."""
     from paper_1909_01580_amd import hgks
-    cfg = hgks.hgks_default_config(16, 12, 10)
-    assert cfg.characteristic == 0
-    n0 = hgks.hgks_workspace_size(cfg)
-    cfg.characteristic = 1
-    n1 = hgks.hgks_workspace_size(cfg)
-    assert n1 - n0 >= 6 * 50 * 8 * 16 * 12 * 10
-    cfg.moving = 1
-    with pytest.raises(hgks.HGKSError):
-        hgks.hgks_workspace_size(cfg)
+    for moving in (0, 1):
+        cfg = hgks.hgks_default_config(16, 12, 10)
+        cfg.moving = moving
+        assert cfg.characteristic == 0
+        n0 = hgks.hgks_workspace_size(cfg)
+        cfg.characteristic = 1
+        n1 = hgks.hgks_workspace_size(cfg)
+        assert n1 - n0 >= 6 * 50 * 8 * 16 * 12 * 10
     cfg.moving = 0
     with pytest.raises(hgks.HGKSError):
         hgks.hgks_batch_workspace_size([cfg])
