@@ -89,17 +89,22 @@ HGKS_FN void full_line(T U, T h, T (&m)[7]) {
   for (int k = 1; k < 6; ++k) m[k + 1] = U * m[k] + T(k) * h * m[k - 1];
 }
 
-// Half-line u-moments; SIDE = +1: u > 0, SIDE = -1: u < 0.  il = 2 lambda
+// Half-line u-moments; sg = +1: u > 0, sg = -1: u < 0.  il = 2 lambda
 // = 1/h; 1/sqrt(lambda) = 2 h sqrt(lambda), so no division is needed.
-template <int SIDE, typename T>
-HGKS_FN void half_line(T U, T h, T il, T (&m)[7]) {
+template <typename T>
+HGKS_FN void half_line_s(T U, T h, T il, T sg, T (&m)[7]) {
   const T lam = T(0.5) * il;
   const T sl = d_sqrt(lam);
   const T inv_sqrt_pi = T(0.56418958354775628694807945156077259);
-  m[0] = T(0.5) * d_erfc(T(-SIDE) * sl * U);
-  m[1] = U * m[0] + T(SIDE) * inv_sqrt_pi * h * sl * d_exp(-lam * U * U);
+  m[0] = T(0.5) * d_erfc(-sg * sl * U);
+  m[1] = U * m[0] + sg * inv_sqrt_pi * h * sl * d_exp(-lam * U * U);
 #pragma unroll
   for (int k = 1; k < 6; ++k) m[k + 1] = U * m[k] + T(k) * h * m[k - 1];
+}
+
+template <int SIDE, typename T>
+HGKS_FN void half_line(T U, T h, T il, T (&m)[7]) {
+  half_line_s(U, h, il, T(SIDE), m);
 }
 
 // A micro-slope prepared for moments: tangential mean alpha(u) = c0 + a2 u +
@@ -232,12 +237,6 @@ HGKS_FN void axpy5(T s, const T (&x)[5], T (&y)[5]) {
   for (int i = 0; i < 5; ++i) y[i] += s * x[i];
 }
 
-// Contributions of one side (SIDE = +1: left state, particles with u > 0;
-// SIDE = -1: right state, u < 0).  W: conservative variables in the local
-// frame; dW[j]: their derivatives along n_x, n_y, n_z.  The three
-// micro-slopes are formed and consumed one at a time, so that only one is
-// live: each adds its full-line term to the compatibility residual (which
-// gives A) and its half-line terms to dQ0[j] and X5.
 // Primitive quantities of a state with conservative variables Q, from one
 // reciprocal: with p2 = 2 rho E - |M|^2 = 2 rho p / (gamma - 1) and
 // R = 1 / (rho p2), 1/rho = p2 R and 2 lambda = rho/p = (2/(gamma-1)) rho^2/p2.
@@ -264,8 +263,16 @@ HGKS_FN void primitives(const T (&Q)[5], const GasParams<T>& g, Prim<T>& s) {
   s.c5 = s.il * s.il * g.inv_K3;             // 4 lambda^2 / (K + 3)
 }
 
-template <int SIDE, bool PR = false, typename T>
-HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>& g, FluxAcc<T>& A) {
+// Contributions of one side (sg = +1: left state, particles with u > 0;
+// sg = -1: right state, u < 0; sg may be a runtime value).  W: conservative
+// variables in the local frame; dW[j]: their derivatives along n_x, n_y,
+// n_z.  The three micro-slopes are formed and consumed one at a time, so
+// that only one is live: each adds its full-line term to the compatibility
+// residual (which gives A) and its half-line terms to dQ0[j] and X5.  The
+// side's pressure goes to pside.
+template <bool PR = false, typename T>
+HGKS_FN void side_terms_s(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>& g, T sg, FluxAcc<T>& A,
+                          T& pside) {
   Prim<T> P;
   primitives(W, g, P);
   const T rho = P.rho, U = P.U, V = P.V, Wv = P.W, p = P.p, h = P.h, il = P.il, q = P.q, c5 = P.c5;
@@ -273,7 +280,7 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
   tang_init(t, V, Wv, h, g);
   T mf[7], mh[7];
   full_line(U, h, mf);
-  half_line<SIDE>(U, h, il, mh);
+  half_line_s(U, h, il, sg, mh);
 
   // r = rho <(a_1 u + a_2 v + a_3 w) psi>, then A from <(a.u + A) psi> = 0.
   T r[5];
@@ -322,7 +329,12 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
   axpy5(rho, v5, A.Q0);
   mom_psi<1>(t, mh, v5);
   axpy5(rho, v5, A.X4);
-  A.p[SIDE > 0 ? 0 : 1] = p;
+  pside = p;
+}
+
+template <int SIDE, bool PR = false, typename T>
+HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>& g, FluxAcc<T>& A) {
+  side_terms_s<PR>(W, dW, g, T(SIDE), A, A.p[SIDE > 0 ? 0 : 1]);
 }
 
 // Register budget of the flux kernels: at least two waves per SIMD, so
@@ -353,19 +365,32 @@ HGKS_FN void time_integrals(T delta, T tau, T E, T (&Tc)[5]) {
   Tc[4] = T(2) * tau * tau * om - tau * delta * E;
 }
 
-// Equilibrium part, collision time and the time fit.  On return F and dF
-// hold the flux and its time derivative in the local frame; A.Q0 holds the
-// conservative variables of g_0.  The collision time and the coefficients
-// of the time fit come first, so that every moment is folded into F and dF
-// as soon as it is formed.
+// The state of g_0 and the coefficients of the time fit: everything the
+// moments of the equilibrium part and the folding into F and dF need.
+template <typename T>
+struct EqState {
+  T r0, U, V, W, h, il, q, c5, tau;
+  T c[5], d[5];  // F- and dF-coefficients of the five time integrals
+  Tang<T> t;
+  T m[7];        // full-line u-moments of g_0
+};
+
+// Collision time and the time fit from the summed accumulators (A.Q0 the
+// conservative variables of g_0, A.p the two sides' pressures).
 // PR: the extended viscous model -- the viscosity law and the Prandtl
 // correction (either may be trivial: mu_exp = 0, pr_fix = 0).
 template <bool PR = false, typename T>
-HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&F)[5], T (&dF)[5]) {
+HGKS_FN void eq_state(const FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, EqState<T>& e) {
   Prim<T> P;
   primitives(A.Q0, g, P);
-  const T r0 = P.rho, U = P.U, V = P.V, W = P.W, h = P.h, il = P.il, q = P.q, c5 = P.c5;
-
+  e.r0 = P.rho;
+  e.U = P.U;
+  e.V = P.V;
+  e.W = P.W;
+  e.h = P.h;
+  e.il = P.il;
+  e.q = P.q;
+  e.c5 = P.c5;
   const T jump = d_abs(A.p[0] - A.p[1]) * d_rcp(A.p[0] + A.p[1]) * dt;
   // mu / p_0 = mu (rho_0 / p_0) (1 / rho_0); mu = mu0 (T / T0)^omega with
   // T = p_0 / rho_0 when a viscosity law is set
@@ -373,114 +398,139 @@ HGKS_FN void finish_flux(FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&
   if constexpr (PR) {
     if (g.mu_exp != T(0)) mu *= exp(g.mu_exp * log(P.h * g.mu_iT0));
   }
-  const T tau = g.viscous ? mu * il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
-  const T itau = T(1) / tau;
-  T c[5], d[5];
+  e.tau = g.viscous ? mu * P.il * P.ir + g.tau_C * jump : g.tau_eps * dt + g.tau_C * jump;
+  const T itau = T(1) / e.tau;
   {
     T Tf[5], Th[5];
     // exp(-dt / tau) as the square of exp(-dt / (2 tau))
     const T Eh = d_exp(T(-0.5) * dt * itau);
-    time_integrals(dt, tau, Eh * Eh, Tf);
-    time_integrals(T(0.5) * dt, tau, Eh, Th);
+    time_integrals(dt, e.tau, Eh * Eh, Tf);
+    time_integrals(T(0.5) * dt, e.tau, Eh, Th);
     const T idt2 = T(4) * idt * idt;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
-      c[i] = (T(4) * Th[i] - Tf[i]) * idt;
-      d[i] = (Tf[i] - T(2) * Th[i]) * idt2;
+      e.c[i] = (T(4) * Th[i] - Tf[i]) * idt;
+      e.d[i] = (Tf[i] - T(2) * Th[i]) * idt2;
     }
   }
-  // Non-equilibrium part: T4, T5 and tau T4 terms.
-  {
-    const T c6 = tau * c[3], d6 = tau * d[3];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      F[i] = c[3] * A.X4[i] - c[4] * A.X5[i] - c6 * A.X6[i];
-      dF[i] = d[3] * A.X4[i] - d[4] * A.X5[i] - d6 * A.X6[i];
-    }
-  }
+  tang_init(e.t, e.V, e.W, e.h, g);
+  full_line(e.U, e.h, e.m);
+}
 
-  Tang<T> t;
-  tang_init(t, V, W, h, g);
-  T m[7];
-  full_line(U, h, m);
-  T v5[5];
-  mom_psi<1>(t, m, v5);
-  {
-    const T c0 = c[0] * r0, d0 = d[0] * r0;
+// Non-equilibrium part (T4, T5 and tau T4 terms) of the sums in A:
+// F = c3 X4 - c4 X5 - tau c3 X6 (likewise dF).
+template <typename T>
+HGKS_FN void fold_noneq(const FluxAcc<T>& A, const EqState<T>& e, T (&F)[5], T (&dF)[5]) {
+  const T c6 = e.tau * e.c[3], d6 = e.tau * e.d[3];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      F[i] += c0 * v5[i];
-      dF[i] += d0 * v5[i];
-    }
+  for (int i = 0; i < 5; ++i) {
+    F[i] = e.c[3] * A.X4[i] - e.c[4] * A.X5[i] - c6 * A.X6[i];
+    dF[i] = e.d[3] * A.X4[i] - e.d[4] * A.X5[i] - d6 * A.X6[i];
   }
-  // abar_j from dQ0[j] (carrying rho_0), one at a time; the T2 term and the
-  // compatibility residual that gives Abar.
+}
+
+// T1 term: rho_0 <u psi>_0.
+template <typename T>
+HGKS_FN void fold_eq_mean(const EqState<T>& e, T (&F)[5], T (&dF)[5]) {
+  T v5[5];
+  mom_psi<1>(e.t, e.m, v5);
+  const T c0 = e.c[0] * e.r0, d0 = e.d[0] * e.r0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    F[i] += c0 * v5[i];
+    dF[i] += d0 * v5[i];
+  }
+}
+
+// Micro-slope abar_J of g_0 from its moments b = dQ0[J] (carrying rho_0):
+// its T2 term into F and dF, its part of the compatibility residual into r
+// (assigned when ACC is false).
+template <int J, bool ACC, typename T>
+HGKS_FN void fold_abar(const EqState<T>& e, const T (&b)[5], T (&r)[5], T (&F)[5], T (&dF)[5]) {
+  T a[5];
+  Slope<T> s;
+  micro_slope(b, e.U, e.V, e.W, e.il, e.q, e.c5, a);
+  slope_prep(a, e.t, s);
+  T v5[5];
+  if constexpr (J == 0) {
+    mom_a<1, ACC>(s, e.t, e.m, r);
+    mom_a<2, false>(s, e.t, e.m, v5);
+  } else if constexpr (J == 1) {
+    mom_av<0, ACC>(s, e.t, e.m, r);
+    mom_av<1, false>(s, e.t, e.m, v5);
+  } else {
+    mom_aw<0, ACC>(s, e.t, e.m, r);
+    mom_aw<1, false>(s, e.t, e.m, v5);
+  }
+  axpy5(e.c[1], v5, F);
+  axpy5(e.d[1], v5, dF);
+}
+
+// Time derivative Abar of g_0 from rA = rho_0 <Abar psi> (minus the
+// compatibility residual): its T3 term into F and dF.
+template <typename T>
+HGKS_FN void fold_Abar(const EqState<T>& e, const T (&rA)[5], T (&F)[5], T (&dF)[5]) {
+  T a[5];
+  Slope<T> s;
+  micro_slope(rA, e.U, e.V, e.W, e.il, e.q, e.c5, a);
+  slope_prep(a, e.t, s);
+  T v5[5];
+  mom_a<1, false>(s, e.t, e.m, v5);
+  axpy5(e.c[2], v5, F);
+  axpy5(e.d[2], v5, dF);
+}
+
+// X_E - U.X_M + |U|^2/2 X_rho for a moment vector X and the velocity U of
+// g_0: the heat-flux form of the Prandtl correction below.
+template <typename T>
+HGKS_FN T heat_form(const EqState<T>& e, const T (&X)[5]) {
+  const T u2 = T(0.5) * (e.U * e.U + e.V * e.V + e.W * e.W);
+  return X[4] - (e.U * X[1] + e.V * X[2] + e.W * X[3]) + u2 * X[0];
+}
+
+// Prandtl correction: the heat flux relative to the velocity (U, V, W) of
+// g_0 is the moment of (u - U)(|c|^2 + xi^2)/2, which expands into the
+// fluxes F and the state moments S of the same distribution:
+//   q = F_E - U.F_M + |U|^2/2 F_rho - U (S_E - U.S_M + |U|^2/2 S_rho).
+// S over time: g_0's moments Q0 (T1 and T4 terms), rho_0 <Abar psi> = rA
+// (T3 - T2) and the initial slopes and time derivatives (-T5 S5,
+// -tau T4 S6); fitted with the same coefficients as the flux.
+template <typename T>
+HGKS_FN void prandtl_fix(const FluxAcc<T>& A, const EqState<T>& e, const T (&rA)[5], const GasParams<T>& g,
+                         T (&F)[5], T (&dF)[5]) {
+  T S[5], dS[5];
+  const T ce = e.c[0] + e.c[3], de = e.d[0] + e.d[3], cr = e.c[2] - e.c[1], dr = e.d[2] - e.d[1];
+  const T c6 = e.tau * e.c[3], d6 = e.tau * e.d[3];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    S[i] = ce * A.Q0[i] + cr * rA[i] - e.c[4] * A.S5[i] - c6 * A.S6[i];
+    dS[i] = de * A.Q0[i] + dr * rA[i] - e.d[4] * A.S5[i] - d6 * A.S6[i];
+  }
+  const T qf = heat_form(e, F) - e.U * heat_form(e, S);
+  const T dq = heat_form(e, dF) - e.U * heat_form(e, dS);
+  F[4] += g.pr_fix * qf;
+  dF[4] += g.pr_fix * dq;
+}
+
+// Equilibrium part, collision time and the time fit.  On return F and dF
+// hold the flux and its time derivative in the local frame.  The collision
+// time and the coefficients of the time fit come first, so that every
+// moment is folded into F and dF as soon as it is formed; the micro-slopes
+// abar_j of g_0 are formed one at a time.
+template <bool PR = false, typename T>
+HGKS_FN void finish_flux(const FluxAcc<T>& A, const GasParams<T>& g, T dt, T idt, T (&F)[5], T (&dF)[5]) {
+  EqState<T> e;
+  eq_state<PR>(A, g, dt, idt, e);
+  fold_noneq(A, e, F, dF);
+  fold_eq_mean(e, F, dF);
   T r[5];
-  {
-    T a[5];
-    Slope<T> s;
-    micro_slope(A.dQ0[0], U, V, W, il, q, c5, a);
-    slope_prep(a, t, s);
-    mom_a<1, false>(s, t, m, r);
-    mom_a<2, false>(s, t, m, v5);
-    axpy5(c[1], v5, F);
-    axpy5(d[1], v5, dF);
-  }
-  {
-    T a[5];
-    Slope<T> s;
-    micro_slope(A.dQ0[1], U, V, W, il, q, c5, a);
-    slope_prep(a, t, s);
-    mom_av<0, true>(s, t, m, r);
-    mom_av<1, false>(s, t, m, v5);
-    axpy5(c[1], v5, F);
-    axpy5(d[1], v5, dF);
-  }
-  {
-    T a[5];
-    Slope<T> s;
-    micro_slope(A.dQ0[2], U, V, W, il, q, c5, a);
-    slope_prep(a, t, s);
-    mom_aw<0, true>(s, t, m, r);
-    mom_aw<1, false>(s, t, m, v5);
-    axpy5(c[1], v5, F);
-    axpy5(d[1], v5, dF);
-  }
+  fold_abar<0, false>(e, A.dQ0[0], r, F, dF);
+  fold_abar<1, true>(e, A.dQ0[1], r, F, dF);
+  fold_abar<2, true>(e, A.dQ0[2], r, F, dF);
 #pragma unroll
   for (int i = 0; i < 5; ++i) r[i] = -r[i];
-  {
-    T a[5];
-    Slope<T> s;
-    micro_slope(r, U, V, W, il, q, c5, a);
-    slope_prep(a, t, s);
-    mom_a<1, false>(s, t, m, v5);
-    axpy5(c[2], v5, F);
-    axpy5(d[2], v5, dF);
-  }
-  if constexpr (PR) {
-    // Prandtl correction: the heat flux relative to the velocity (U, V, W)
-    // of g_0 is the moment of (u - U)(|c|^2 + xi^2)/2, which expands into the
-    // fluxes F and the state moments S of the same distribution:
-    //   q = F_E - U.F_M + |U|^2/2 F_rho - U (S_E - U.S_M + |U|^2/2 S_rho).
-    // S over time: g_0's moments Q0 (T1 and T4 terms), rho_0 <Abar psi> = r
-    // (T3 - T2) and the initial slopes and time derivatives (-T5 S5,
-    // -tau T4 S6); fitted with the same coefficients as the flux.
-    const T u2 = T(0.5) * (U * U + V * V + W * W);
-    T S[5], dS[5];
-    const T ce = c[0] + c[3], de = d[0] + d[3], cr = c[2] - c[1], dr = d[2] - d[1];
-    const T c6 = tau * c[3], d6 = tau * d[3];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      S[i] = ce * A.Q0[i] + cr * r[i] - c[4] * A.S5[i] - c6 * A.S6[i];
-      dS[i] = de * A.Q0[i] + dr * r[i] - d[4] * A.S5[i] - d6 * A.S6[i];
-    }
-    const T B = S[4] - (U * S[1] + V * S[2] + W * S[3]) + u2 * S[0];
-    const T dB = dS[4] - (U * dS[1] + V * dS[2] + W * dS[3]) + u2 * dS[0];
-    const T qf = F[4] - (U * F[1] + V * F[2] + W * F[3]) + u2 * F[0] - U * B;
-    const T dq = dF[4] - (U * dF[1] + V * dF[2] + W * dF[3]) + u2 * dF[0] - U * dB;
-    F[4] += g.pr_fix * qf;
-    dF[4] += g.pr_fix * dq;
-  }
+  fold_Abar(e, r, F, dF);
+  if constexpr (PR) prandtl_fix(A, e, r, g, F, dF);
 }
 
 }  // namespace hgks
