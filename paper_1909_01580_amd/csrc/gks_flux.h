@@ -480,11 +480,10 @@ HGKS_FN void fold_Abar(const EqState<T>& e, const T (&rA)[5], T (&F)[5], T (&dF)
   axpy5(e.d[2], v5, dF);
 }
 
-// X_E - U.X_M + |U|^2/2 X_rho for a moment vector X and the velocity U of
-// g_0: the heat-flux form of the Prandtl correction below.
+// X_E - U.X_M + u2 X_rho for a moment vector X, the velocity U of g_0 and
+// u2 = |U|^2/2: the heat-flux form of the Prandtl correction below.
 template <typename T>
-HGKS_FN T heat_form(const EqState<T>& e, const T (&X)[5]) {
-  const T u2 = T(0.5) * (e.U * e.U + e.V * e.V + e.W * e.W);
+HGKS_FN T heat_form(const EqState<T>& e, T u2, const T (&X)[5]) {
   return X[4] - (e.U * X[1] + e.V * X[2] + e.W * X[3]) + u2 * X[0];
 }
 
@@ -506,8 +505,9 @@ HGKS_FN void prandtl_fix(const FluxAcc<T>& A, const EqState<T>& e, const T (&rA)
     S[i] = ce * A.Q0[i] + cr * rA[i] - e.c[4] * A.S5[i] - c6 * A.S6[i];
     dS[i] = de * A.Q0[i] + dr * rA[i] - e.d[4] * A.S5[i] - d6 * A.S6[i];
   }
-  const T qf = heat_form(e, F) - e.U * heat_form(e, S);
-  const T dq = heat_form(e, dF) - e.U * heat_form(e, dS);
+  const T u2 = T(0.5) * (e.U * e.U + e.V * e.V + e.W * e.W);
+  const T qf = heat_form(e, u2, F) - e.U * heat_form(e, u2, S);
+  const T dq = heat_form(e, u2, dF) - e.U * heat_form(e, u2, dS);
   F[4] += g.pr_fix * qf;
   dF[4] += g.pr_fix * dq;
 }
