@@ -119,10 +119,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       tsum[f] = rsum[f] = 0.0;
       db[f][0] = db[f][1] = db[f][2] = 0.0;
     }
-#pragma unroll 1
-    for (int m = 0; m < 24; ++m) {
-      double bq[5][3];
-      sub_fit<false>(nb, Ci, qc, m, bq);
+    each_sub_fit(nb, Ci, qc, [&](const double (&bq)[5][3]) {
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
         double bu[3];
@@ -138,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
         for (int e = 0; e < 3; ++e) db[f][e] += dr * bu[e];
       }
-    }
+    });
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
       const double tau = tsum[f] * (1.0 / 24.0);

@@ -379,33 +379,34 @@ __device__ __forceinline__ void sub_offsets_wide(int m, int (&o)[3][3]) {
   o[2][2] = sz;
 }
 
-// Linear least squares of a sub-stencil with NR neighbour rows at offsets
-// o for all five variables of cell i: b[v][3] in the scaled basis (NR = 4:
-// Sec. 2; NR = 3: Remark 1, where the square system is solved exactly).
-template <int NR, typename NB>
-__device__ __forceinline__ void sub_fit_rows(const NB& nb, const HexCell& Ci, const double (&qc)[5],
-                                             const int (&o)[NR][3], double (&b)[5][3]) {
-  double A[6] = {0, 0, 0, 0, 0, 0};  // xx, yy, zz, xy, yz, xz
+// Sums over rows of a sub-stencil's normal equations: A (xx, yy, zz, xy,
+// yz, xz) and r[v] = sum d dq[v].
+struct SubSums {
+  double A[6];
   double r[5][3];
+};
+
+template <typename NB>
+__device__ __forceinline__ void sub_add_row(const NB& nb, const HexCell& Ci, const double (&qc)[5], int ox, int oy,
+                                            int oz, SubSums& S) {
+  double d[3], mo[6], dq[5];
+  nb.template get<false>(ox, oy, oz, Ci, qc, d, mo, dq);
+  S.A[0] += d[0] * d[0];
+  S.A[1] += d[1] * d[1];
+  S.A[2] += d[2] * d[2];
+  S.A[3] += d[0] * d[1];
+  S.A[4] += d[1] * d[2];
+  S.A[5] += d[0] * d[2];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) r[v][0] = r[v][1] = r[v][2] = 0.0;
+  for (int v = 0; v < 5; ++v) {
 #pragma unroll
-  for (int s = 0; s < NR; ++s) {
-    double d[3], mo[6], dq[5];
-    nb.template get<false>(o[s][0], o[s][1], o[s][2], Ci, qc, d, mo, dq);
-    A[0] += d[0] * d[0];
-    A[1] += d[1] * d[1];
-    A[2] += d[2] * d[2];
-    A[3] += d[0] * d[1];
-    A[4] += d[1] * d[2];
-    A[5] += d[0] * d[2];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-#pragma unroll
-      for (int e = 0; e < 3; ++e) r[v][e] += d[e] * dq[v];
-    }
+    for (int e = 0; e < 3; ++e) S.r[v][e] += d[e] * dq[v];
   }
-  // closed-form inverse of the symmetric 3x3 normal matrix
+}
+
+// The linear fit from summed normal equations (closed-form 3x3 inverse).
+__device__ __forceinline__ void sub_solve(const SubSums& S, double (&b)[5][3]) {
+  const double* A = S.A;
   const double c00 = A[1] * A[2] - A[4] * A[4];
   const double c01 = A[5] * A[4] - A[3] * A[2];
   const double c02 = A[3] * A[4] - A[1] * A[5];
@@ -415,10 +416,26 @@ __device__ __forceinline__ void sub_fit_rows(const NB& nb, const HexCell& Ci, co
   const double idet = d_rcp(A[0] * c00 + A[3] * c01 + A[5] * c02);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    b[v][0] = idet * (c00 * r[v][0] + c01 * r[v][1] + c02 * r[v][2]);
-    b[v][1] = idet * (c01 * r[v][0] + c11 * r[v][1] + c12 * r[v][2]);
-    b[v][2] = idet * (c02 * r[v][0] + c12 * r[v][1] + c22 * r[v][2]);
+    b[v][0] = idet * (c00 * S.r[v][0] + c01 * S.r[v][1] + c02 * S.r[v][2]);
+    b[v][1] = idet * (c01 * S.r[v][0] + c11 * S.r[v][1] + c12 * S.r[v][2]);
+    b[v][2] = idet * (c02 * S.r[v][0] + c12 * S.r[v][1] + c22 * S.r[v][2]);
   }
+}
+
+// Linear least squares of a sub-stencil with NR neighbour rows at offsets
+// o for all five variables of cell i: b[v][3] in the scaled basis (NR = 4:
+// Sec. 2; NR = 3: Remark 1, where the square system is solved exactly).
+template <int NR, typename NB>
+__device__ __forceinline__ void sub_fit_rows(const NB& nb, const HexCell& Ci, const double (&qc)[5],
+                                             const int (&o)[NR][3], double (&b)[5][3]) {
+  SubSums S;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) S.A[e] = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) S.r[v][0] = S.r[v][1] = S.r[v][2] = 0.0;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) sub_add_row(nb, Ci, qc, o[s][0], o[s][1], o[s][2], S);
+  sub_solve(S, b);
 }
 
 // Linear fit of sub-stencil m of the stencil family (WIDE: Remark 1).
@@ -439,6 +456,42 @@ __device__ __forceinline__ void sub_fit(const NB& nb, const HexCell& Ci, const d
 // Sub-stencils of the family: 24 (Sec. 2) or 8 (Remark 1).
 template <bool WIDE>
 constexpr int kHexSubs = WIDE ? 8 : 24;
+
+// Calls take(b) with the fits of the 24 sub-stencils of Sec. 2 (the order
+// t * 8 + r with r = 0, 4, 1, 5, ...).  Sub-stencils t * 8 + r come in pairs
+// that differ only in the sign of their last row (the face neighbour along
+// e_c, bit 2 of r): the three shared rows (the face neighbours along e_a
+// and e_b and their edge neighbour) are summed once per pair, in the order
+// of sub_fit, so every fit equals sub_fit's.
+template <typename NB, typename F>
+__device__ __forceinline__ void each_sub_fit(const NB& nb, const HexCell& Ci, const double (&qc)[5], F&& take) {
+#pragma unroll 1
+  for (int p = 0; p < 12; ++p) {
+    const int t = p >> 2, ea = t, eb = (t + 1) % 3, ec = (t + 2) % 3;
+    const int sa = (p & 1) ? -1 : 1, sb = (p & 2) ? -1 : 1;
+    int oa[3] = {0, 0, 0}, ob[3] = {0, 0, 0}, oe[3] = {0, 0, 0};
+    oa[ea] = sa;
+    ob[eb] = sb;
+    oe[ea] = sa;
+    oe[eb] = sb;
+    SubSums S3;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) S3.A[e] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) S3.r[v][0] = S3.r[v][1] = S3.r[v][2] = 0.0;
+    sub_add_row(nb, Ci, qc, oa[0], oa[1], oa[2], S3);
+    sub_add_row(nb, Ci, qc, ob[0], ob[1], ob[2], S3);
+    sub_add_row(nb, Ci, qc, oe[0], oe[1], oe[2], S3);
+#pragma unroll
+    for (int sc = 1; sc >= -1; sc -= 2) {
+      SubSums S = S3;
+      sub_add_row(nb, Ci, qc, ec == 0 ? sc : 0, ec == 1 ? sc : 0, ec == 2 ? sc : 0, S);
+      double b[5][3];
+      sub_solve(S, b);
+      take(b);
+    }
+  }
+}
 
 // Quadratic least squares of the big stencil for all five variables: the
 // row of neighbour o is the mean over o of (X, X_x^2 - m_xx, ...,
@@ -667,10 +720,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     for (int e = 0; e < 9; ++e) cv[(e + 1) * kCB<TS>] = TS(a[v][e]);
   }
   asm volatile("" ::: "memory");
-#pragma unroll 1
-  for (int m = 0; m < kHexSubs<WIDE>; ++m) {
-    double b[5][3];
-    sub_fit<WIDE>(nb, Ci, qc, m, b);
+  auto take = [&](const double (&b)[5][3]) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       const double bm = b[v][0] * b[v][0] + b[v][1] * b[v][1] + b[v][2] * b[v][2];
@@ -682,6 +732,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
       for (int e = 0; e < 3; ++e) db[v][e] += dr * b[v][e];
       bnd[v] = fmax(bnd[v], fabs(b[v][0]) * pmax[0] + fabs(b[v][1]) * pmax[1] + fabs(b[v][2]) * pmax[2]);
     }
+  };
+  if constexpr (WIDE) {
+#pragma unroll 1
+    for (int m = 0; m < kHexSubs<WIDE>; ++m) {
+      double b[5][3];
+      sub_fit<WIDE>(nb, Ci, qc, m, b);
+      take(b);
+    }
+  } else {
+    each_sub_fit(nb, Ci, qc, take);
   }
   double S[5], wb[5][3], w0r[5];
 #pragma unroll
