@@ -214,9 +214,16 @@ def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2, prandtl=
         b.set_state(i, torch.tensor(p["state"], device="cuda:0"))
     b.sync()
     tot0 = b.totals()
-    table = None
+    table = tuning = None
     if tune:
-        table, _ = autotune.tune(b)
+        table, timings = autotune.tune(b)
+        # ms per batched step of every candidate the tuner timed (the last
+        # sweep's value for the workgroup counts)
+        tuning = {"tile": {"x".join(map(str, k[1])): v for k, v in timings.items() if k[0] == "tile"},
+                  "flux_band": {str(k[1]): v for k, v in timings.items() if k[0] == "flux_band"}}
+        for k, v in timings.items():
+            if isinstance(k[0], int):
+                tuning.setdefault(hgks.PHASES[k[0]] + "_workgroups", {})[str(k[1])] = v
     b.capture(0.35, steps, 2)
     b.replay()                      # warm-up replay
     b.sync()
@@ -232,7 +239,8 @@ def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2, prandtl=
     states = [b.get_state(i).cpu().numpy() for i in range(b.n)]
     tot1 = b.totals()
     out = {"cells": cells, "grids": len(grids), "ms": ms, "steps": steps,
-           "value": cells * 2 * steps / (ms / 1e3), "launch_table": table, "states": states,
+           "value": cells * 2 * steps / (ms / 1e3), "launch_table": table, "tuning_ms_per_step": tuning,
+           "states": states,
            "drift": max(drift(t0, t1) for t0, t1 in zip(tot0, tot1))}
     if unbatched_steps:
         # The same problems one context at a time (same precision).  Each
@@ -727,6 +735,7 @@ def main():
             "max_norm_error_vs_fp64": worst.tolist(),
             "conservation_rel_drift": {"mixed": bm["drift"], "fp64": b64["drift"]},
             "launch_table": bm["launch_table"],
+            "tuning_ms_per_step": bm["tuning_ms_per_step"],
         }
         bp = run_batched(args.batched_steps, "mixed", tune=False, unbatched_steps=0, prandtl=0.72)
         out["batched"]["prandtl_0.72"] = {
