@@ -71,8 +71,9 @@ bool valid_config(const hgks_config* c) {
   if (c->characteristic != 0 && c->characteristic != 1) return false;
   if (!(c->mu_T0 > 0.0) || !std::isfinite(c->mu_exponent) || !(c->prandtl > 0.0) || !std::isfinite(c->prandtl))
     return false;
-  // the stencils of Remark 1: box grids, component-wise reconstruction; a
-  // mirror two cells past the ghost layer needs three cells on that axis
+  // the stencils of Remark 1: component-wise reconstruction (box and
+  // hexahedral grids); a mirror two cells past the ghost layer needs three
+  // cells on that axis
   if (c->stencil != 0 && c->stencil != 1) return false;
   if (c->stencil && (c->characteristic || !(c->weno_Gamma < 1.0 / 24.0))) return false;
   if (c->stencil) {
@@ -84,7 +85,7 @@ bool valid_config(const hgks_config* c) {
     for (int d = 0; d < 3; ++d)
       if (c->bc[d] != HGKS_BC_PERIODIC) return false;
   // Cell and face indices are split in 32-bit arithmetic.
-  if ((uint64_t)(c->nx + 2) * (uint64_t)(c->ny + 2) * (uint64_t)(c->nz + 2) >= (1ull << 32)) return false;
+  if (((uint64_t)c->nx + 2) * ((uint64_t)c->ny + 2) * ((uint64_t)c->nz + 2) >= (1ull << 32)) return false;
   return true;
 }
 

@@ -51,7 +51,9 @@ def test_defaults_and_workspace(lib):
 
 @pytest.mark.parametrize("field,value", [("nx", 1), ("gamma", 1.0), ("weno_Gamma", 0.05),
                                          ("weno_eps", 0.0), ("precision", 7), ("moving", 2),
-                                         ("characteristic", 2), ("mu_T0", 0.0), ("prandtl", 0.0)])
+                                         ("characteristic", 2), ("mu_T0", 0.0), ("prandtl", 0.0),
+                                         # cell and face indices are split in 32 bits
+                                         ("nx", 2 ** 31 - 1), ("nz", 1 << 26)])
 def test_invalid_configurations_rejected(lib, field, value):
     from paper_1909_01580_amd import hgks
     cfg = hgks.hgks_default_config(8, 8, 8)
