@@ -728,10 +728,10 @@ __device__ __forceinline__ void eval_char_gp_dir(int D, const TC* cv, const doub
 // l / 4 (face_of_block).
 // PR: the extended viscous model (viscosity law, Prandtl correction); FS:
 // per-face coefficient arrays (characteristic reconstruction).
-template <typename TC, bool PR = false, bool FS = false>
+template <typename TC, bool PR = false, bool FS = false, bool DMA = false>
 __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, const BoxGrid& G, const GasParams<TC>& gp,
-                                              TC dt, TC idt, unsigned lb, int D) {
+                                              TC dt, TC idt, unsigned lb, int D, TC* stage = nullptr) {
   const FaceAxes ax = face_axes(D);
   const int gpi = (int)(threadIdx.x & 3);
   int cR[3];
@@ -772,6 +772,50 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, WR, dWR);
     side_terms<+1, PR>(WL, dWL, gp, acc);
     side_terms<-1, PR>(WR, dWR, gp, acc);
+  } else if constexpr (DMA) {
+    // The right cells' 50 values go to LDS by direct loads issued before
+    // the left side's terms: they arrive while those run and hold no
+    // registers meanwhile.  Each wave copies the right cells of its own 16 faces into
+    // its own [50 rows][16 faces] array and reads only that array, after
+    // waiting for its own loads: no workgroup barrier.
+    static_assert(sizeof(TC) == 8 && kCB<TC> == 8, "rows of 8 doubles");
+    const unsigned l = threadIdx.x & 63u;
+    TC* rs = stage + (threadIdx.x >> 6) * (50 * 16);
+    // lane l copies dword l of every 64-dword piece: face slot (l / 2) % 16
+    // of the wave, row 2 k + l / 32 in piece k, half l % 2
+    unsigned src_cell = __shfl((unsigned)iR, (int)(((l >> 1) & 15u) * 4u));
+    {
+      TC W[5], dW[3][5];
+      eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
+      // The copies are issued once the left cell's values have arrived: the
+      // memory counter is waited on in issue order, so copies issued
+      // earlier would hold up the left side's first use of its loads.
+      asm volatile("" : "+v"(src_cell) : "v"(W[0]), "v"(dW[2][4]));
+      const char* src = (const char*)(coefR + coef_cell<TC>(src_cell)) + (l >> 5) * 64 + (l & 1u) * 4;
+      char __attribute__((address_space(3)))* dst = (char __attribute__((address_space(3)))*)rs;
+#pragma unroll
+      for (int k = 0; k < 25; ++k)
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 128 * k),
+                                         (void __attribute__((address_space(3)))*)(dst + 256 * k), 4, 0, 0);
+      side_terms<+1, PR>(W, dW, gp, acc);
+    }
+    // the right side's LDS reads wait for the left side's results and for
+    // this wave's copies
+    size_t slot = threadIdx.x >> 2 & 15u;
+    after_left_side(slot, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("" ::: "memory");
+    {
+      TC W[5], dW[3][5];
+      const TC* cv = rs + slot;
+      if (D == 0)
+        eval_rows_gp<0, 16>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
+      else if (D == 1)
+        eval_rows_gp<1, 16>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
+      else
+        eval_rows_gp<2, 16>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
+      side_terms<-1, PR>(W, dW, gp, acc);
+    }
   } else {
     {
       TC W[5], dW[3][5];
@@ -843,7 +887,12 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
   unsigned lb;
   flux_block(b, nb, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
-  flux_box_face<TC, PR, FS>(coef, mask, face, G, gp, dt, idt, lb, D);
+  if constexpr (sizeof(TC) == 8 && !FS) {
+    __shared__ double stage[kBlock / 64 * 50 * 16];
+    flux_box_face<TC, PR, FS, true>(coef, mask, face, G, gp, dt, idt, lb, D, stage);
+  } else {
+    flux_box_face<TC, PR, FS>(coef, mask, face, G, gp, dt, idt, lb, D);
+  }
 }
 
 // ---------------------------------------------------------------- update
