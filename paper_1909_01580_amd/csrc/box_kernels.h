@@ -723,7 +723,7 @@ __device__ __forceinline__ void eval_char_gp_dir(int D, const TC* cv, const doub
 }
 
 // One lane = one Gauss point of one face normal to axis D; the four lanes of
-// a face sum their weighted fluxes with lane shuffles.  Lane l of the
+// a face sum their weighted fluxes with quad-permute moves.  Lane l of the
 // 256-lane block lb of direction D takes Gauss point l % 4 of face slot
 // l / 4 (face_of_block).
 // PR: the extended viscous model (viscosity law, Prandtl correction); FS:
@@ -837,10 +837,8 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   for (int i = 0; i < 5; ++i) {
     F[i] *= w;
     dF[i] *= w;
-    F[i] += __shfl_xor(F[i], 1);
-    dF[i] += __shfl_xor(dF[i], 1);
-    F[i] += __shfl_xor(F[i], 2);
-    dF[i] += __shfl_xor(dF[i], 2);
+    F[i] = quad_xor_add<2>(quad_xor_add<1>(F[i]));
+    dF[i] = quad_xor_add<2>(quad_xor_add<1>(dF[i]));
   }
   if (live && gpi == 0) {
     const size_t NF = (size_t)G.nf[D][0] * G.nf[D][1] * G.nf[D][2];

@@ -117,6 +117,25 @@ template <> HGKS_FN float d_rcp<float>(float x) {
 #endif
 }
 
+// x plus x of lane l ^ MASK (MASK = 1 or 2) within each group of four
+// lanes: a quad-permute DPP move per 32-bit half, which the vector unit
+// does in the instruction itself (no LDS-unit round trip as for a general
+// lane shuffle).
+template <int MASK>
+__device__ __forceinline__ float quad_xor_add(float x) {
+  constexpr int ctrl = MASK == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+  return x + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+
+template <int MASK>
+__device__ __forceinline__ double quad_xor_add(double x) {
+  constexpr int ctrl = MASK == 1 ? 0xB1 : 0x4E;
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), ctrl, 0xF, 0xF, false);
+  return x + __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Workgroups are dispatched round-robin over the eight XCDs (block b runs
 // on XCD b % 8).  Remapping gives every XCD one contiguous range of logical
 // blocks, so that neighbouring tiles share an L2.  The grid must hold

@@ -1221,8 +1221,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   out[11] = 0.25 * rate;
 #pragma unroll
   for (int e = 0; e < 12; ++e) {
-    out[e] += __shfl_xor(out[e], 1);
-    out[e] += __shfl_xor(out[e], 2);
+    out[e] = quad_xor_add<2>(quad_xor_add<1>(out[e]));
   }
   if (live && gpi == 0) {
 #pragma unroll

@@ -37,6 +37,13 @@ CASES = {
     "symmetric_mixed_ends": dict(n=(9, 12, 10), L=(0.9, 1.2, 1.0),
                                  bc=(("symmetric", "outflow"), "periodic", ("outflow", "symmetric")), mu=0.0,
                                  state=lambda n, L: smooth_state(n, L, 5, mach=0.5)),
+    # degenerate extents: the smallest periodic grid the library takes (the
+    # stencil wraps onto the same cells), and a slab two cells thick with
+    # outflow ends (every cell is next to a ghost layer)
+    "tiny_periodic": dict(n=(2, 3, 2), L=(0.4, 0.6, 0.4), bc=("periodic",) * 3, mu=1e-3,
+                          state=lambda n, L: smooth_state(n, L, 6)),
+    "thin_outflow_slab": dict(n=(2, 17, 5), L=(0.2, 1.7, 0.5), bc=("outflow",) * 3, mu=0.0,
+                              state=lambda n, L: blast_state(n, L, centre=(0.1, 0.8, 0.25), radius=0.3)),
 }
 
 
