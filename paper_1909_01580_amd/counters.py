@@ -39,11 +39,36 @@ CYCLES_PER_VALU = 4     # a wave64 VALU instruction on a 16-lane SIMD
 XCDS = 8                # GRBM_GUI_ACTIVE sums the eight XCDs' busy cycles
 
 
+def code_only(text):
+    """C++ source without its comments and with whitespace runs collapsed:
+    what the compiler sees, so that a comment edit keeps a record valid."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif text[i] == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(names=FLUX_SOURCES):
+    """Hash of the code (comments excluded) of the flux kernel's sources."""
     h = hashlib.sha256()
     for name in names:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

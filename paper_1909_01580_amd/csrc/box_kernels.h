@@ -775,9 +775,9 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   } else if constexpr (DMA) {
     // The right cells' 50 values go to LDS by direct loads issued before
     // the left side's terms: they arrive while those run and hold no
-    // registers meanwhile.  Each wave copies the right cells of its own 16 faces into
-    // its own [50 rows][16 faces] array and reads only that array, after
-    // waiting for its own loads: no workgroup barrier.
+    // registers meanwhile.  Each wave copies the right cells of its own 16
+    // faces into its own [50 rows][16 faces] array and reads only that
+    // array, after waiting for its own loads: no workgroup barrier.
     static_assert(sizeof(TC) == 8 && kCB<TC> == 8, "rows of 8 doubles");
     const unsigned l = threadIdx.x & 63u;
     TC* rs = stage + (threadIdx.x >> 6) * (50 * 16);

@@ -337,10 +337,11 @@ HGKS_FN void side_terms(const T (&W)[5], const T (&dW)[3][5], const GasParams<T>
   side_terms_s<PR>(W, dW, g, T(SIDE), A, A.p[SIDE > 0 ? 0 : 1]);
 }
 
-// Register budget of the flux kernels: at least two waves per SIMD, so
-// that one wave's memory and transcendental latency hides behind another's
-// arithmetic.  In FP64 the compiler would otherwise keep one wave per SIMD
-// (over 256 registers); the few values that do not fit are spilled.
+// Register budget of the flux kernels: at least two waves per SIMD in FP64
+// (three in FP32), so that one wave's memory and transcendental latency
+// hides behind another's arithmetic.  Left to itself the compiler would
+// keep one FP64 wave per SIMD (over 256 registers); a third FP64 wave does
+// not fit without spilling the left side's sums.
 #define HGKS_FLUX_OCCUPANCY __attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 ? 2 : 3)))
 
 // Orders the loads of the right cell after the left side's terms.  The

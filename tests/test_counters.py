@@ -71,3 +71,11 @@ def test_pick_refuses_ambiguous(tmp_path):
     write_csv(p, [("1", FLUX64, "SQ_WAVES", 1), ("2", FLUX64.replace("true, false", "true, true"), "SQ_WAVES", 1)])
     with pytest.raises(SystemExit):
         counters.pick(counters.read_counters(str(p)), "k_flux_box", "<double")
+
+
+def test_code_only_ignores_comments_not_code():
+    a = 'int f(int x) { // the input\n  return x + 1; /* one more */ }\nconst char* s = "a // b";\n'
+    b = 'int f(int x) {\n  return x + 1;   }\nconst char* s = "a // b";'
+    assert counters.code_only(a) == counters.code_only(b)
+    assert counters.code_only(a) != counters.code_only(a.replace("x + 1", "x + 2"))
+    assert '"a // b"' in counters.code_only(a)
