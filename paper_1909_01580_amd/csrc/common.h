@@ -96,8 +96,9 @@ template <typename T> HGKS_FN T d_abs(T x) { return x < T(0) ? -x : x; }
 
 // Reciprocal of a nonzero finite x: the hardware estimate refined by
 // Newton-Raphson steps r <- r + r (1 - x r) (two in double, one in float),
-// which lands within an ulp or two of 1/x at a fraction of the cost of a
-// correctly rounded division.
+// at a fraction of the cost of a correctly rounded division.  On gfx950 the
+// FP64 estimate is within 2^-24.4 of 1/x; one step leaves up to 11 ulp, two
+// steps gave the correctly rounded 1/x on 4 million sampled inputs.
 template <typename T> HGKS_FN T d_rcp(T x);
 template <> HGKS_FN double d_rcp<double>(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
