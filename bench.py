@@ -559,6 +559,35 @@ def cpu_baseline(q0, n, pool, workers, first=None, c1_steps=20):
         "value": ne ** 3 * 2 / el, "processes": workers, "seconds": el,
         "sample": f"one two-stage step of the 64^3 spherical explosion (outflow), {workers} z-slabs with "
                   f"{HALO} halo planes per side"}
+    # (5) moving mesh: one step of the same node motion and stream on a 16^3 mesh, one thread
+    import math
+    nm = 16
+    v0 = wl.sine_mesh_vertices(nm, 0.0, amp=0.05, omega=2 * math.pi)
+    qm = wl.hex_average(v0, (2.0,) * 3, wl.pulse_point)
+    pm0 = oracle.vertex_problem((nm,) * 3, v0, (2.0,) * 3)
+    dtm = oracle.max_dt(pm0, qm, 0.35)
+    pm = oracle.vertex_problem((nm,) * 3, v0, (2.0,) * 3,
+                               verts_next=wl.sine_mesh_vertices(nm, dtm, amp=0.05, omega=2 * math.pi))
+    t0 = time.perf_counter()
+    oracle.step(pm, qm, dtm)
+    el = time.perf_counter() - t0
+    legs["moving16_one_thread"] = {
+        "value": nm ** 3 * 2 / el, "threads": 1, "seconds": el,
+        "sample": "one two-stage step of the moving-mesh workload's node motion and stream on a 16^3 mesh "
+                  "(the same cell work as at 128^3: per-cell least squares, bilinear faces, grid velocity)"}
+
+    # (6) batch: one step of the smallest of the 48 grids, pool
+    bp = min(wl.batch_problems(), key=lambda p: int(np.prod(p["n"])))
+    nb = bp["n"]
+    hb = tuple(bp["length"][d] / nb[d] for d in range(3))
+    qb = bp["state"]
+    pb = oracle.uniform_problem(nb, (0, 0, 0), bp["length"], params=oracle.Params(mu=bp["mu"]))
+    dtb = oracle.max_dt(pb, qb, 0.35)
+    _, el = pool_step(pool, qb, hb, ("periodic",) * 3, {"mu": bp["mu"]}, dtb, workers)
+    legs["batch_grid_pool"] = {
+        "value": int(np.prod(nb)) * 2 / el, "processes": workers, "seconds": el,
+        "sample": f"one two-stage step of the smallest of the 48 batch grids ({nb[0]} x {nb[1]} x {nb[2]}, "
+                  f"periodic), {workers} z-slabs with {HALO} halo planes per side"}
     if limiter is not None:
         limiter.unregister()
     rec = {"value": pool_value, "unit": "cell-stage updates/s", "cores": workers, "kind": "oracle",
