@@ -754,8 +754,9 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   // low face (the same array unless the faces have their own)
   const TC* coefL = FS ? coef + (size_t)(2 * D + 1) * G.fs_stride : coef;
   const TC* coefR = FS ? coef + (size_t)(2 * D) * G.fs_stride : coef;
+  // the left side assigns the sums, the right side adds to them
   FluxAcc<TC> acc;
-  acc_zero(acc);
+  acc_begin(acc);
   if constexpr (FS) {
     // characteristic reconstruction: the face's mean state from the two
     // cells' conservative means gives R for both sides
@@ -770,7 +771,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     TC WL[5], dWL[3][5], WR[5], dWR[3][5];
     eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, WL, dWL);
     eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, WR, dWR);
-    side_terms<+1, PR>(WL, dWL, gp, acc);
+    side_terms<+1, PR, kAssignFirst<TC>>(WL, dWL, gp, acc);
     side_terms<-1, PR>(WR, dWR, gp, acc);
   } else if constexpr (DMA) {
     // The right cells' 50 values go to LDS by direct loads issued before
@@ -797,7 +798,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
       for (int k = 0; k < 25; ++k)
         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 128 * k),
                                          (void __attribute__((address_space(3)))*)(dst + 256 * k), 4, 0, 0);
-      side_terms<+1, PR>(W, dW, gp, acc);
+      side_terms<+1, PR, kAssignFirst<TC>>(W, dW, gp, acc);
     }
     // the right side's LDS reads wait for the left side's results and for
     // this wave's copies
@@ -820,7 +821,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     {
       TC W[5], dW[3][5];
       eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
-      side_terms<+1, PR>(W, dW, gp, acc);
+      side_terms<+1, PR, kAssignFirst<TC>>(W, dW, gp, acc);
     }
     after_left_side(iR, acc);
     {

@@ -1134,6 +1134,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   };
 
   FluxAcc<TC> acc;
+  acc_begin(acc);
   if constexpr (std::is_same<TC, float>::value) {
     // FP32: both sides' local states first, then the side terms; the
     // accumulators are not live while the coefficients are loaded (113
@@ -1155,11 +1156,9 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       eval_side(coefR, iR, shR, x, fbR, val, grad);
       to_local(val, grad, u, n0, n1, n2, WR, dWR);
     }
-    acc_zero(acc);
-    side_terms<+1, PR>(WL, dWL, gp, acc);
+    side_terms<+1, PR, kAssignFirst<TC>>(WL, dWL, gp, acc);
     side_terms<-1, PR>(WR, dWR, gp, acc);
   } else {
-    acc_zero(acc);
     {
       asm volatile("" ::: "memory");
       double x[3], u[3], n0[3], n1[3], n2[3];
@@ -1172,7 +1171,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
       eval_side(coefL, iL, shL, x, fbL, val, grad);
       TC W[5], dW[3][5];
       to_local(val, grad, u, n0, n1, n2, W, dW);
-      side_terms<+1, PR>(W, dW, gp, acc);
+      side_terms<+1, PR, kAssignFirst<TC>>(W, dW, gp, acc);
     }
     size_t iRt = iR;
     after_left_side(iRt, acc);

@@ -67,11 +67,10 @@ int main() {
 
   cnt::reset();
   FluxAcc<Cnt> acc;
-  acc_zero(acc);
   {
     Cnt W[5], dW[3][5];
     eval_box_gp<0>(coef, 0, Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
-    side_terms<+1>(W, dW, g, acc);
+    side_terms<+1, false, true>(W, dW, g, acc);
   }
   {
     Cnt W[5], dW[3][5];
@@ -91,11 +90,10 @@ int main() {
   cnt::reset();
   {
     FluxAcc<Cnt> accp;
-    acc_zero(accp);
     {
       Cnt W[5], dW[3][5];
       eval_box_gp<0>(coef, 0, Cnt(0.5), Cnt(0.2887), Cnt(-0.2887), false, invd, W, dW);
-      side_terms<+1, true>(W, dW, g, accp);
+      side_terms<+1, true, true>(W, dW, g, accp);
     }
     {
       Cnt W[5], dW[3][5];
