@@ -126,28 +126,26 @@ def run_gpu(n, steps, warmup, precision, cfl=0.35, record_first=False, character
     torch.cuda.synchronize()
     ek0 = ctx.kinetic_energy()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # timed steps: each step's CFL time step is reduced and used on the
-    # device (hgks_step_cfl), so the host never waits between steps
-    dts = torch.zeros(steps, dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
     ev0.record()
-    for k in range(steps):
-        ctx.step_cfl(cfl, 2, dts[k:k + 1])
+    t_sim = 0.0
+    for _ in range(steps):
+        dt = ctx.max_dt(cfl)
+        ctx.step(dt, 2)
+        t_sim += dt
     ev1.record()
-    ctx.sync()                                      # raises on a non-physical state
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
-    t_sim = float(dts.sum().item())
     state = ctx.get_state().cpu().numpy()
     totals = ctx.totals()
     ek1 = ctx.kinetic_energy()
-    # the same number of steps again with per-phase HIP events, outside the
+    # the same number of steps again with HIP events per phase, outside the
     # timed region
     ctx.profile_begin()
     for _ in range(steps):
-        ctx.step_cfl(cfl, 2)
-    ctx.sync()
+        ctx.step(ctx.max_dt(cfl), 2)
+    torch.cuda.synchronize()
     prof = ctx.profile_end()
     return {"ms": ms, "wall": wall, "prof": prof, "state": state, "totals": totals, "totals0": tot0,
             "first": first, "q0": q0.cpu().numpy(), "ek": (ek0, ek1, t_sim)}
@@ -351,17 +349,16 @@ def run_turbulence(n, steps, warmup, precision, mach_t):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for _ in range(steps):
-        ctx.step_cfl(0.35, 2)
+        ctx.step(ctx.max_dt(0.35), 2)
     ev1.record()
-    ctx.sync()
     torch.cuda.synchronize()
     out = {"ms": ev0.elapsed_time(ev1), "state": ctx.get_state().cpu().numpy(),
            "nonphysical": ctx.check()[0], "drift": drift(tot0, ctx.totals())}
     # per-phase times from as many steps again, outside the timed region
     ctx.profile_begin()
     for _ in range(steps):
-        ctx.step_cfl(0.35, 2)
-    ctx.sync()
+        ctx.step(ctx.max_dt(0.35), 2)
+    torch.cuda.synchronize()
     out["prof"] = ctx.profile_end()
     return out
 

@@ -178,20 +178,6 @@ hgks_status hgks_max_dt(hgks_ctx ctx, double cfl, double* dt_host);
  * which rejects such a step. */
 hgks_status hgks_step(hgks_ctx ctx, double dt, int32_t n_stages);
 
-/* hgks_max_dt followed by hgks_step with that time step, formed and used on
- * the device: the step does not wait for the host, so steps can be queued
- * back to back.  The time step is the same number hgks_max_dt returns (the
- * CFL rule of Sec. 4 with its minimum taken on the device).  Box grids
- * (moving = 0) only: a moving mesh needs dt on the host for its next
- * vertices (HGKS_EUNSUPPORTED).  dt_dev: NULL, or a device pointer to one
- * double that receives the step's dt (stream-ordered; the caller owns it).
- * Asynchronous.  A state with a cell whose density or pressure is not
- * positive (or not a number) gives dt = 0: the step leaves the state as it
- * was and sets the context's status word, which the next hgks_sync reports
- * (HGKS_ENONPHYS) and clears.  HGKS_EINVAL unless 0 < cfl < infinity and
- * n_stages is 1 or 2; HGKS_ESTATE before the grid and the state are set. */
-hgks_status hgks_step_cfl(hgks_ctx ctx, double cfl, int32_t n_stages, double* dt_dev);
-
 /* hgks_step with step rejection, for static grids: the step is taken with
  * dt / 2^k for the smallest k <= max_halvings (0..60) after which every
  * cell has positive density and pressure; *dt_taken_host receives that
@@ -260,9 +246,7 @@ typedef enum {
 hgks_status hgks_profile_begin(hgks_ctx ctx);
 hgks_status hgks_profile_end(hgks_ctx ctx, double ms_host[5], int64_t launches_host[5]);
 
-/* Waits for the context's stream.  HGKS_ENONPHYS when a hgks_step_cfl
- * since the last hgks_sync found a non-physical state (that step and the
- * ones after it left the state unchanged). */
+/* Waits for the context's stream. */
 hgks_status hgks_sync(hgks_ctx ctx);
 
 /* ---------------------------------------------------------------- batches

@@ -874,21 +874,13 @@ HGKS_FN void flux_block(unsigned b, const unsigned (&nb)[3], int& D, unsigned& l
   lb = m + b;
 }
 
-// All faces of the three directions in one launch (see flux_block).  dtp:
-// null, or the time step in device memory, which then replaces dt and idt
-// (a step whose time step was formed on the device).
+// All faces of the three directions in one launch (see flux_block).
 template <typename TC, bool PR = false, bool FS = false>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
     const TC* __restrict__ coef, const uint32_t* __restrict__ mask, TC* __restrict__ fx, TC* __restrict__ fy,
-    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, unsigned nb0, unsigned nb1, unsigned nb2,
-    const double* __restrict__ dtp) {
+    TC* __restrict__ fz, BoxGrid G, GasParams<TC> gp, TC dt, TC idt, unsigned nb0, unsigned nb1, unsigned nb2) {
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= nb0 + nb1 + nb2) return;
-  if (dtp) {
-    const double d = *dtp;
-    dt = TC(d);
-    idt = TC(1.0 / d);
-  }
   const unsigned nb[3] = {nb0, nb1, nb2};
   int D;
   unsigned lb;
@@ -946,21 +938,13 @@ __device__ __forceinline__ void update_box_cell(double* __restrict__ q, double* 
   }
 }
 
-// dtp: null, or the time step in device memory, which replaces dt; a time
-// step there that is not positive (the reduction found a non-physical cell)
-// leaves every array as it was.
 template <typename TF>
 __global__ void __launch_bounds__(kBlock) k_update_box(double* __restrict__ q, double* __restrict__ qs,
                                                        double* __restrict__ acc, const TF* __restrict__ fx,
                                                        const TF* __restrict__ fy, const TF* __restrict__ fz,
-                                                       BoxGrid G, double dt, int mode, size_t N,
-                                                       const double* __restrict__ dtp) {
+                                                       BoxGrid G, double dt, int mode, size_t N) {
   const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= N) return;
-  if (dtp) {
-    dt = *dtp;
-    if (!(dt > 0.0)) return;
-  }
   update_box_cell(q, qs, acc, fx, fy, fz, G, dt, mode, N, idx);
 }
 
@@ -1012,21 +996,6 @@ __global__ void __launch_bounds__(kBlock) k_min_final(const double* __restrict__
   for (int i = threadIdx.x; i < n; i += kBlock) v = fmin(v, part[i]);
   const double r = block_reduce(v, sh, MinOp());
   if (threadIdx.x == 0) out[0] = r;
-}
-
-// The time step on the device: dt = cfl m from the reduction's minimum m,
-// the same product as on the host.  A minimum that is not positive (a cell
-// with non-positive or not-a-number density or pressure) gives dt = 0 and
-// sets *status to 1.  dt_out (may be null) receives a copy of dt.
-__global__ void k_dt_set(const double* __restrict__ m, double cfl, double* __restrict__ dt,
-                         double* __restrict__ status, double* __restrict__ dt_out) {
-  if (threadIdx.x != 0) return;
-  const double v = *m;
-  const bool ok = v > 0.0;
-  const double d = ok ? cfl * v : 0.0;
-  *dt = d;
-  if (!ok) *status = 1.0;
-  if (dt_out) *dt_out = d;
 }
 
 // sum |Omega| Q_v: fixed-order block sums, then a fixed-order final sum.

@@ -160,8 +160,6 @@ struct hgks_ctx_s {
   HexGrid H;
   char* ws;
   bool grid_set = false, state_set = false, next_set = false;
-  // hgks_step_cfl was called since the last report of its status word
-  bool cfl_pending = false;
   hgks_status sticky = HGKS_OK;
   double period[3];
   // Phase timing (hgks_profile_begin / hgks_profile_end).
@@ -181,11 +179,6 @@ struct hgks_ctx_s {
   void* face(int d) { return ws + L.face[d]; }
   double* vface(int d) { return (double*)(ws + L.vface[d]); }
   double* red() { return (double*)(ws + L.red); }
-  // the tail of the reduction scratch (64 doubles past the per-block
-  // partials): final results at nred - 8, the device time step of
-  // hgks_step_cfl at nred - 16 and its status word at nred - 15
-  double* dt_dev() { return red() + D.nred - 16; }
-  double* cfl_status() { return red() + D.nred - 15; }
   double* geo() { return (double*)(ws + L.geo); }
   double* verts() { return (double*)(ws + L.verts); }
   double* vnext() { return (double*)(ws + L.vnext); }
@@ -274,9 +267,8 @@ TC* face_coef(hgks_ctx c) {
 }
 
 // Reconstruction (with the fallback mask) and face fluxes of the state qin.
-// dtp: null, or the time step in device memory, which replaces dt.
 template <typename TC>
-hgks_status box_stage(hgks_ctx c, const double* qin, double dt, const double* dtp = nullptr) {
+hgks_status box_stage(hgks_ctx c, const double* qin, double dt) {
   const Dims& D = c->D;
   const double dx[3] = {1.0 / c->G.inv_dx[0], 1.0 / c->G.inv_dx[1], 1.0 / c->G.inv_dx[2]};
   const WenoParams<TC> P = weno_params<TC>(c->cfg, dx);
@@ -332,7 +324,7 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt, const double* dt
   const bool ext = c->cfg.prandtl != 1.0 || c->cfg.mu_exponent != 0.0, fs = c->cfg.characteristic != 0;
 #define HGKS_FLUX_LAUNCH(E, F)                                                                                   \
   hipLaunchKernelGGL((k_flux_box<TC, E, F>), grid, dim3(kBlock), 0, c->stream, fc, c->mask(), f[0], f[1], f[2], \
-                     c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2], dtp)
+                     c->G, gp, TC(dt), TC(1.0 / dt), nb[0], nb[1], nb[2])
   if (ext && fs)
     HGKS_FLUX_LAUNCH(true, true);
   else if (ext)
@@ -347,22 +339,22 @@ hgks_status box_stage(hgks_ctx c, const double* qin, double dt, const double* dt
 }
 
 template <typename TF>
-hgks_status box_update(hgks_ctx c, double dt, int mode, const double* dtp = nullptr) {
+hgks_status box_update(hgks_ctx c, double dt, int mode) {
   prof_mark(c, HGKS_PHASE_UPDATE, true);
   hipLaunchKernelGGL((k_update_box<TF>), dim3(blocks_for(c->D.N)), dim3(kBlock), 0, c->stream, c->q(), c->qs(),
                      c->acc(), (const TF*)c->face(0), (const TF*)c->face(1), (const TF*)c->face(2), c->G, dt, mode,
-                     c->D.N, dtp);
+                     c->D.N);
   prof_mark(c, HGKS_PHASE_UPDATE, false);
   return launched(c, "update");
 }
 
 template <typename T>
-hgks_status box_step(hgks_ctx c, double dt, int n_stages, const double* dtp = nullptr) {
-  if (hgks_status s = box_stage<T>(c, c->q(), dt, dtp)) return s;
-  if (n_stages == 1) return box_update<T>(c, dt, 0, dtp);
-  if (hgks_status s = box_update<T>(c, dt, 1, dtp)) return s;
-  if (hgks_status s = box_stage<T>(c, c->qs(), dt, dtp)) return s;
-  return box_update<T>(c, dt, 2, dtp);
+hgks_status box_step(hgks_ctx c, double dt, int n_stages) {
+  if (hgks_status s = box_stage<T>(c, c->q(), dt)) return s;
+  if (n_stages == 1) return box_update<T>(c, dt, 0);
+  if (hgks_status s = box_update<T>(c, dt, 1)) return s;
+  if (hgks_status s = box_stage<T>(c, c->qs(), dt)) return s;
+  return box_update<T>(c, dt, 2);
 }
 
 // ------------------------------------------------------------ hexahedral grids
@@ -694,30 +686,6 @@ hgks_status hgks_step(hgks_ctx c, double dt, int32_t n_stages) {
   return s;
 }
 
-hgks_status hgks_step_cfl(hgks_ctx c, double cfl, int32_t n_stages, double* dt_dev) {
-  if (hgks_status s = ready(c)) return s;
-  if (c->cfg.moving) return fail(HGKS_EUNSUPPORTED, "step_cfl needs a box grid (moving = 0)");
-  if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(HGKS_EINVAL, "bad cfl");
-  if (n_stages != 1 && n_stages != 2) return fail(HGKS_EINVAL, "n_stages must be 1 or 2");
-  if (!c->cfl_pending) {
-    // a fresh status word (two 32-bit halves)
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(2), 0, c->stream, (uint32_t*)c->cfl_status());
-    c->cfl_pending = true;
-  }
-  const unsigned nb = blocks_for(c->D.N);
-  double* part = c->red();
-  prof_mark(c, HGKS_PHASE_REDUCE, true);
-  hipLaunchKernelGGL(k_dt_box, dim3(nb), dim3(kBlock), 0, c->stream, c->q(), c->G, c->cfg.gamma, part, c->D.N);
-  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, c->stream, part, (int)nb, part + c->D.nred - 8);
-  hipLaunchKernelGGL(k_dt_set, dim3(1), dim3(64), 0, c->stream, part + c->D.nred - 8, cfl, c->dt_dev(),
-                     c->cfl_status(), dt_dev);
-  prof_mark(c, HGKS_PHASE_REDUCE, false);
-  if (hgks_status s = launched(c, "step_cfl time step")) return s;
-  // dt and 1/dt of the by-value arguments are placeholders: every kernel
-  // reads the time step from c->dt_dev()
-  return c->mixed() ? box_step<float>(c, 1.0, n_stages, c->dt_dev()) : box_step<double>(c, 1.0, n_stages, c->dt_dev());
-}
-
 hgks_status hgks_step_checked(hgks_ctx c, double dt, int32_t n_stages, int32_t max_halvings, double* dt_taken) {
   if (hgks_status s = ready(c)) return s;
   if (c->cfg.moving) return fail(HGKS_EUNSUPPORTED, "step_checked needs a static grid");
@@ -866,12 +834,7 @@ hgks_status hgks_debug_face_flux(hgks_ctx c, double dt, double* out) {
 
 hgks_status hgks_sync(hgks_ctx c) {
   if (hgks_status s = usable(c)) return s;
-  if (!c->cfl_pending) return check_hip(c, hipStreamSynchronize(c->stream), "synchronise");
-  double st = 0.0;
-  if (hgks_status s = sync_copy(c, &st, c->cfl_status(), sizeof st)) return s;
-  c->cfl_pending = false;
-  if (st != 0.0) return fail(HGKS_ENONPHYS, "non-physical state at a step of hgks_step_cfl (not advanced)");
-  return HGKS_OK;
+  return check_hip(c, hipStreamSynchronize(c->stream), "synchronise");
 }
 
 hgks_status hgks_profile_begin(hgks_ctx c) {

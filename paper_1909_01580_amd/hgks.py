@@ -25,7 +25,7 @@ STENCIL = {"S": 0, "S_prime": 1}
 EXPORTS = [
     "hgks_default_config", "hgks_workspace_size", "hgks_create", "hgks_destroy",
     "hgks_set_uniform_grid", "hgks_set_vertices", "hgks_set_next_vertices",
-    "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_step_cfl", "hgks_step_checked", "hgks_totals",
+    "hgks_set_state", "hgks_get_state", "hgks_max_dt", "hgks_step", "hgks_step_checked", "hgks_totals",
     "hgks_check", "hgks_debug_gp_states", "hgks_debug_face_flux", "hgks_sync",
     "hgks_last_error", "hgks_profile_begin", "hgks_profile_end",
     "hgks_batch_workspace_size", "hgks_batch_create", "hgks_batch_destroy",
@@ -85,7 +85,6 @@ def load():
         "hgks_get_state": [P, P],
         "hgks_max_dt": [P, D, DP],
         "hgks_step": [P, D, I32],
-        "hgks_step_cfl": [P, D, I32, P],
         "hgks_step_checked": [P, D, I32, I32, DP],
         "hgks_totals": [P, DP],
         "hgks_check": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
@@ -194,18 +193,6 @@ def hgks_max_dt(h, cfl):
 
 def hgks_step(h, dt, n_stages=2):
     _check(load().hgks_step(h, dt, n_stages))
-
-
-def hgks_step_cfl(h, cfl, n_stages=2, dt_out=None):
-    """dt_out: None, or a CUDA float64 tensor whose first element receives
-    the step's dt (stream-ordered)."""
-    if dt_out is not None:
-        if not (dt_out.is_cuda and dt_out.dtype == torch.float64 and dt_out.numel() >= 1):
-            raise ValueError("dt_out must be a CUDA float64 tensor with at least one element")
-        ptr = ctypes.c_void_p(dt_out.data_ptr())
-    else:
-        ptr = ctypes.c_void_p(None)
-    _check(load().hgks_step_cfl(h, cfl, n_stages, ptr))
 
 
 def hgks_step_checked(h, dt, n_stages=2, max_halvings=8):
@@ -354,9 +341,6 @@ class Context:
 
     def step(self, dt, n_stages=2):
         hgks_step(self.h, dt, n_stages)
-
-    def step_cfl(self, cfl, n_stages=2, dt_out=None):
-        hgks_step_cfl(self.h, cfl, n_stages, dt_out)
 
     def step_checked(self, dt, n_stages=2, max_halvings=8):
         return hgks_step_checked(self.h, dt, n_stages, max_halvings)
