@@ -722,6 +722,26 @@ __device__ __forceinline__ void eval_char_gp_dir(int D, const TC* cv, const doub
     eval_char_gp<2>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
 }
 
+// LDS of the FP64 flux's right cells, in doubles: per group of 8 faces 50
+// rows of 8 and one row of padding (it moves the second group's reads to
+// other banks), two groups per wave.
+constexpr int kStageGroup = 50 * 8 + 8;
+constexpr int kStageWave = 2 * kStageGroup;
+
+typedef const void __attribute__((address_space(1)))* GlobalPtr;
+typedef void __attribute__((address_space(3)))* LdsPtr;
+
+// Direct global-to-LDS copies of pieces K0..K1-1 of 256 bytes: piece k at
+// immediate offset 256 k of both addresses (the offset is a constant of
+// the instruction; the LDS address, in M0, stays the same for all).
+template <int K0, int K1>
+__device__ __forceinline__ void copy_pieces(GlobalPtr src, LdsPtr dst) {
+  if constexpr (K0 < K1) {
+    __builtin_amdgcn_global_load_lds(src, dst, 4, 256 * K0, 0);
+    copy_pieces<K0 + 1, K1>(src, dst);
+  }
+}
+
 // One lane = one Gauss point of one face normal to axis D; the four lanes of
 // a face sum their weighted fluxes with quad-permute moves.  Lane l of the
 // 256-lane block lb of direction D takes Gauss point l % 4 of face slot
@@ -777,27 +797,38 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     // The right cells' 50 values go to LDS by direct loads issued before
     // the left side's terms: they arrive while those run and hold no
     // registers meanwhile.  Each wave copies the right cells of its own 16
-    // faces into its own [50 rows][16 faces] array and reads only that
-    // array, after waiting for its own loads: no workgroup barrier.
+    // faces, as two groups of 8 faces, into its own [50 rows][8 faces]
+    // arrays and reads only those, after waiting for its own loads: no
+    // workgroup barrier.  A row of 8 doubles is 64 bytes in LDS as in the
+    // coefficient array, so one immediate offset steps the global and the
+    // LDS address together and the 26 copies need no address arithmetic.
     static_assert(sizeof(TC) == 8 && kCB<TC> == 8, "rows of 8 doubles");
     const unsigned l = threadIdx.x & 63u;
-    TC* rs = stage + (threadIdx.x >> 6) * (50 * 16);
-    // lane l copies dword l of every 64-dword piece: face slot (l / 2) % 16
-    // of the wave, row 2 k + l / 32 in piece k, half l % 2
-    unsigned src_cell = __shfl((unsigned)iR, (int)(((l >> 1) & 15u) * 4u));
+    TC* rs = stage + (threadIdx.x >> 6) * kStageWave;
+    // in piece k of group g lane l copies row 4 k + l / 16 of face slot
+    // 8 g + (l / 2) % 8, 32-bit half l % 2: byte 4 l of the piece
+    unsigned cell0 = __shfl((unsigned)iR, (int)(((l >> 1) & 7u) * 4u));
+    unsigned cell1 = __shfl((unsigned)iR, (int)((8u + ((l >> 1) & 7u)) * 4u));
     {
       TC W[5], dW[3][5];
       eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
       // The copies are issued once the left cell's values have arrived: the
       // memory counter is waited on in issue order, so copies issued
       // earlier would hold up the left side's first use of its loads.
-      asm volatile("" : "+v"(src_cell) : "v"(W[0]), "v"(dW[2][4]));
-      const char* src = (const char*)(coefR + coef_cell<TC>(src_cell)) + (l >> 5) * 64 + (l & 1u) * 4;
-      char __attribute__((address_space(3)))* dst = (char __attribute__((address_space(3)))*)rs;
-#pragma unroll
-      for (int k = 0; k < 25; ++k)
-        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)(src + 128 * k),
-                                         (void __attribute__((address_space(3)))*)(dst + 256 * k), 4, 0, 0);
+      asm volatile("" : "+v"(cell0), "+v"(cell1) : "v"(W[0]), "v"(dW[2][4]));
+      const unsigned lane = (l >> 4) * 64 + (l & 1u) * 4;
+      const GlobalPtr s0 = (GlobalPtr)((const char*)(coefR + coef_cell<TC>(cell0)) + lane);
+      const GlobalPtr s1 = (GlobalPtr)((const char*)(coefR + coef_cell<TC>(cell1)) + lane);
+      const LdsPtr d0 = (LdsPtr)rs;
+      const LdsPtr d1 = (LdsPtr)(rs + kStageGroup);
+      // rows 0-47: twelve pieces of four rows per group
+      copy_pieces<0, 12>(s0, d0);
+      copy_pieces<0, 12>(s1, d1);
+      // rows 48 and 49: the lanes of the next piece's first two rows
+      if (l < 32u) {
+        copy_pieces<12, 13>(s0, d0);
+        copy_pieces<12, 13>(s1, d1);
+      }
       side_terms<+1, PR, kAssignFirst<TC>>(W, dW, gp, acc);
     }
     // the right side's LDS reads wait for the left side's results and for
@@ -808,13 +839,13 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     asm volatile("" ::: "memory");
     {
       TC W[5], dW[3][5];
-      const TC* cv = rs + slot;
+      const TC* cv = rs + (slot >> 3) * kStageGroup + (slot & 7u);
       if (D == 0)
-        eval_rows_gp<0, 16>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
+        eval_rows_gp<0, 8>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
       else if (D == 1)
-        eval_rows_gp<1, 16>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
+        eval_rows_gp<1, 8>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
       else
-        eval_rows_gp<2, 16>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
+        eval_rows_gp<2, 8>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
       side_terms<-1, PR>(W, dW, gp, acc);
     }
   } else {
@@ -887,7 +918,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
   flux_block(b, nb, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
   if constexpr (sizeof(TC) == 8 && !FS) {
-    __shared__ double stage[kBlock / 64 * 50 * 16];
+    __shared__ double stage[kBlock / 64 * kStageWave];
     flux_box_face<TC, PR, FS, true>(coef, mask, face, G, gp, dt, idt, lb, D, stage);
   } else {
     flux_box_face<TC, PR, FS>(coef, mask, face, G, gp, dt, idt, lb, D);
