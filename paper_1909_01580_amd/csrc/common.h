@@ -92,7 +92,18 @@ template <> HGKS_FN float d_erfc<float>(float x) {
 template <typename T> HGKS_FN T d_sqrt(T x);
 template <> HGKS_FN double d_sqrt<double>(double x) { return sqrt(x); }
 template <> HGKS_FN float d_sqrt<float>(float x) { return sqrtf(x); }
+// |x|.  For double and float the sign bit is cleared (an abs modifier on
+// the instruction that uses it, or one bitwise and), where the comparison
+// form costs a compare, a negation and two selects per double.
 template <typename T> HGKS_FN T d_abs(T x) { return x < T(0) ? -x : x; }
+template <> HGKS_FN double d_abs<double>(double x) { return __builtin_fabs(x); }
+template <> HGKS_FN float d_abs<float>(float x) { return __builtin_fabsf(x); }
+
+// The larger of a and b (one max instruction for double and float; the
+// same value as the comparison form unless an argument is not a number).
+template <typename T> HGKS_FN T d_max(T a, T b) { return a > b ? a : b; }
+template <> HGKS_FN double d_max<double>(double a, double b) { return __builtin_fmax(a, b); }
+template <> HGKS_FN float d_max<float>(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // Reciprocal of a nonzero finite x: the hardware estimate refined by
 // Newton-Raphson steps r <- r + r (1 - x r) (two in double, one in float),

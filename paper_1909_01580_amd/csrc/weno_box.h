@@ -183,7 +183,7 @@ HGKS_FN void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out
           cl[eb] += cm * bb;
           cl[ec] += cm * bc;
           const T bm = T(0.5) * (d_abs(ba) + d_abs(bb) + d_abs(bc));
-          bnd = bnd > bm ? bnd : bm;
+          bnd = d_max(bnd, bm);
         }
   }
   out.c[0] = cl[0];
@@ -305,7 +305,7 @@ HGKS_FN void weno_box_wide(const T (&d)[27], const T (&f)[6], const WenoParams<T
     cl[1] += cm * b[1];
     cl[2] += cm * b[2];
     const T bm = T(0.5) * (d_abs(b[0]) + d_abs(b[1]) + d_abs(b[2]));
-    bnd = bnd > bm ? bnd : bm;
+    bnd = d_max(bnd, bm);
   }
   out.c[0] = cl[0];
   out.c[1] = cl[1];
