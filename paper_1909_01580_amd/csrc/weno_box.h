@@ -121,44 +121,18 @@ HGKS_FN void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out
                   P.kq[0] * a[3] * a[3] + P.kq[1] * a[4] * a[4] + P.kq[2] * a[5] * a[5] +
                   P.km[0] * a[6] * a[6] + P.km[1] * a[7] * a[7] + P.km[2] * a[8] * a[8];
 
-  // Sub-stencil slopes, in the order of the printed S_1..S_8 and their two
-  // cyclic permutations: triple t, then s_c, s_b, s_a in (+, -).
-  T beta[24];
-#pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    const int ea = t, eb = (t + 1) % 3, ec = (t + 2) % 3;
-#pragma unroll
-    for (int ic = 0; ic < 2; ++ic)
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int ia = 0; ia < 2; ++ia) {
-          const int sa = ia ? -1 : 1, sb = ib ? -1 : 1, sc = ic ? -1 : 1;
-          int oa[3] = {0, 0, 0}, ob[3] = {0, 0, 0}, oab[3] = {0, 0, 0}, oc[3] = {0, 0, 0};
-          oa[ea] = sa; ob[eb] = sb; oab[ea] = sa; oab[eb] = sb; oc[ec] = sc;
-          const T da = d[sidx3(oa)], db = d[sidx3(ob)], dab = d[sidx3(oab)], dc = d[sidx3(oc)];
-          const T bc = T(sc) * dc;
-          const T ba = T(sa) * (T(2) * da - db + dab) * T(1.0 / 3.0);
-          const T bb = T(sb) * (T(2) * db - da + dab) * T(1.0 / 3.0);
-          beta[t * 8 + ic * 4 + ib * 2 + ia] = P.kl[ea] * ba * ba + P.kl[eb] * bb * bb + P.kl[ec] * bc * bc;
-        }
-  }
-  T tau = T(0);
-#pragma unroll
-  for (int m = 0; m < 24; ++m) tau += d_abs(beta0 - beta[m]);
-  tau *= T(1.0 / 24.0);
-  const T w0r = T(1) + tau * d_rcp(beta0 + P.eps);  // omega_0 / gamma_0
-  T wsum = P.gamma0 * w0r;
-#pragma unroll
-  for (int m = 0; m < 24; ++m) {
-    beta[m] = P.Gamma * (T(1) + tau * d_rcp(beta[m] + P.eps));  // omega_m
-    wsum += beta[m];
-  }
-  const T iw = d_rcp(wsum);
-  const T w0g = w0r * iw;  // wbar_0 / gamma_0
-  const T off = w0g * P.Gamma;
-
-  T cl[3] = {w0g * a[0], w0g * a[1], w0g * a[2]};
+  // One pass over the sub-stencils.  With r_m = 1/(beta_m + eps) and
+  // r_0 = 1/(beta_0 + eps) the nonlinear weights are affine in tau:
+  // omega_m = Gamma (1 + tau r_m), omega_0 / gamma_0 = 1 + tau r_0.  So the
+  // weight sum is S = gamma_0 (1 + tau r_0) + Gamma (24 + tau sum_m r_m)
+  // and the combined linear part sum_m (omega_m - Gamma omega_0 / gamma_0)
+  // b^m / S is (Gamma tau / S) sum_m (r_m - r_0) b^m.  The pass gathers
+  // sum |beta_0 - beta_m| (tau), sum r_m and sum (r_m - r_0) b^m; tau enters
+  // afterwards, and no sub-stencil's indicator is kept.  Sub-stencils in the
+  // order of the printed S_1..S_8 and their two cyclic permutations: triple
+  // t, then s_c, s_b, s_a in (+, -).
+  const T r0 = d_rcp(beta0 + P.eps);
+  T tsum = T(0), rsum = T(0), db[3] = {T(0), T(0), T(0)};
   T bnd = T(0.5) * (d_abs(a[0]) + d_abs(a[1]) + d_abs(a[2])) +
           T(1.0 / 6.0) * (d_abs(a[3]) + d_abs(a[4]) + d_abs(a[5])) +
           T(0.14433756729740644113) * (d_abs(a[6]) + d_abs(a[7]) + d_abs(a[8]));
@@ -174,21 +148,28 @@ HGKS_FN void weno_box(const T (&d)[27], const WenoParams<T>& P, BoxRecon<T>& out
           const int sa = ia ? -1 : 1, sb = ib ? -1 : 1, sc = ic ? -1 : 1;
           int oa[3] = {0, 0, 0}, ob[3] = {0, 0, 0}, oab[3] = {0, 0, 0}, oc[3] = {0, 0, 0};
           oa[ea] = sa; ob[eb] = sb; oab[ea] = sa; oab[eb] = sb; oc[ec] = sc;
-          const T da = d[sidx3(oa)], db = d[sidx3(ob)], dab = d[sidx3(oab)], dc = d[sidx3(oc)];
+          const T da = d[sidx3(oa)], db_ = d[sidx3(ob)], dab = d[sidx3(oab)], dc = d[sidx3(oc)];
           const T bc = T(sc) * dc;
-          const T ba = T(sa) * (T(2) * da - db + dab) * T(1.0 / 3.0);
-          const T bb = T(sb) * (T(2) * db - da + dab) * T(1.0 / 3.0);
-          const T cm = beta[t * 8 + ic * 4 + ib * 2 + ia] * iw - off;
-          cl[ea] += cm * ba;
-          cl[eb] += cm * bb;
-          cl[ec] += cm * bc;
-          const T bm = T(0.5) * (d_abs(ba) + d_abs(bb) + d_abs(bc));
-          bnd = d_max(bnd, bm);
+          const T ba = T(sa) * (T(2) * da - db_ + dab) * T(1.0 / 3.0);
+          const T bb = T(sb) * (T(2) * db_ - da + dab) * T(1.0 / 3.0);
+          const T beta = P.kl[ea] * ba * ba + P.kl[eb] * bb * bb + P.kl[ec] * bc * bc;
+          tsum += d_abs(beta0 - beta);
+          const T rm = d_rcp(beta + P.eps);
+          rsum += rm;
+          const T dr = rm - r0;
+          db[ea] += dr * ba;
+          db[eb] += dr * bb;
+          db[ec] += dr * bc;
+          bnd = d_max(bnd, T(0.5) * (d_abs(ba) + d_abs(bb) + d_abs(bc)));
         }
   }
-  out.c[0] = cl[0];
-  out.c[1] = cl[1];
-  out.c[2] = cl[2];
+  const T tau = tsum * T(1.0 / 24.0);
+  const T w0r = T(1) + tau * r0;  // omega_0 / gamma_0
+  const T iS = d_rcp(P.gamma0 * w0r + P.Gamma * (T(24) + tau * rsum));
+  const T w0g = w0r * iS;           // wbar_0 / gamma_0
+  const T gl = P.Gamma * tau * iS;  // weight of sum (r_m - r_0) b^m
+#pragma unroll
+  for (int e = 0; e < 3; ++e) out.c[e] = w0g * a[e] + gl * db[e];
 #pragma unroll
   for (int k = 3; k < 9; ++k) out.c[k] = w0g * a[k];
   out.bound = bnd;
