@@ -161,6 +161,43 @@ __device__ __forceinline__ void face_corners(const HexGrid& H, int d, int i, int
     }
 }
 
+// The four corners of the face normal to axis D whose lowest vertex is the
+// lattice point c, every c[d] in [0, n_d) (the face flux's case): only the
+// +1 neighbours along the face's own axes A and B can pass the last plane,
+// where they wrap to 0 with their position shifted by the period.  Indices
+// in 32-bit arithmetic and loads at 32-bit byte offsets from the arrays'
+// uniform bases (the grid has fewer than 2^29 vertices); the same values as
+// face_corners for such c.
+template <int D>
+__device__ __forceinline__ void face_corners_in(const HexGrid& H, const int (&c)[3], double (&cx)[4][3],
+                                               double (&cu)[4][3]) {
+  constexpr int A = (D + 1) % 3, B = (D + 2) % 3;
+  const unsigned st[3] = {1u, (unsigned)H.n[0], (unsigned)H.n[0] * (unsigned)H.n[1]};
+  const unsigned N = st[2] * (unsigned)H.n[2];
+  const unsigned base = (unsigned)c[0] + (unsigned)c[1] * st[1] + (unsigned)c[2] * st[2];
+  const bool wa = c[A] + 1 == H.n[A], wb = c[B] + 1 == H.n[B];
+  const unsigned oa = wa ? 0u - (unsigned)c[A] * st[A] : st[A];
+  const unsigned ob = wb ? 0u - (unsigned)c[B] * st[B] : st[B];
+  const double sa = wa ? H.period[A] : 0.0, sb = wb ? H.period[B] : 0.0;
+  const double* __restrict__ x1p = H.x1 ? H.x1 : H.x0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int ia = m >> 1, ib = m & 1;
+    const unsigned off = (base + (ia ? oa : 0u) + (ib ? ob : 0u)) * 8u;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      // uniform base of coordinate e, per-lane 32-bit byte offset
+      const char* __restrict__ x0 = (const char*)(H.x0 + (size_t)e * N);
+      const char* __restrict__ x1 = (const char*)(x1p + (size_t)e * N);
+      const double s = (e == A && ia) ? sa : ((e == B && ib) ? sb : 0.0);
+      const double a = *(const double*)(x0 + off) + s;
+      const double b = *(const double*)(x1 + off) + s;
+      cx[m][e] = a + H.alpha * (b - a);
+      cu[m][e] = (b - a) * H.inv_dt;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- K1
 // Cell geometry record at the stage time.
 __global__ void __launch_bounds__(kBlock) k_geometry_hex(HexGrid H, double* __restrict__ geo, size_t N) {
@@ -1031,9 +1068,15 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
   int c[3];
   size_t f;
   const bool live = face_of_block(H.box, D, lb, threadIdx.x >> 2, c, f);
-  // Face on the lower side of cell c along D: plane c[D].
+  // Face on the lower side of cell c along D: plane c[D] (c[d] in [0, n_d)
+  // for every lane, dead ones included).
   double cx[4][3], cu[4][3];
-  face_corners(H, D, c[0], c[1], c[2], cx, cu);
+  if (D == 0)
+    face_corners_in<0>(H, c, cx, cu);
+  else if (D == 1)
+    face_corners_in<1>(H, c, cx, cu);
+  else
+    face_corners_in<2>(H, c, cx, cu);
   FacePoint Pt;
   face_point(cx, cu, (gpi >> 1) ? kGaussNode : -kGaussNode, (gpi & 1) ? kGaussNode : -kGaussNode, Pt);
   double av[3], adot[3], t1[3], t2[3];
@@ -1094,11 +1137,24 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     for (int e = 0; e < 3; ++e) v[e] = gs[(k + e) * kBlock];
   };
 
-  int cL[3] = {c[0], c[1], c[2]};
-  cL[D] -= 1;
-  double shL[3], shR[3];
-  const size_t iL = hex_index(H, cL[0], cL[1], cL[2], shL);
-  const size_t iR = hex_index(H, c[0], c[1], c[2], shR);
+  // The two cells: c itself (in range, no shift) and its lower neighbour
+  // along D, which wraps to the last plane, shifted back by the period,
+  // where c[D] = 0.
+  double shL[3] = {0.0, 0.0, 0.0}, shR[3] = {0.0, 0.0, 0.0};
+  size_t iL, iR;
+  {
+    const unsigned s1 = (unsigned)H.n[0], s2 = s1 * (unsigned)H.n[1];
+    const unsigned r = (unsigned)c[0] + (unsigned)c[1] * s1 + (unsigned)c[2] * s2;
+    const unsigned sD = D == 0 ? 1u : (D == 1 ? s1 : s2);
+    const int cD = D == 0 ? c[0] : (D == 1 ? c[1] : c[2]);
+    const bool wrap = cD == 0;
+    iR = r;
+    iL = wrap ? r + (unsigned)(H.n[D] - 1) * sD : r - sD;
+    const double sh = wrap ? -H.period[D] : 0.0;
+    shL[0] = D == 0 ? sh : 0.0;
+    shL[1] = D == 1 ? sh : 0.0;
+    shL[2] = D == 2 ? sh : 0.0;
+  }
   const bool fbL = (mask[iL] >> (4 * (2 * D + 1) + gpi)) & 1u;
   const bool fbR = (mask[iR] >> (4 * (2 * D) + gpi)) & 1u;
   // the left cell's reconstruction for its high face, the right cell's for
