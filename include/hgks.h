@@ -92,8 +92,9 @@ typedef struct {
                              paper uses 0.01 and 1                            */
   int32_t precision;      /* hgks_prec                                        */
   int32_t moving;         /* 1: hexahedral vertex grid given by
-                             hgks_set_vertices (all axes periodic); 0: uniform
-                             box grid from hgks_set_uniform_grid              */
+                             hgks_set_vertices (all axes periodic, fewer than
+                             2^29 cells); 0: uniform box grid from
+                             hgks_set_uniform_grid                            */
   void* stream;           /* hipStream_t, NULL for the default stream         */
   int32_t bc_hi[3];       /* hgks_bc at the high end of each axis, or
                              HGKS_BC_SAME (the default): as bc[d]             */

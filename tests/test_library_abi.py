@@ -63,6 +63,22 @@ def test_invalid_configurations_rejected(lib, field, value):
     assert e.value.status == hgks.HGKS_EINVAL
 
 
+def test_moving_grid_size_limit(lib):
+    """A moving (hexahedral) grid addresses its vertex arrays with 32-bit
+    byte offsets: fewer than 2^29 cells; the same extents on a box grid are
+    accepted."""
+    from paper_1909_01580_amd import hgks
+    cfg = hgks.hgks_default_config(1024, 1024, 512)          # 2^29 cells
+    assert hgks.hgks_workspace_size(cfg) > 0
+    cfg.moving = 1
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.hgks_workspace_size(cfg)
+    assert e.value.status == hgks.HGKS_EINVAL
+    cfg = hgks.hgks_default_config(1024, 1024, 511)
+    cfg.moving = 1
+    assert hgks.hgks_workspace_size(cfg) > 0
+
+
 def test_boundary_ends(lib):
     """bc_hi defaults to "as the low end"; symmetric and mixed ends are
     accepted; a periodic end needs a periodic partner; unknown codes fail."""
