@@ -198,6 +198,46 @@ __device__ __forceinline__ void face_corners_in(const HexGrid& H, const int (&c)
   }
 }
 
+// The eight vertices of cell (i, j, k) with every index in [0, n) (vertex
+// m = 4 a + 2 b + c at (i + a, j + b, k + c)): only the +1 neighbours can
+// pass the last plane, where they wrap with a period shift.  32-bit indices
+// and byte offsets as in face_corners_in; the same positions as hex_vertex.
+struct CellVerts {
+  unsigned base, o[3], N;
+  double s[3];
+};
+
+__device__ __forceinline__ CellVerts cell_verts(const HexGrid& H, int i, int j, int k) {
+  CellVerts V;
+  const unsigned st[3] = {1u, (unsigned)H.n[0], (unsigned)H.n[0] * (unsigned)H.n[1]};
+  V.N = st[2] * (unsigned)H.n[2];
+  const int c[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool w = c[d] + 1 == H.n[d];
+    V.o[d] = w ? 0u - (unsigned)c[d] * st[d] : st[d];
+    V.s[d] = w ? H.period[d] : 0.0;
+  }
+  V.base = (unsigned)i + (unsigned)j * st[1] + (unsigned)k * st[2];
+  return V;
+}
+
+// Position of vertex m of the cell at the stage time.
+__device__ __forceinline__ void cell_vertex(const HexGrid& H, const CellVerts& V, int m, double (&x)[3]) {
+  const int bit[3] = {(m >> 2) & 1, (m >> 1) & 1, m & 1};
+  const unsigned off = (V.base + (bit[0] ? V.o[0] : 0u) + (bit[1] ? V.o[1] : 0u) + (bit[2] ? V.o[2] : 0u)) * 8u;
+  const double* __restrict__ x1p = H.x1 ? H.x1 : H.x0;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const char* __restrict__ x0 = (const char*)(H.x0 + (size_t)e * V.N);
+    const char* __restrict__ x1 = (const char*)(x1p + (size_t)e * V.N);
+    const double sh = bit[e] ? V.s[e] : 0.0;
+    const double a = *(const double*)(x0 + off) + sh;
+    const double b = *(const double*)(x1 + off) + sh;
+    x[e] = a + H.alpha * (b - a);
+  }
+}
+
 // ---------------------------------------------------------------- K1
 // Cell geometry record at the stage time.
 __global__ void __launch_bounds__(kBlock) k_geometry_hex(HexGrid H, double* __restrict__ geo, size_t N) {
@@ -206,10 +246,10 @@ __global__ void __launch_bounds__(kBlock) k_geometry_hex(HexGrid H, double* __re
   int i, j, k;
   split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], i, j, k);
   double cx[8][3];
+  {
+    const CellVerts cv = cell_verts(H, i, j, k);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    double u[3];
-    hex_vertex(H, i + ((m >> 2) & 1), j + ((m >> 1) & 1), k + (m & 1), cx[m], u);
+    for (int m = 0; m < 8; ++m) cell_vertex(H, cv, m, cx[m]);
   }
   const double g = kGaussNode;
   double xq[8][3], wq[8];
@@ -715,10 +755,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   double pmax[9];
   {
     double xm[3] = {0.0, 0.0, 0.0};
+    const CellVerts cv = cell_verts(H, i, j, k);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      double xv[3], uv[3];
-      hex_vertex(H, i + ((m >> 2) & 1), j + ((m >> 1) & 1), k + (m & 1), xv, uv);
+      double xv[3];
+      cell_vertex(H, cv, m, xv);
 #pragma unroll
       for (int e = 0; e < 3; ++e) xm[e] = fmax(xm[e], fabs((xv[e] - Ci.c[e]) * Ci.ih));
     }
