@@ -664,24 +664,35 @@ __device__ __forceinline__ double pbasis(int n, const double (&X)[3], const doub
 __device__ __forceinline__ void stage_hex_tile(const HexGrid& H, const double* __restrict__ geo,
                                                const double* __restrict__ q, size_t N, int o0, int o1, int o2,
                                                HexTile& T) {
+  // A tile with its layer reaches at most one period past either end when
+  // every extent is at least the tile's (uniform test); a very small grid
+  // may be passed several times and takes the general wrap.
+  const bool one_period = H.n[0] >= kTX && H.n[1] >= kTY && H.n[2] >= kTZ;
   for (int t = threadIdx.x; t < kHalo; t += kBlock) {
     const int g[3] = {o0 + t % kHX - 1, o1 + (t / kHX) % kHY - 1, o2 + t / (kHX * kHY) - 1};
     int c[3];
     double sh[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      // the tile may reach several periods past a very small grid
-      const int w = g[d] >= 0 ? g[d] / H.n[d] : -((-g[d] + H.n[d] - 1) / H.n[d]);
+      int w;
+      if (one_period)
+        w = g[d] < 0 ? -1 : (g[d] >= H.n[d] ? 1 : 0);
+      else
+        w = g[d] >= 0 ? g[d] / H.n[d] : -((-g[d] + H.n[d] - 1) / H.n[d]);
       c[d] = g[d] - w * H.n[d];
       sh[d] = w * H.period[d];
     }
-    const size_t io = ((size_t)c[2] * H.n[1] + c[1]) * H.n[0] + c[0];
+    // 32-bit byte offset from each array's uniform base (fewer than 2^29
+    // cells on a hexahedral grid)
+    const unsigned off = ((unsigned)c[0] + (unsigned)c[1] * (unsigned)H.n[0] +
+                          (unsigned)c[2] * ((unsigned)H.n[0] * (unsigned)H.n[1])) * 8u;
+    auto at = [&](const double* __restrict__ base) { return *(const double*)((const char*)base + off); };
 #pragma unroll
-    for (int e = 0; e < 3; ++e) T.c[e][t] = geo[(1 + e) * N + io] + sh[e];
+    for (int e = 0; e < 3; ++e) T.c[e][t] = at(geo + (1 + e) * N) + sh[e];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) T.m[e][t] = geo[(4 + e) * N + io];
+    for (int e = 0; e < 6; ++e) T.m[e][t] = at(geo + (4 + e) * N);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) T.q[v][t] = q[v * N + io];
+    for (int v = 0; v < 5; ++v) T.q[v][t] = at(q + v * N);
   }
 }
 

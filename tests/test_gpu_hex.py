@@ -72,6 +72,21 @@ def test_static_step(hg, n_stages):
     assert np.allclose(ctx.totals(), oracle.totals(prob, ref), rtol=1e-13)
 
 
+def test_static_step_small_grid(hg):
+    """Extents below the reconstruction tile's (8 x 8 x 4): the staged tile
+    passes the grid more than once along each axis (the general wrap)."""
+    n = (6, 5, 3)
+    verts, Q = static_case(n)
+    prob = oracle.vertex_problem(n, verts, PERIOD, params=oracle.Params(mu=1e-3))
+    ctx = make(hg, n, verts, Q, mu=1e-3)
+    ref = Q
+    for _ in range(2):
+        dt = oracle.max_dt(prob, ref, 0.35)
+        ref = oracle.step(prob, ref, dt, n_stages=2)
+        ctx.step(dt, 2)
+    assert nerr(ctx.get_state().cpu().numpy(), ref).max() < TOL
+
+
 def test_moving_steps(hg):
     n = (9, 10, 8)
     dt, t = 0.04, 0.2
