@@ -77,7 +77,7 @@ typedef enum {
 
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 2, with
-                             (nx+2)(ny+2)(nz+2) < 2^32                        */
+                             (nx+2)(ny+2)(nz+2) < 2^29                        */
   int32_t bc[3];          /* hgks_bc per axis (x, y, z): the low end, and the
                              high end too unless bc_hi says otherwise         */
   double gamma;           /* ratio of specific heats, 1 < gamma < 5/3 (1.4)   */
@@ -92,9 +92,8 @@ typedef struct {
                              paper uses 0.01 and 1                            */
   int32_t precision;      /* hgks_prec                                        */
   int32_t moving;         /* 1: hexahedral vertex grid given by
-                             hgks_set_vertices (all axes periodic, fewer than
-                             2^29 cells); 0: uniform box grid from
-                             hgks_set_uniform_grid                            */
+                             hgks_set_vertices (all axes periodic); 0: uniform
+                             box grid from hgks_set_uniform_grid              */
   void* stream;           /* hipStream_t, NULL for the default stream         */
   int32_t bc_hi[3];       /* hgks_bc at the high end of each axis, or
                              HGKS_BC_SAME (the default): as bc[d]             */

@@ -252,17 +252,23 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
       fz[t] = bc_index(G, 2, k + 4 * t - 2, gz[t]);
     }
   }
-  const size_t nx = G.n[0], nxy = (size_t)G.n[0] * G.n[1], N = nxy * G.n[2];
+  const size_t N = (size_t)G.n[0] * G.n[1] * G.n[2];
+  // element offsets in 32 bits (fewer than 2^29 cells), byte offsets from
+  // each variable's uniform base
+  const unsigned nx = (unsigned)G.n[0], nxy = (unsigned)G.n[0] * (unsigned)G.n[1];
   TC qc[5], bnd[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const double* qv = q + v * N;
+    auto ld = [&](int z, int y, int x) {
+      return *(const double*)((const char*)qv + ((unsigned)z * nxy + (unsigned)y * nx + (unsigned)x) * 8u);
+    };
     // sign of variable v in the cell at offset o: the momentum component
     // along an axis flips in a mirror image across that axis
     auto sg = [&](int ox, int oy, int oz) -> double {
       return v == 1 ? sx[ox + 1] : (v == 2 ? sy[oy + 1] : (v == 3 ? sz[oz + 1] : 1.0));
     };
-    const double c = sg(0, 0, 0) * qv[iz[1] * nxy + iy[1] * nx + ix[1]];
+    const double c = sg(0, 0, 0) * ld(iz[1], iy[1], ix[1]);
     TC d[27];
 #pragma unroll
     for (int oz = -1; oz <= 1; ++oz)
@@ -275,7 +281,7 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
             d[sidx(ox, oy, oz)] = TC(0);
           } else {
             d[sidx(ox, oy, oz)] =
-                TC(sg(ox, oy, oz) * qv[iz[oz + 1] * nxy + iy[oy + 1] * nx + ix[ox + 1]] - c);
+                TC(sg(ox, oy, oz) * ld(iz[oz + 1], iy[oy + 1], ix[ox + 1]) - c);
           }
         }
     BoxRecon<TC> r;
@@ -288,9 +294,9 @@ __device__ __forceinline__ void recon_box_cell(const double* __restrict__ q, TC*
         const double s0 = v == 1 ? gx[t] : (v == 2 ? sy[1] : (v == 3 ? sz[1] : 1.0));
         const double s1 = v == 1 ? sx[1] : (v == 2 ? gy[t] : (v == 3 ? sz[1] : 1.0));
         const double s2 = v == 1 ? sx[1] : (v == 2 ? sy[1] : (v == 3 ? gz[t] : 1.0));
-        f[t] = TC(s0 * qv[iz[1] * nxy + iy[1] * nx + fx[t]] - c);
-        f[2 + t] = TC(s1 * qv[iz[1] * nxy + fy[t] * nx + ix[1]] - c);
-        f[4 + t] = TC(s2 * qv[fz[t] * nxy + iy[1] * nx + ix[1]] - c);
+        f[t] = TC(s0 * ld(iz[1], iy[1], fx[t]) - c);
+        f[2 + t] = TC(s1 * ld(iz[1], fy[t], ix[1]) - c);
+        f[4 + t] = TC(s2 * ld(fz[t], iy[1], ix[1]) - c);
       }
       weno_box_wide(d, f, P, r);
     } else {
@@ -947,24 +953,30 @@ __device__ __forceinline__ void update_box_cell(double* __restrict__ q, double* 
     int hi[3] = {c[0], c[1], c[2]};
     hi[d] += 1;
     if (G.per[d] && hi[d] == G.n[d]) hi[d] = 0;
-    const size_t lo_i = ((size_t)c[2] * nf[1] + c[1]) * nf[0] + c[0];
-    const size_t hi_i = ((size_t)hi[2] * nf[1] + hi[1]) * nf[0] + hi[0];
+    // byte offsets in 32 bits from each array's uniform base (every array
+    // has fewer than 2^29 elements)
+    const unsigned lo_b = (unsigned)(((unsigned)c[2] * nf[1] + c[1]) * nf[0] + c[0]) * (unsigned)sizeof(TF);
+    const unsigned hi_b = (unsigned)(((unsigned)hi[2] * nf[1] + hi[1]) * nf[0] + hi[0]) * (unsigned)sizeof(TF);
 #pragma unroll
-    for (int k = 0; k < 10; ++k) R[k] -= (double)fs[d][k * NF + hi_i] - (double)fs[d][k * NF + lo_i];
+    for (int k = 0; k < 10; ++k) {
+      const char* base = (const char*)(fs[d] + k * NF);
+      R[k] -= (double)*(const TF*)(base + hi_b) - (double)*(const TF*)(base + lo_b);
+    }
   }
   const double iv = 1.0 / G.vol;
+  const unsigned ob = (unsigned)idx * 8u;
+  auto at = [&](double* a, int v) -> double& { return *(double*)((char*)(a + (size_t)v * N) + ob); };
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const double L = R[v] * iv, dL = R[5 + v] * iv;
-    const size_t o = (size_t)v * N + idx;
     if (mode == 0) {
-      q[o] = q[o] + dt * L + 0.5 * dt * dt * dL;
+      at(q, v) = at(q, v) + dt * L + 0.5 * dt * dt * dL;
     } else if (mode == 1) {
-      const double q0 = q[o];
-      qs[o] = q0 + 0.5 * dt * L + 0.125 * dt * dt * dL;
-      acc[o] = q0 + dt * L + dt * dt / 6.0 * dL;
+      const double q0 = at(q, v);
+      at(qs, v) = q0 + 0.5 * dt * L + 0.125 * dt * dt * dL;
+      at(acc, v) = q0 + dt * L + dt * dt / 6.0 * dL;
     } else {
-      q[o] = acc[o] + dt * dt / 3.0 * dL;
+      at(q, v) = at(acc, v) + dt * dt / 3.0 * dL;
     }
   }
 }

@@ -84,12 +84,11 @@ bool valid_config(const hgks_config* c) {
   if (c->moving)
     for (int d = 0; d < 3; ++d)
       if (c->bc[d] != HGKS_BC_PERIODIC) return false;
-  // Cell and face indices are split in 32-bit arithmetic.
-  if (((uint64_t)c->nx + 2) * ((uint64_t)c->ny + 2) * ((uint64_t)c->nz + 2) >= (1ull << 32)) return false;
-  // The hexahedral face flux addresses the vertex arrays with 32-bit byte
-  // offsets (below 2^32 for N < 2^29 vertices; a grid that large would need
-  // over 600 GB of workspace anyway).
-  if (c->moving && (uint64_t)c->nx * c->ny * c->nz >= (1ull << 29)) return false;
+  // Cell and face indices are split in 32-bit arithmetic, and kernels
+  // address their arrays with 32-bit byte offsets from uniform bases: fewer
+  // than 2^29 elements per array (a grid that large would need some 400 GB
+  // of workspace in FP64 anyway).
+  if (((uint64_t)c->nx + 2) * ((uint64_t)c->ny + 2) * ((uint64_t)c->nz + 2) >= (1ull << 29)) return false;
   return true;
 }
 

@@ -52,7 +52,7 @@ def test_defaults_and_workspace(lib):
 @pytest.mark.parametrize("field,value", [("nx", 1), ("gamma", 1.0), ("weno_Gamma", 0.05),
                                          ("weno_eps", 0.0), ("precision", 7), ("moving", 2),
                                          ("characteristic", 2), ("mu_T0", 0.0), ("prandtl", 0.0),
-                                         # cell and face indices are split in 32 bits
+                                         # 32-bit indices and byte offsets
                                          ("nx", 2 ** 31 - 1), ("nz", 1 << 26)])
 def test_invalid_configurations_rejected(lib, field, value):
     from paper_1909_01580_amd import hgks
@@ -63,20 +63,19 @@ def test_invalid_configurations_rejected(lib, field, value):
     assert e.value.status == hgks.HGKS_EINVAL
 
 
-def test_moving_grid_size_limit(lib):
-    """A moving (hexahedral) grid addresses its vertex arrays with 32-bit
-    byte offsets: fewer than 2^29 cells; the same extents on a box grid are
-    accepted."""
+def test_grid_size_limit(lib):
+    """Kernels address their arrays with 32-bit byte offsets: every grid,
+    box or hexahedral, needs (nx+2)(ny+2)(nz+2) < 2^29."""
     from paper_1909_01580_amd import hgks
-    cfg = hgks.hgks_default_config(1024, 1024, 512)          # 2^29 cells
-    assert hgks.hgks_workspace_size(cfg) > 0
-    cfg.moving = 1
-    with pytest.raises(hgks.HGKSError) as e:
-        hgks.hgks_workspace_size(cfg)
-    assert e.value.status == hgks.HGKS_EINVAL
-    cfg = hgks.hgks_default_config(1024, 1024, 511)
-    cfg.moving = 1
-    assert hgks.hgks_workspace_size(cfg) > 0
+    for moving in (0, 1):
+        cfg = hgks.hgks_default_config(1022, 1022, 510)        # 2^29 with the layers
+        cfg.moving = moving
+        with pytest.raises(hgks.HGKSError) as e:
+            hgks.hgks_workspace_size(cfg)
+        assert e.value.status == hgks.HGKS_EINVAL
+        cfg = hgks.hgks_default_config(1022, 1022, 509)
+        cfg.moving = moving
+        assert hgks.hgks_workspace_size(cfg) > 0
 
 
 def test_boundary_ends(lib):
