@@ -1376,6 +1376,11 @@ __global__ void __launch_bounds__(kBlock) k_update_hex(HexGrid H, double* __rest
   split_index((uint32_t)idx, H.n[0], H.n[1], H.box.inv_n[0], H.box.inv_n[1], c[0], c[1], c[2]);
   const TF* fs[3] = {fx, fy, fz};
   const double* vs[3] = {vx, vy, vz};
+  // byte offsets in 32 bits from each array's uniform base (fewer than 2^29
+  // cells)
+  const unsigned ob = (unsigned)idx * 8u;
+  auto ld = [](const auto* base, unsigned off) { return *(const decltype(+*base)*)((const char*)base + off); };
+  auto el = [&](double* a, int v) -> double& { return *(double*)((char*)(a + (size_t)v * N) + ob); };
   double R[12];
 #pragma unroll
   for (int e = 0; e < 12; ++e) R[e] = 0.0;
@@ -1383,32 +1388,33 @@ __global__ void __launch_bounds__(kBlock) k_update_hex(HexGrid H, double* __rest
   for (int d = 0; d < 3; ++d) {
     int hi[3] = {c[0], c[1], c[2]};
     hi[d] = hi[d] + 1 == H.n[d] ? 0 : hi[d] + 1;
-    const size_t hi_i = ((size_t)hi[2] * H.n[1] + hi[1]) * H.n[0] + hi[0];
+    const unsigned hi_i = ((unsigned)hi[2] * (unsigned)H.n[1] + (unsigned)hi[1]) * (unsigned)H.n[0] + (unsigned)hi[0];
+    const unsigned hf = hi_i * (unsigned)sizeof(TF), lf = (unsigned)idx * (unsigned)sizeof(TF);
 #pragma unroll
-    for (int e = 0; e < 10; ++e) R[e] -= (double)fs[d][e * N + hi_i] - (double)fs[d][e * N + idx];
-    R[10] += vs[d][hi_i] - vs[d][idx];
-    R[11] += vs[d][N + hi_i] - vs[d][N + idx];
+    for (int e = 0; e < 10; ++e) R[e] -= (double)ld(fs[d] + e * N, hf) - (double)ld(fs[d] + e * N, lf);
+    R[10] += ld(vs[d], hi_i * 8u) - ld(vs[d], ob);
+    R[11] += ld(vs[d] + N, hi_i * 8u) - ld(vs[d] + N, ob);
   }
   if (mode == 2) {
-    const double Vn = vacc[idx] + dt * dt / 3.0 * R[11];
+    const double Vn = ld(vacc, ob) + dt * dt / 3.0 * R[11];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) q[v * N + idx] = (acc[v * N + idx] + dt * dt / 3.0 * R[5 + v]) / Vn;
+    for (int v = 0; v < 5; ++v) el(q, v) = (el(acc, v) + dt * dt / 3.0 * R[5 + v]) / Vn;
     return;
   }
-  const double V = geo[idx];
+  const double V = ld(geo, ob);
   if (mode == 0) {
     const double Vn = V + dt * R[10] + 0.5 * dt * dt * R[11];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) q[v * N + idx] = (V * q[v * N + idx] + dt * R[v] + 0.5 * dt * dt * R[5 + v]) / Vn;
+    for (int v = 0; v < 5; ++v) el(q, v) = (V * el(q, v) + dt * R[v] + 0.5 * dt * dt * R[5 + v]) / Vn;
     return;
   }
   const double Vs = V + 0.5 * dt * R[10] + 0.125 * dt * dt * R[11];
-  vacc[idx] = V + dt * R[10] + dt * dt / 6.0 * R[11];
+  *(double*)((char*)vacc + ob) = V + dt * R[10] + dt * dt / 6.0 * R[11];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double U = V * q[v * N + idx];
-    qs[v * N + idx] = (U + 0.5 * dt * R[v] + 0.125 * dt * dt * R[5 + v]) / Vs;
-    acc[v * N + idx] = U + dt * R[v] + dt * dt / 6.0 * R[5 + v];
+    const double U = V * el(q, v);
+    el(qs, v) = (U + 0.5 * dt * R[v] + 0.125 * dt * dt * R[5 + v]) / Vs;
+    el(acc, v) = U + dt * R[v] + dt * dt / 6.0 * R[5 + v];
   }
 }
 
