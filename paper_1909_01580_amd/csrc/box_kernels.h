@@ -664,23 +664,26 @@ HGKS_FN void eval_box_gp_dir(int D, const TC* __restrict__ coef, size_t cell, TC
 // point of a cell reconstructed in characteristic variables: cv points at
 // the cell in its face array, Qbar is the face's mean state.  The result is
 // in the local variable order of eval_box_gp.
-template <int D, typename TC>
+//
+// From global memory (PRE) all 45 coefficients are requested before the
+// eigenvectors are formed (the fence keeps the loads there), so that their
+// latency overlaps it; from LDS each field's nine are read where they are
+// used, which keeps the registers of the other 36 free.
+template <int D, bool PRE = true, typename TC>
 __device__ __forceinline__ void eval_char_gp(const TC* cv, const double (&Qbar)[5], double gamma, TC xD, TC xA,
                                              TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
                                              TC (&dW)[3][5]) {
   constexpr int A = (D + 1) % 3, B = (D + 2) % 3, CB = kCB<TC>;
   constexpr int lv[5] = {0, 1 + D, 1 + A, 1 + B, 4};
   constexpr int cp[9] = {D, A, B, 3 + D, 3 + A, 3 + B, 6 + D, 6 + A, 6 + B};
-  // All 45 coefficients are requested before the eigenvectors are formed
-  // (the fence keeps the loads there), so that their latency overlaps it;
-  // the flux forms both sides' states before any side terms, so the
-  // registers for them are there.
   TC call[5][9];
+  if constexpr (PRE) {
 #pragma unroll
-  for (int f = 0; f < 5; ++f)
+    for (int f = 0; f < 5; ++f)
 #pragma unroll
-    for (int m = 0; m < 9; ++m) call[f][m] = cv[(f * 10 + cp[m] + 1) * CB];
-  asm volatile("" ::: "memory");
+      for (int m = 0; m < 9; ++m) call[f][m] = cv[(f * 10 + cp[m] + 1) * CB];
+    asm volatile("" ::: "memory");
+  }
   CharBasis Bs;
   char_basis(Qbar, D, gamma, Bs);
   TC val[5], grad[5][3];
@@ -694,7 +697,7 @@ __device__ __forceinline__ void eval_char_gp(const TC* cv, const double (&Qbar)[
     for (int f = 0; f < 5; ++f) {
       TC c[9];
 #pragma unroll
-      for (int m = 0; m < 9; ++m) c[m] = call[f][m];
+      for (int m = 0; m < 9; ++m) c[m] = PRE ? call[f][m] : cv[(f * 10 + cp[m] + 1) * CB];
       TC du, g[3];
       quad_eval(TC(0), c, xD, xA, xB, du, g[0], g[1], g[2]);
       double r[5];
@@ -716,16 +719,16 @@ __device__ __forceinline__ void eval_char_gp(const TC* cv, const double (&Qbar)[
   }
 }
 
-template <typename TC>
+template <bool PRE = true, typename TC>
 __device__ __forceinline__ void eval_char_gp_dir(int D, const TC* cv, const double (&Qbar)[5], double gamma, TC xD,
                                                  TC xA, TC xB, bool fallback, const TC (&invd)[3], TC (&W)[5],
                                                  TC (&dW)[3][5]) {
   if (D == 0)
-    eval_char_gp<0>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
+    eval_char_gp<0, PRE>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
   else if (D == 1)
-    eval_char_gp<1>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
+    eval_char_gp<1, PRE>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
   else
-    eval_char_gp<2>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
+    eval_char_gp<2, PRE>(cv, Qbar, gamma, xD, xA, xB, fallback, invd, W, dW);
 }
 
 // LDS of the FP64 flux's right cells, in doubles: per group of 8 faces 50
@@ -783,23 +786,7 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
   // the left side assigns the sums, the right side adds to them
   FluxAcc<TC> acc;
   acc_begin(acc);
-  if constexpr (FS) {
-    // characteristic reconstruction: the face's mean state from the two
-    // cells' conservative means gives R for both sides
-    double Qbar[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v)
-      Qbar[v] = 0.5 * ((double)coefL[coef_cell<TC>(iL) + v * 10 * kCB<TC>] +
-                       (double)coefR[coef_cell<TC>(iR) + v * 10 * kCB<TC>]);
-    // Both sides' Gauss-point states are formed before any side terms,
-    // while the flux accumulators are not yet live: there are registers for
-    // each side's 45 coefficient loads to be in flight together.
-    TC WL[5], dWL[3][5], WR[5], dWR[3][5];
-    eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, WL, dWL);
-    eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, WR, dWR);
-    side_terms<+1, PR, kAssignFirst<TC>>(WL, dWL, gp, acc);
-    side_terms<-1, PR>(WR, dWR, gp, acc);
-  } else if constexpr (DMA) {
+  if constexpr (DMA) {
     // The right cells' 50 values go to LDS by direct loads issued before
     // the left side's terms: they arrive while those run and hold no
     // registers meanwhile.  Each wave copies the right cells of its own 16
@@ -815,9 +802,21 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     // 8 g + (l / 2) % 8, 32-bit half l % 2: byte 4 l of the piece
     unsigned cell0 = __shfl((unsigned)iR, (int)(((l >> 1) & 7u) * 4u));
     unsigned cell1 = __shfl((unsigned)iR, (int)((8u + ((l >> 1) & 7u)) * 4u));
+    // characteristic reconstruction: the face's mean state from the two
+    // cells' conservative means gives R for both sides
+    double Qbar[5];
+    if constexpr (FS) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        Qbar[v] = 0.5 * ((double)coefL[coef_cell<TC>(iL) + v * 10 * kCB<TC>] +
+                         (double)coefR[coef_cell<TC>(iR) + v * 10 * kCB<TC>]);
+    }
     {
       TC W[5], dW[3][5];
-      eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
+      if constexpr (FS)
+        eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, W, dW);
+      else
+        eval_box_gp_dir(D, coefL, iL, TC(0.5), xa, xb, fbL, invd, W, dW);
       // The copies are issued once the left cell's values have arrived: the
       // memory counter is waited on in issue order, so copies issued
       // earlier would hold up the left side's first use of its loads.
@@ -846,7 +845,9 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
     {
       TC W[5], dW[3][5];
       const TC* cv = rs + (slot >> 3) * kStageGroup + (slot & 7u);
-      if (D == 0)
+      if constexpr (FS)
+        eval_char_gp_dir<false>(D, cv, Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, W, dW);
+      else if (D == 0)
         eval_rows_gp<0, 8>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
       else if (D == 1)
         eval_rows_gp<1, 8>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
@@ -854,6 +855,20 @@ __device__ __forceinline__ void flux_box_face(const TC* __restrict__ coef, const
         eval_rows_gp<2, 8>(cv, TC(-0.5), xa, xb, fbR, invd, W, dW);
       side_terms<-1, PR>(W, dW, gp, acc);
     }
+  } else if constexpr (FS) {
+    double Qbar[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      Qbar[v] = 0.5 * ((double)coefL[coef_cell<TC>(iL) + v * 10 * kCB<TC>] +
+                       (double)coefR[coef_cell<TC>(iR) + v * 10 * kCB<TC>]);
+    // Both sides' Gauss-point states are formed before any side terms,
+    // while the flux accumulators are not yet live: there are registers for
+    // each side's 45 coefficient loads to be in flight together.
+    TC WL[5], dWL[3][5], WR[5], dWR[3][5];
+    eval_char_gp_dir(D, coefL + coef_cell<TC>(iL), Qbar, gp.gamma, TC(0.5), xa, xb, fbL, invd, WL, dWL);
+    eval_char_gp_dir(D, coefR + coef_cell<TC>(iR), Qbar, gp.gamma, TC(-0.5), xa, xb, fbR, invd, WR, dWR);
+    side_terms<+1, PR, kAssignFirst<TC>>(WL, dWL, gp, acc);
+    side_terms<-1, PR>(WR, dWR, gp, acc);
   } else {
     {
       TC W[5], dW[3][5];
@@ -923,7 +938,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY k_flux_box(
   unsigned lb;
   flux_block(b, nb, D, lb);
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
-  if constexpr (sizeof(TC) == 8 && !FS) {
+  if constexpr (sizeof(TC) == 8) {
     __shared__ double stage[kBlock / 64 * kStageWave];
     flux_box_face<TC, PR, FS, true>(coef, mask, face, G, gp, dt, idt, lb, D, stage);
   } else {
