@@ -920,11 +920,13 @@ __global__ void __launch_bounds__(kBlock) k_posit_exact_hex(HexGrid H, const dou
 // physical point x (centroid shifted by `shift` for periodic images), in
 // the compute type: the scaled coordinates are formed in double (absolute
 // positions), the polynomial is evaluated in TC.  A first-order fallback
-// point gives the cell mean and zero gradient (Sec. 4).
+// point gives the cell mean and zero gradient (Sec. 4).  cv points at the
+// cell's 50 rows, kCB values apart: in the coefficient array or in a staged
+// copy with the same row stride.
 template <typename TC>
-__device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const double* __restrict__ geo, size_t N,
-                                         size_t idx, const double (&shift)[3], const double (&x)[3], bool fb,
-                                         TC (&val)[5], TC (&grad)[5][3]) {
+__device__ __forceinline__ void eval_hex_rows(const TC* cv, const double* __restrict__ geo, size_t N, size_t idx,
+                                              const double (&shift)[3], const double (&x)[3], bool fb, TC (&val)[5],
+                                              TC (&grad)[5][3]) {
   HexCell C;
   load_cell(geo, N, idx, C);
   TC X[3], m[6];
@@ -933,7 +935,6 @@ __device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const doub
 #pragma unroll
   for (int e = 0; e < 6; ++e) m[e] = TC(C.m[e]);
   const TC ih = TC(C.ih);
-  const TC* cv = coef + coef_cell<TC>(idx);
   constexpr int CB = kCB<TC>;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -957,6 +958,13 @@ __device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const doub
       grad[v][0] = grad[v][1] = grad[v][2] = TC(0);
     }
   }
+}
+
+template <typename TC>
+__device__ __forceinline__ void eval_hex(const TC* __restrict__ coef, const double* __restrict__ geo, size_t N,
+                                         size_t idx, const double (&shift)[3], const double (&x)[3], bool fb,
+                                         TC (&val)[5], TC (&grad)[5][3]) {
+  eval_hex_rows(coef + coef_cell<TC>(idx), geo, N, idx, shift, x, fb, val, grad);
 }
 
 // Frame of Sec. 3 at the face point P: n along X_a x X_b, t2 along X_b,
@@ -1115,7 +1123,7 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
                                               const double* __restrict__ geo, const uint32_t* __restrict__ mask,
                                               TC* __restrict__ face, double* __restrict__ vface,
                                               const GasParams<TC>& gp, TC dt, TC idt, size_t N, unsigned lb, int D,
-                                              double (&stash)[kHexStash<FS>][kBlock]) {
+                                              double (&stash)[kHexStash<FS>][kBlock], TC* stage = nullptr) {
   const int gpi = (int)(threadIdx.x & 3);
   int c[3];
   size_t f;
@@ -1266,6 +1274,62 @@ __device__ __forceinline__ void flux_hex_face(const HexGrid& H, const TC* __rest
     }
     side_terms<+1, PR, kAssignFirst<TC>>(WL, dWL, gp, acc);
     side_terms<-1, PR>(WR, dWR, gp, acc);
+  } else if constexpr (!FS) {
+    // FP64: the right cells' coefficients are staged in LDS by direct
+    // loads issued after the left cell's values have arrived, as in the box
+    // flux (the same [50 rows][8 faces] groups of 64-byte rows), and read
+    // from there after the left side's terms; the right cell's geometry
+    // comes from global memory as before.
+    static_assert(sizeof(TC) == 8 && kCB<TC> == 8, "rows of 8 doubles");
+    const unsigned l = threadIdx.x & 63u;
+    TC* rs = stage + (threadIdx.x >> 6) * kStageWave;
+    unsigned cell0 = __shfl((unsigned)iR, (int)(((l >> 1) & 7u) * 4u));
+    unsigned cell1 = __shfl((unsigned)iR, (int)((8u + ((l >> 1) & 7u)) * 4u));
+    {
+      asm volatile("" ::: "memory");
+      double x[3], u[3], n0[3], n1[3], n2[3];
+      get3(0, x);
+      get3(3, u);
+      get3(6, n0);
+      get3(9, n1);
+      get3(12, n2);
+      TC val[5], grad[5][3];
+      eval_hex(coefL, geo, N, iL, shL, x, fbL, val, grad);
+      TC W[5], dW[3][5];
+      to_local(val, grad, u, n0, n1, n2, W, dW);
+      asm volatile("" : "+v"(cell0), "+v"(cell1) : "v"(W[0]), "v"(dW[2][4]));
+      const unsigned lane = (l >> 4) * 64 + (l & 1u) * 4;
+      const GlobalPtr s0 = (GlobalPtr)((const char*)(coefR + coef_cell<TC>(cell0)) + lane);
+      const GlobalPtr s1 = (GlobalPtr)((const char*)(coefR + coef_cell<TC>(cell1)) + lane);
+      const LdsPtr d0 = (LdsPtr)rs;
+      const LdsPtr d1 = (LdsPtr)(rs + kStageGroup);
+      copy_pieces<0, 12>(s0, d0);
+      copy_pieces<0, 12>(s1, d1);
+      if (l < 32u) {
+        copy_pieces<12, 13>(s0, d0);
+        copy_pieces<12, 13>(s1, d1);
+      }
+      side_terms<+1, PR, kAssignFirst<TC>>(W, dW, gp, acc);
+    }
+    size_t iRt = iR;
+    after_left_side(iRt, acc);
+    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("" ::: "memory");
+    {
+      const unsigned slot = threadIdx.x >> 2 & 15u;
+      const TC* cv = rs + (slot >> 3) * kStageGroup + (slot & 7u);
+      double x[3], u[3], n0[3], n1[3], n2[3];
+      get3(0, x);
+      get3(3, u);
+      get3(6, n0);
+      get3(9, n1);
+      get3(12, n2);
+      TC val[5], grad[5][3];
+      eval_hex_rows(cv, geo, N, iRt, shR, x, fbR, val, grad);
+      TC W[5], dW[3][5];
+      to_local(val, grad, u, n0, n1, n2, W, dW);
+      side_terms<-1, PR>(W, dW, gp, acc);
+    }
   } else {
     {
       asm volatile("" ::: "memory");
@@ -1356,7 +1420,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
   TC* face = D == 0 ? fx : (D == 1 ? fy : fz);
   double* vface = D == 0 ? vx : (D == 1 ? vy : vz);
   __shared__ double stash[kHexStash<FS>][kBlock];
-  flux_hex_face<TC, PR, FS>(H, coef, geo, mask, face, vface, gp, dt, idt, N, lb, D, stash);
+  if constexpr (sizeof(TC) == 8 && !FS) {
+    __shared__ double stage[kBlock / 64 * kStageWave];
+    flux_hex_face<TC, PR, FS>(H, coef, geo, mask, face, vface, gp, dt, idt, N, lb, D, stash, stage);
+  } else {
+    flux_hex_face<TC, PR, FS>(H, coef, geo, mask, face, vface, gp, dt, idt, N, lb, D, stash);
+  }
 }
 
 // ---------------------------------------------------------------- K4
