@@ -123,10 +123,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __r
 
 // PR: the extended viscous model (viscosity law, Prandtl correction), per
 // grid through its gas parameters (trivial for grids that use neither).
+// FP64 stages the right cells in LDS as the single-grid flux does; in the
+// persistent form a wave's staged values are consumed before its next
+// tile's copies are issued.
 template <typename TC, bool LOOP, bool PR = false>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
     k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles, const TC* __restrict__ coef,
                  const uint32_t* __restrict__ mask, TC* __restrict__ face, const double* __restrict__ dt) {
+  constexpr bool kStage = sizeof(TC) == 8;
+  __shared__ TC stage[kStage ? kBlock / 64 * kStageWave : 1];
   for_tiles<LOOP>(ntiles, [&](unsigned t) {
     const int g = batch_grid_of<TC, true>(B, ng, t);
     const BatchGrid<TC>& b = B[g];
@@ -139,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
     const unsigned nb[3] = {b.nt_flux[0], b.nt_flux[1], b.nt_flux[2]};
     int D;
     flux_block(t - b.t_flux, nb, D, lt);
-    flux_box_face<TC, PR>(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D);
+    flux_box_face<TC, PR, false, kStage>(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D, stage);
   });
 }
 
