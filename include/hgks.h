@@ -119,9 +119,10 @@ typedef struct {
                              Remark 1 (S plus the cells two steps away along
                              the axes, 8 octant sub-stencils, linear weights
                              1 - 8 Gamma and Gamma).  Box and hexahedral
-                             grids, component-wise reconstruction, not in
-                             batches; a symmetric end needs at least 3 cells
-                             on its axis                                     */
+                             grids and batches (one family for every grid of
+                             a batch), component-wise reconstruction; a
+                             symmetric end needs at least 3 cells on its
+                             axis                                            */
 } hgks_config;
 
 /* Fills *cfg with the paper's defaults (gamma 1.4, Gamma 0.0025, eps 1e-8,
@@ -257,9 +258,10 @@ hgks_status hgks_sync(hgks_ctx ctx);
  *
  * cfgs[i] describes grid i (sizes, mu, and the viscosity law and Prandtl
  * number, mu_T0, mu_exponent, prandtl); every grid must be a uniform box
- * (moving = 0, component-wise reconstruction on the stencils of Sec. 2)
- * with all axes periodic, and gamma, weno_Gamma, weno_eps, tau_eps, tau_C
- * and precision must equal those of cfgs[0].  The stream
+ * (moving = 0, component-wise reconstruction) with all axes periodic, and
+ * gamma, weno_Gamma, weno_eps, tau_eps, tau_C, precision and the stencil
+ * family (stencil: Sec. 2 or Remark 1) must equal those of cfgs[0];
+ * otherwise HGKS_EINVAL and nothing is created.  The stream
  * of cfgs[0] is used; it must not be the legacy default stream when
  * hgks_batch_capture is used.  Grid i's state is [5][nz_i][ny_i][nx_i]. */
 hgks_status hgks_batch_workspace_size(const hgks_config* cfgs, int32_t n, size_t* bytes);

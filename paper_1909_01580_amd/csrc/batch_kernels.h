@@ -96,7 +96,9 @@ __device__ __forceinline__ void for_tiles(unsigned ntiles, F&& body) {
   }
 }
 
-template <typename TC, bool LOOP>
+// WIDE: the stencils of Remark 1 for every grid of the batch (the flux and
+// update do not depend on the stencil family).
+template <typename TC, bool LOOP, bool WIDE = false>
 __global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                         const double* __restrict__ q, TC* __restrict__ coef,
                                                         uint32_t* __restrict__ mask, TC margin, TC gm1) {
@@ -104,12 +106,12 @@ __global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __r
     const int g = batch_grid_of<TC, false>(B, ng, t);
     size_t idx;
     if (batch_cell(B[g], t - B[g].t_cell, threadIdx.x, idx))
-      recon_box_cell(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin, gm1,
-                     B[g].N, idx);
+      recon_box_cell<TC, WIDE>(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin,
+                               gm1, B[g].N, idx);
   });
 }
 
-template <typename TC, bool LOOP>
+template <typename TC, bool LOOP, bool WIDE = false>
 __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                         const double* __restrict__ q, uint32_t* __restrict__ mask,
                                                         TC gm1) {
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __r
     const int g = batch_grid_of<TC, false>(B, ng, t);
     size_t idx;
     if (batch_cell(B[g], t - B[g].t_cell, threadIdx.x, idx) && mask[B[g].mask_off + idx] == kNeedsCheck)
-      posit_exact_box_cell(q + B[g].q_off, mask + B[g].mask_off, B[g].G, gm1, idx);
+      posit_exact_box_cell<TC, WIDE>(q + B[g].q_off, mask + B[g].mask_off, B[g].G, gm1, idx);
   });
 }
 

@@ -963,6 +963,7 @@ struct hgks_batch_s {
   int ct[3] = {0, 0, 0};   // cell tile shape (0: 256 consecutive cells)
   int band = kFluxBand;    // rows per band of the flux block order
   bool ext = false;  // some grid uses the viscosity law or the Prandtl correction
+  bool wide = false;  // every grid reconstructs with the stencils of Remark 1
   std::vector<BatchGrid<double>> gd;  // host copies of the descriptors
   std::vector<BatchGrid<float>> gf;
   std::vector<bool> grid_set, state_set;
@@ -988,11 +989,11 @@ hgks_status busable(hgks_batch b) {
 }
 
 bool batch_compatible(const hgks_config& a, const hgks_config& c) {
-  if (!valid_config(&c) || c.moving || c.characteristic || c.stencil) return false;
+  if (!valid_config(&c) || c.moving || c.characteristic) return false;
   for (int d = 0; d < 3; ++d)
     if (c.bc[d] != HGKS_BC_PERIODIC) return false;
   return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&
-         c.tau_eps == a.tau_eps && c.tau_C == a.tau_C && c.precision == a.precision;
+         c.tau_eps == a.tau_eps && c.tau_C == a.tau_C && c.precision == a.precision && c.stencil == a.stencil;
 }
 
 // Offsets of every arena and the per-grid descriptors (without the grid
@@ -1135,6 +1136,15 @@ unsigned batch_wg(hgks_batch b, int phase, unsigned tiles) {
 // Persistent tile walk (a workgroup count was set) or one workgroup per tile.
 bool batch_loop(hgks_batch b, int phase) { return b->wg[phase] > 0; }
 
+// The same with a third template argument W (the stencil family).
+#define HGKS_BATCH_LAUNCH_W(kernel, TC, W, loop, grid, ...)                                              \
+  do {                                                                                                 \
+    if (loop)                                                                                          \
+      hipLaunchKernelGGL((kernel<TC, true, W>), dim3(grid), dim3(kBlock), 0, __VA_ARGS__);            \
+    else                                                                                               \
+      hipLaunchKernelGGL((kernel<TC, false, W>), dim3(grid), dim3(kBlock), 0, __VA_ARGS__);           \
+  } while (0)
+
 #define HGKS_BATCH_LAUNCH(kernel, TC, loop, grid, ...)                                                   \
   do {                                                                                                 \
     if (loop)                                                                                          \
@@ -1162,11 +1172,17 @@ hgks_status batch_stage(hgks_batch b, const double* qin, const double* dt_dev) {
   uint32_t* mask = (uint32_t*)(b->ws + b->mask);
   const TC margin = sizeof(TC) == 8 ? TC(1e-10) : TC(1e-5);
   const TC gm1 = TC(b->base.gamma - 1.0);
-  HGKS_BATCH_LAUNCH(k_batch_recon, TC, batch_loop(b, HGKS_PHASE_RECON), batch_wg(b, HGKS_PHASE_RECON, b->tiles_cell),
-                    b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin, gm1);
-  HGKS_BATCH_LAUNCH(k_batch_posit, TC, batch_loop(b, HGKS_PHASE_FALLBACK),
-                    batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell), b->stream, D, b->ng, b->tiles_cell, qin, mask,
-                    gm1);
+  const bool rl = batch_loop(b, HGKS_PHASE_RECON), pl = batch_loop(b, HGKS_PHASE_FALLBACK);
+  const unsigned rg = batch_wg(b, HGKS_PHASE_RECON, b->tiles_cell), pg = batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell);
+  if (b->wide) {
+    HGKS_BATCH_LAUNCH_W(k_batch_recon, TC, true, rl, rg, b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin,
+                        gm1);
+    HGKS_BATCH_LAUNCH_W(k_batch_posit, TC, true, pl, pg, b->stream, D, b->ng, b->tiles_cell, qin, mask, gm1);
+  } else {
+    HGKS_BATCH_LAUNCH_W(k_batch_recon, TC, false, rl, rg, b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin,
+                        gm1);
+    HGKS_BATCH_LAUNCH_W(k_batch_posit, TC, false, pl, pg, b->stream, D, b->ng, b->tiles_cell, qin, mask, gm1);
+  }
   {
     const bool loop = batch_loop(b, HGKS_PHASE_FLUX);
     const dim3 grid(batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux));
@@ -1260,6 +1276,7 @@ hgks_status hgks_batch_create(const hgks_config* cfgs, int32_t n, void* ws, size
   else
     batch_layout<double>(cfgs, n, b, b->gd);
   for (int i = 0; i < n; ++i) b->ext = b->ext || cfgs[i].prandtl != 1.0 || cfgs[i].mu_exponent != 0.0;
+  b->wide = cfgs[0].stencil == 1;
   b->grid_set.assign(n, false);
   b->state_set.assign(n, false);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, b->stream, (uint32_t*)(b->ws + b->status));

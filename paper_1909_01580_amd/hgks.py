@@ -459,7 +459,8 @@ class Batch:
     """Independent periodic box grids advanced together.  ``grids`` is a
     list of dicts with keys n (nx, ny, nz), length (Lx, Ly, Lz) and mu, and
     optionally the grid's own viscosity law and Prandtl number (mu_T0,
-    mu_exponent, prandtl); keyword arguments set a field for every grid."""
+    mu_exponent, prandtl); keyword arguments set a field for every grid
+    (``stencil="S_prime"``: the stencils of Remark 1 for the whole batch)."""
 
     def __init__(self, grids, gamma=1.4, precision="mixed", device="cuda:0", stream=None, **kw):
         self.device = torch.device(device)
@@ -472,7 +473,7 @@ class Batch:
             cfg.gamma, cfg.mu = gamma, g.get("mu", 0.0)
             cfg.precision = PREC[precision]
             for k, v in kw.items():
-                setattr(cfg, k, v)
+                setattr(cfg, k, STENCIL[v] if k == "stencil" else v)
             for k in ("mu_T0", "mu_exponent", "prandtl"):
                 if k in g:
                     setattr(cfg, k, g[k])

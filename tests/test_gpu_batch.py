@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests.helpers import smooth_state
+from tests.helpers import nerr, smooth_state
 
 pytestmark = pytest.mark.gpu
 
@@ -31,17 +31,17 @@ def states():
     return [smooth_state(g["n"], g["length"], 40 + i, mach=0.5) for i, g in enumerate(GRIDS)]
 
 
-def make_batch(hg, precision, qs):
-    b = hg.Batch(GRIDS, precision=precision)
+def make_batch(hg, precision, qs, stencil="S"):
+    b = hg.Batch(GRIDS, precision=precision, stencil=stencil)
     for i, q in enumerate(qs):
         b.set_state(i, torch.tensor(q, device="cuda:0"))
     return b
 
 
-def run_single(hg, precision, qs, dts_per_step):
+def run_single(hg, precision, qs, dts_per_step, stencil="S"):
     out = []
     for i, g in enumerate(GRIDS):
-        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision)
+        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision, stencil=stencil)
         ctx.set_uniform_grid((0, 0, 0), g["length"])
         ctx.set_state(torch.tensor(qs[i], device="cuda:0"))
         for dts in dts_per_step:
@@ -50,10 +50,12 @@ def run_single(hg, precision, qs, dts_per_step):
     return out
 
 
+@pytest.mark.parametrize("stencil", ["S", "S_prime"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batch_equals_single_grids(hg, precision):
+def test_batch_equals_single_grids(hg, precision, stencil):
+    """stencil S_prime: the stencils of Remark 1 for every grid."""
     qs = states()
-    b = make_batch(hg, precision, qs)
+    b = make_batch(hg, precision, qs, stencil)
     dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
     dts_per_step = []
     for _ in range(3):
@@ -62,7 +64,7 @@ def test_batch_equals_single_grids(hg, precision):
         dts_per_step.append(dt.cpu().numpy().copy())
         b.step(dt, 2)
     b.sync()
-    single = run_single(hg, precision, qs, dts_per_step)
+    single = run_single(hg, precision, qs, dts_per_step, stencil)
     # The batch and single-grid kernels run the same per-face and per-cell
     # code, but the compiler may fuse float operations differently in the
     # two kernels: FP64 agrees to round-off, mixed to float rounding.
@@ -73,10 +75,35 @@ def test_batch_equals_single_grids(hg, precision):
         assert err < tol, (i, err)
     # per-grid dt equals the single-grid reduction
     for i, g in enumerate(GRIDS):
-        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision)
+        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision, stencil=stencil)
         ctx.set_uniform_grid((0, 0, 0), g["length"])
         ctx.set_state(torch.tensor(qs[i], device="cuda:0"))
         assert abs(ctx.max_dt(0.35) - dts_per_step[0][i]) <= 1e-15 * dts_per_step[0][i]
+
+
+@pytest.mark.parametrize("stencil", ["S", "S_prime"])
+def test_batch_step_against_oracle(hg, stencil):
+    """One two-stage FP64 step of every grid of the batch against the
+    oracle's step of that grid (periodic, its own mu and time step),
+    element by element: normalised max-norm error <= 1e-12."""
+    import oracle
+
+    qs = states()
+    b = make_batch(hg, "fp64", qs, stencil)
+    dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
+    b.max_dt(0.35, dt)
+    b.sync()
+    dts = dt.cpu().numpy().copy()
+    b.step(dt, 2)
+    b.sync()
+    for i, g in enumerate(GRIDS):
+        prob = oracle.uniform_problem(g["n"], (0.0, 0.0, 0.0), g["length"], bc=("periodic",) * 3,
+                                      params=oracle.Params(mu=g["mu"], stencil=stencil))
+        assert abs(oracle.max_dt(prob, qs[i], 0.35) - dts[i]) <= 1e-14 * dts[i]
+        ref = oracle.step(prob, qs[i], dts[i], n_stages=2)
+        e = nerr(b.get_state(i).cpu().numpy(), ref, mom_scale=True)
+        assert e.max() < 1e-12, (i, e)
+
 
 
 def test_graph_replay_equals_eager(hg):

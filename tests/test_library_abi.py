@@ -146,8 +146,8 @@ def test_viscosity_law_and_prandtl_limits(lib):
 
 
 def test_wide_stencil_limits(lib):
-    """The stencils of Remark 1: box and hexahedral grids with component-wise
-    reconstruction, not in batches; a symmetric end needs 3 cells."""
+    """The stencils of Remark 1: box and hexahedral grids and batches with
+    component-wise reconstruction; a symmetric end needs 3 cells."""
     from paper_1909_01580_amd import hgks
     cfg = hgks.hgks_default_config(8, 8, 8)
     assert cfg.stencil == 0
@@ -168,8 +168,7 @@ def test_wide_stencil_limits(lib):
     thin.bc[0] = hgks.BC["symmetric"]
     with pytest.raises(hgks.HGKSError):
         hgks.hgks_workspace_size(thin)
-    with pytest.raises(hgks.HGKSError):
-        hgks.hgks_batch_workspace_size([cfg])
+    assert hgks.hgks_batch_workspace_size([cfg]) > 0
 
 
 def test_moving_requires_periodic(lib):
@@ -190,3 +189,18 @@ def test_null_and_small_workspace(lib):
     st = lib.hgks_create(ctypes.byref(cfg), ctypes.c_void_p(256), 16, ctypes.byref(h))
     assert st == hgks.HGKS_ENOMEM
     assert b"workspace" in lib.hgks_last_error()
+
+
+def test_batch_stencil_family(lib):
+    """A batch takes the stencils of Sec. 2 or of Remark 1, one family for
+    all its grids: a batch that mixes them is refused."""
+    from paper_1909_01580_amd import hgks
+    cfgs = [hgks.hgks_default_config(12, 10, 9), hgks.hgks_default_config(8, 14, 11)]
+    n_s = hgks.hgks_batch_workspace_size(cfgs)
+    for c in cfgs:
+        c.stencil = hgks.STENCIL["S_prime"]
+    assert hgks.hgks_batch_workspace_size(cfgs) == n_s
+    cfgs[0].stencil = hgks.STENCIL["S"]
+    with pytest.raises(hgks.HGKSError) as e:
+        hgks.hgks_batch_workspace_size(cfgs)
+    assert e.value.status == hgks.HGKS_EINVAL
