@@ -201,7 +201,7 @@ def run_explosion(n, precision, t_end=0.1, cfl=0.35, t_early=0.02):
             "tot_early": tot_early}
 
 
-def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2, prandtl=1.0, stencil="S"):
+def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2, prandtl=1.0, **options):
     """48 independent periodic problems of uneven sizes (32..96 per axis,
     about 1.0e7 cells): autotuned persistent launches, a HIP graph of
     ``steps`` steps (per-grid dt reduction inside), timed by replay."""
@@ -215,7 +215,7 @@ def run_batched(steps, precision="mixed", tune=True, unbatched_steps=2, prandtl=
     grids = [{"n": p["n"], "length": p["length"], "mu": p["mu"], "prandtl": prandtl if p["mu"] > 0 else 1.0}
              for p in problems]
     cells = sum(int(np.prod(g["n"])) for g in grids)
-    b = hgks.Batch(grids, precision=precision, stencil=stencil)
+    b = hgks.Batch(grids, precision=precision, **options)
     for i, p in enumerate(problems):
         b.set_state(i, torch.tensor(p["state"], device="cuda:0"))
     b.sync()
@@ -796,6 +796,15 @@ def main():
             "value": bw["value"], "ms_per_step": bw["ms"] / bw["steps"],
             "conservation_rel_drift": bw["drift"],
             "max_norm_difference_vs_stencil_S": wdiff.tolist()}
+        bc = run_batched(args.batched_steps, "mixed", tune=False, unbatched_steps=0, characteristic=1)
+        cdiff = np.max([state_errors(a, r)["max_norm_per_variable"] for a, r in zip(bc["states"], bm["states"])],
+                       axis=0)
+        out["batched"]["characteristic"] = {
+            "workload": "the same batch reconstructed in characteristic variables for every grid (mixed), "
+                        "default launch shapes, the flux one workgroup per tile",
+            "value": bc["value"], "ms_per_step": bc["ms"] / bc["steps"],
+            "conservation_rel_drift": bc["drift"],
+            "max_norm_difference_vs_conservative": cdiff.tolist()}
     if not args.no_moving:
         v0, q0m = moving_initial(args.n)
         mv = {p: run_moving(args.n, args.moving_steps, 2, p, v0, q0m) for p in ("fp64", "mixed")}

@@ -101,9 +101,9 @@ typedef struct {
                              4): per face, Euler eigenvectors along the face
                              frame at the face centre (the normal and the two
                              tangential axes) at the mean of the two cell
-                             averages; box and hexahedral grids, not in
-                             batches.  0: the conservative variables
-                             component-wise (default)                        */
+                             averages; box and hexahedral grids and batches
+                             (one choice for every grid of a batch).  0: the
+                             conservative variables component-wise (default) */
   double mu_T0;           /* viscosity law mu (T / mu_T0)^mu_exponent with T =
                              p / rho of the interface equilibrium state, as in
                              the isotropic-turbulence test of Sec. 4 (0.76);  */
@@ -258,10 +258,13 @@ hgks_status hgks_sync(hgks_ctx ctx);
  *
  * cfgs[i] describes grid i (sizes, mu, and the viscosity law and Prandtl
  * number, mu_T0, mu_exponent, prandtl); every grid must be a uniform box
- * (moving = 0, component-wise reconstruction) with all axes periodic, and
- * gamma, weno_Gamma, weno_eps, tau_eps, tau_C, precision and the stencil
- * family (stencil: Sec. 2 or Remark 1) must equal those of cfgs[0];
- * otherwise HGKS_EINVAL and nothing is created.  The stream
+ * (moving = 0) with all axes periodic, and gamma, weno_Gamma, weno_eps,
+ * tau_eps, tau_C, precision, the stencil family (stencil: Sec. 2 or
+ * Remark 1) and the reconstruction variables (characteristic) must equal
+ * those of cfgs[0]; otherwise HGKS_EINVAL and nothing is created.  In
+ * characteristic variables the flux phase always runs one workgroup per
+ * tile (a flux workgroup count set by hgks_batch_set_launch is not used)
+ * and the coefficient arena is seven times as large.  The stream
  * of cfgs[0] is used; it must not be the legacy default stream when
  * hgks_batch_capture is used.  Grid i's state is [5][nz_i][ny_i][nx_i]. */
 hgks_status hgks_batch_workspace_size(const hgks_config* cfgs, int32_t n, size_t* bytes);

@@ -15,6 +15,7 @@
 #pragma once
 
 #include "box_kernels.h"
+#include "char_box.h"
 
 namespace hgks {
 
@@ -34,6 +35,9 @@ struct BatchGrid {
   unsigned nt_flux[3]; // flux tiles per direction
   int ct[3];           // cell tile shape; ct[0] = 0: 256 consecutive cells
   int nct[3];          // cell tiles per axis (box tiles)
+  unsigned t_char;     // characteristic variables: first tile of k_batch_char_recon
+  unsigned nt_char;    // its tiles (kCX x kCY x kCZ cells each)
+  unsigned ncx, ncy;   // its tiles along x and y
 };
 
 // Cell of lane `lane` in cell tile lt (counted from the grid's first):
@@ -62,6 +66,18 @@ __device__ __forceinline__ int batch_grid_of(const BatchGrid<TC>* __restrict__ B
     const int mid = (lo + hi + 1) >> 1;
     const unsigned first = FLUX ? B[mid].t_flux : B[mid].t_cell;
     if (first <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Grid owning tile t of the characteristic reconstruction.
+template <typename TC>
+__device__ __forceinline__ int batch_grid_of_char(const BatchGrid<TC>* __restrict__ B, int ng, unsigned t) {
+  int lo = 0, hi = ng - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (B[mid].t_char <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -97,8 +113,9 @@ __device__ __forceinline__ void for_tiles(unsigned ntiles, F&& body) {
 }
 
 // WIDE: the stencils of Remark 1 for every grid of the batch (the flux and
-// update do not depend on the stencil family).
-template <typename TC, bool LOOP, bool WIDE = false>
+// update do not depend on the stencil family).  COEF = false: the fallback
+// mask only (characteristic variables).
+template <typename TC, bool LOOP, bool WIDE = false, bool COEF = true>
 __global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles,
                                                         const double* __restrict__ q, TC* __restrict__ coef,
                                                         uint32_t* __restrict__ mask, TC margin, TC gm1) {
@@ -106,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_recon(const BatchGrid<TC>* __r
     const int g = batch_grid_of<TC, false>(B, ng, t);
     size_t idx;
     if (batch_cell(B[g], t - B[g].t_cell, threadIdx.x, idx))
-      recon_box_cell<TC, WIDE>(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin,
+      recon_box_cell<TC, WIDE, COEF>(q + B[g].q_off, coef + B[g].coef_off, mask + B[g].mask_off, B[g].G, B[g].P, margin,
                                gm1, B[g].N, idx);
   });
 }
@@ -123,12 +140,28 @@ __global__ void __launch_bounds__(kBlock) k_batch_posit(const BatchGrid<TC>* __r
   });
 }
 
+// Reconstruction in characteristic variables (Sec. 4) for every grid of the
+// batch: one workgroup per tile of each grid (the tile is staged in LDS
+// behind a workgroup barrier), the six per-face arrays of a grid following
+// its component-wise coefficient array.
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_batch_char_recon(const BatchGrid<TC>* __restrict__ B, int ng,
+                                                             unsigned ntiles, const double* __restrict__ q,
+                                                             TC* __restrict__ coef, double gamma) {
+  __shared__ double T[5][kCHalo];
+  const unsigned t = xcd_block(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const BatchGrid<TC>& b = B[batch_grid_of_char(B, ng, t)];
+  char_recon_tile(q + b.q_off, coef + b.coef_off + b.G.fs_stride, b.G, b.P, gamma, b.ncx, b.ncy, t - b.t_char, T);
+}
+
 // PR: the extended viscous model (viscosity law, Prandtl correction), per
 // grid through its gas parameters (trivial for grids that use neither).
 // FP64 stages the right cells in LDS as the single-grid flux does; in the
 // persistent form a wave's staged values are consumed before its next
-// tile's copies are issued.
-template <typename TC, bool LOOP, bool PR = false>
+// tile's copies are issued.  FS: the per-face arrays of the
+// characteristic reconstruction.
+template <typename TC, bool LOOP, bool PR = false, bool FS = false>
 __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
     k_batch_flux(const BatchGrid<TC>* __restrict__ B, int ng, unsigned ntiles, const TC* __restrict__ coef,
                  const uint32_t* __restrict__ mask, TC* __restrict__ face, const double* __restrict__ dt) {
@@ -141,12 +174,12 @@ __global__ void __launch_bounds__(kBlock) HGKS_FLUX_OCCUPANCY
     unsigned lt;
     const TC dtg = TC(dt[g]);
     const TC idtg = TC(1.0 / dt[g]);
-    const TC* cf = coef + b.coef_off;
+    const TC* cf = coef + b.coef_off + (FS ? b.G.fs_stride : 0);
     const uint32_t* mk = mask + b.mask_off;
     const unsigned nb[3] = {b.nt_flux[0], b.nt_flux[1], b.nt_flux[2]};
     int D;
     flux_block(t - b.t_flux, nb, D, lt);
-    flux_box_face<TC, PR, false, kStage>(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D, stage);
+    flux_box_face<TC, PR, FS, kStage>(cf, mk, face + b.face_off[D], b.G, b.gp, dtg, idtg, lt, D, stage);
   });
 }
 

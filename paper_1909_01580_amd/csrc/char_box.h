@@ -96,17 +96,15 @@ __device__ __forceinline__ void char_recon_tile_cell(const double (&T)[5][kCHalo
   }
 }
 
-// One workgroup per tile of the reconstruction box (tiles x-fastest, ntx x
-// nty x ntz of them); every lane reconstructs its cell for the six faces in
-// turn.  Lanes of cells beyond the box only help to stage the tile.
+// Tile b of the reconstruction box (tiles x-fastest, ntx x nty x ntz of
+// them) by the whole workgroup: the tile is staged in T, then every lane
+// reconstructs its cell for the six faces in turn.  Lanes of cells beyond
+// the box only help to stage the tile.
 template <typename TC>
-__global__ void __launch_bounds__(kBlock) k_char_recon_box(const double* __restrict__ q, TC* faces, BoxGrid G,
-                                                           WenoParams<TC> P, double gamma, unsigned ntx,
-                                                           unsigned nty, unsigned ntiles) {
+__device__ __forceinline__ void char_recon_tile(const double* __restrict__ q, TC* faces, const BoxGrid& G,
+                                                const WenoParams<TC>& P, double gamma, unsigned ntx, unsigned nty,
+                                                unsigned b, double (&T)[5][kCHalo]) {
   static_assert(kCX * kCY * kCZ == kBlock, "one lane per tile cell");
-  __shared__ double T[5][kCHalo];
-  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  if (b >= ntiles) return;
   const int o[3] = {(int)(b % ntx) * kCX, (int)((b / ntx) % nty) * kCY, (int)(b / (ntx * nty)) * kCZ};
   const size_t nx = G.n[0], nxy = nx * G.n[1], N = nxy * G.n[2];
   for (int t = threadIdx.x; t < kCHalo; t += kBlock) {
@@ -136,6 +134,17 @@ __global__ void __launch_bounds__(kBlock) k_char_recon_box(const double* __restr
 #pragma unroll 1
   for (int fs = 0; fs < 6; ++fs)
     char_recon_tile_cell(T, base, faces + (size_t)fs * G.fs_stride, P, gamma, idx, fs >> 1, fs & 1);
+}
+
+// One workgroup per tile.
+template <typename TC>
+__global__ void __launch_bounds__(kBlock) k_char_recon_box(const double* __restrict__ q, TC* faces, BoxGrid G,
+                                                           WenoParams<TC> P, double gamma, unsigned ntx,
+                                                           unsigned nty, unsigned ntiles) {
+  __shared__ double T[5][kCHalo];
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  if (b >= ntiles) return;
+  char_recon_tile(q, faces, G, P, gamma, ntx, nty, b, T);
 }
 
 }  // namespace hgks

@@ -964,6 +964,8 @@ struct hgks_batch_s {
   int band = kFluxBand;    // rows per band of the flux block order
   bool ext = false;  // some grid uses the viscosity law or the Prandtl correction
   bool wide = false;  // every grid reconstructs with the stencils of Remark 1
+  bool chr = false;   // every grid reconstructs in characteristic variables
+  unsigned tiles_char = 0;  // tiles of the characteristic reconstruction
   std::vector<BatchGrid<double>> gd;  // host copies of the descriptors
   std::vector<BatchGrid<float>> gf;
   std::vector<bool> grid_set, state_set;
@@ -989,11 +991,12 @@ hgks_status busable(hgks_batch b) {
 }
 
 bool batch_compatible(const hgks_config& a, const hgks_config& c) {
-  if (!valid_config(&c) || c.moving || c.characteristic) return false;
+  if (!valid_config(&c) || c.moving) return false;
   for (int d = 0; d < 3; ++d)
     if (c.bc[d] != HGKS_BC_PERIODIC) return false;
   return c.gamma == a.gamma && c.weno_Gamma == a.weno_Gamma && c.weno_eps == a.weno_eps &&
-         c.tau_eps == a.tau_eps && c.tau_C == a.tau_C && c.precision == a.precision && c.stencil == a.stencil;
+         c.tau_eps == a.tau_eps && c.tau_C == a.tau_C && c.precision == a.precision && c.stencil == a.stencil &&
+         c.characteristic == a.characteristic;
 }
 
 // Offsets of every arena and the per-grid descriptors (without the grid
@@ -1035,9 +1038,15 @@ unsigned max_cell_tiles(const int n[3]) {
 // band height (descriptors on the host; the caller uploads them).
 template <typename TC>
 void batch_tiles(std::vector<BatchGrid<TC>>& G, const int ct[3], int band, unsigned& tiles_cell,
-                 unsigned& tiles_flux) {
-  unsigned tc = 0, tf = 0;
+                 unsigned& tiles_flux, unsigned& tiles_char) {
+  unsigned tc = 0, tf = 0, th = 0;
   for (auto& g : G) {
+    // tiles of the characteristic reconstruction (fixed shape)
+    g.ncx = (unsigned)((g.G.n[0] + kCX - 1) / kCX);
+    g.ncy = (unsigned)((g.G.n[1] + kCY - 1) / kCY);
+    g.t_char = th;
+    g.nt_char = g.ncx * g.ncy * (unsigned)((g.G.n[2] + kCZ - 1) / kCZ);
+    th += g.nt_char;
     set_index_split(g.G, band);
     for (int d = 0; d < 3; ++d) g.ct[d] = ct[d];
     g.t_cell = tc;
@@ -1053,6 +1062,7 @@ void batch_tiles(std::vector<BatchGrid<TC>>& G, const int ct[3], int band, unsig
   }
   tiles_cell = tc;
   tiles_flux = tf;
+  tiles_char = th;
 }
 
 template <typename TC>
@@ -1081,7 +1091,11 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
     }
     tmax += max_cell_tiles(D.n);
     N += D.N;
-    C += coef_elems(D.N, sizeof(TC));
+    // characteristic variables: the component-wise array (fallback mask
+    // polynomials are not stored, but the layout is kept) and six per-face
+    // arrays after it
+    g.G.fs_stride = cfgs[i].characteristic ? coef_elems(D.N, sizeof(TC)) : 0;
+    C += coef_elems(D.N, sizeof(TC)) * (cfgs[i].characteristic ? 7 : 1);
     g.gp = gas_params<TC>(cfgs[i]);
   }
   size_t off = 0;
@@ -1092,11 +1106,12 @@ size_t batch_layout(const hgks_config* cfgs, int n, hgks_batch b, std::vector<Ba
   };
   {
     const int lin[3] = {0, 0, 0};
-    unsigned tc, tf;
-    batch_tiles(G, b ? b->ct : lin, b ? b->band : kFluxBand, tc, tf);
+    unsigned tc, tf, th;
+    batch_tiles(G, b ? b->ct : lin, b ? b->band : kFluxBand, tc, tf, th);
     if (b) {
       b->tiles_cell = tc;
       b->tiles_flux = tf;
+      b->tiles_char = th;
     }
   }
   const size_t desc = take(n * sizeof(BatchGrid<TC>));
@@ -1174,7 +1189,19 @@ hgks_status batch_stage(hgks_batch b, const double* qin, const double* dt_dev) {
   const TC gm1 = TC(b->base.gamma - 1.0);
   const bool rl = batch_loop(b, HGKS_PHASE_RECON), pl = batch_loop(b, HGKS_PHASE_FALLBACK);
   const unsigned rg = batch_wg(b, HGKS_PHASE_RECON, b->tiles_cell), pg = batch_wg(b, HGKS_PHASE_FALLBACK, b->tiles_cell);
-  if (b->wide) {
+  if (b->chr) {
+    // the component-wise pass for the fallback mask only, then the six
+    // per-face reconstructions in characteristic variables
+    if (rl)
+      hipLaunchKernelGGL((k_batch_recon<TC, true, false, false>), dim3(rg), dim3(kBlock), 0, b->stream, D, b->ng,
+                         b->tiles_cell, qin, coef, mask, margin, gm1);
+    else
+      hipLaunchKernelGGL((k_batch_recon<TC, false, false, false>), dim3(rg), dim3(kBlock), 0, b->stream, D, b->ng,
+                         b->tiles_cell, qin, coef, mask, margin, gm1);
+    HGKS_BATCH_LAUNCH_W(k_batch_posit, TC, false, pl, pg, b->stream, D, b->ng, b->tiles_cell, qin, mask, gm1);
+    hipLaunchKernelGGL((k_batch_char_recon<TC>), dim3(pad8(b->tiles_char)), dim3(kBlock), 0, b->stream, D, b->ng,
+                       b->tiles_char, qin, coef, b->base.gamma);
+  } else if (b->wide) {
     HGKS_BATCH_LAUNCH_W(k_batch_recon, TC, true, rl, rg, b->stream, D, b->ng, b->tiles_cell, qin, coef, mask, margin,
                         gm1);
     HGKS_BATCH_LAUNCH_W(k_batch_posit, TC, true, pl, pg, b->stream, D, b->ng, b->tiles_cell, qin, mask, gm1);
@@ -1186,9 +1213,13 @@ hgks_status batch_stage(hgks_batch b, const double* qin, const double* dt_dev) {
   {
     const bool loop = batch_loop(b, HGKS_PHASE_FLUX);
     const dim3 grid(batch_wg(b, HGKS_PHASE_FLUX, b->tiles_flux));
-    auto flux = loop ? (b->ext ? k_batch_flux<TC, true, true> : k_batch_flux<TC, true, false>)
-                     : (b->ext ? k_batch_flux<TC, false, true> : k_batch_flux<TC, false, false>);
-    hipLaunchKernelGGL(flux, grid, dim3(kBlock), 0, b->stream, D, b->ng, b->tiles_flux, (const TC*)coef,
+    // characteristic variables: one workgroup per tile only (the per-face
+    // instantiations are not built in the persistent form)
+    auto flux = b->chr ? (b->ext ? k_batch_flux<TC, false, true, true> : k_batch_flux<TC, false, false, true>)
+                : loop ? (b->ext ? k_batch_flux<TC, true, true> : k_batch_flux<TC, true, false>)
+                       : (b->ext ? k_batch_flux<TC, false, true> : k_batch_flux<TC, false, false>);
+    const dim3 fgrid = b->chr ? dim3(pad8(b->tiles_flux)) : grid;
+    hipLaunchKernelGGL(flux, fgrid, dim3(kBlock), 0, b->stream, D, b->ng, b->tiles_flux, (const TC*)coef,
                        (const uint32_t*)mask, (TC*)(b->ws + b->face), dt_dev);
   }
   return bcheck(b, hipGetLastError(), "batch stage");
@@ -1277,6 +1308,7 @@ hgks_status hgks_batch_create(const hgks_config* cfgs, int32_t n, void* ws, size
     batch_layout<double>(cfgs, n, b, b->gd);
   for (int i = 0; i < n; ++i) b->ext = b->ext || cfgs[i].prandtl != 1.0 || cfgs[i].mu_exponent != 0.0;
   b->wide = cfgs[0].stencil == 1;
+  b->chr = cfgs[0].characteristic == 1;
   b->grid_set.assign(n, false);
   b->state_set.assign(n, false);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, b->stream, (uint32_t*)(b->ws + b->status));
@@ -1384,10 +1416,10 @@ hgks_status hgks_batch_set_tiles(hgks_batch b, int32_t tile_x, int32_t tile_y, i
   b->band = flux_band;
   hgks_status s;
   if (b->mixed()) {
-    batch_tiles(b->gf, b->ct, b->band, b->tiles_cell, b->tiles_flux);
+    batch_tiles(b->gf, b->ct, b->band, b->tiles_cell, b->tiles_flux, b->tiles_char);
     s = batch_upload<float>(b);
   } else {
-    batch_tiles(b->gd, b->ct, b->band, b->tiles_cell, b->tiles_flux);
+    batch_tiles(b->gd, b->ct, b->band, b->tiles_cell, b->tiles_flux, b->tiles_char);
     s = batch_upload<double>(b);
   }
   if (s) return s;

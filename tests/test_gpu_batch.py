@@ -31,17 +31,25 @@ def states():
     return [smooth_state(g["n"], g["length"], 40 + i, mach=0.5) for i, g in enumerate(GRIDS)]
 
 
-def make_batch(hg, precision, qs, stencil="S"):
-    b = hg.Batch(GRIDS, precision=precision, stencil=stencil)
+# reconstruction options of the whole batch: the stencils of Sec. 2, those
+# of Remark 1, characteristic variables (Sec. 4)
+OPTIONS = {"S": {}, "S_prime": {"stencil": "S_prime"}, "characteristic": {"characteristic": True}}
+
+
+def make_batch(hg, precision, qs, option="S"):
+    kw = dict(OPTIONS[option])
+    if "characteristic" in kw:
+        kw["characteristic"] = 1
+    b = hg.Batch(GRIDS, precision=precision, **kw)
     for i, q in enumerate(qs):
         b.set_state(i, torch.tensor(q, device="cuda:0"))
     return b
 
 
-def run_single(hg, precision, qs, dts_per_step, stencil="S"):
+def run_single(hg, precision, qs, dts_per_step, option="S"):
     out = []
     for i, g in enumerate(GRIDS):
-        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision, stencil=stencil)
+        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision, **OPTIONS[option])
         ctx.set_uniform_grid((0, 0, 0), g["length"])
         ctx.set_state(torch.tensor(qs[i], device="cuda:0"))
         for dts in dts_per_step:
@@ -50,12 +58,12 @@ def run_single(hg, precision, qs, dts_per_step, stencil="S"):
     return out
 
 
-@pytest.mark.parametrize("stencil", ["S", "S_prime"])
+@pytest.mark.parametrize("option", list(OPTIONS))
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batch_equals_single_grids(hg, precision, stencil):
-    """stencil S_prime: the stencils of Remark 1 for every grid."""
+def test_batch_equals_single_grids(hg, precision, option):
+    """option: the reconstruction option of every grid (OPTIONS)."""
     qs = states()
-    b = make_batch(hg, precision, qs, stencil)
+    b = make_batch(hg, precision, qs, option)
     dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
     dts_per_step = []
     for _ in range(3):
@@ -64,7 +72,7 @@ def test_batch_equals_single_grids(hg, precision, stencil):
         dts_per_step.append(dt.cpu().numpy().copy())
         b.step(dt, 2)
     b.sync()
-    single = run_single(hg, precision, qs, dts_per_step, stencil)
+    single = run_single(hg, precision, qs, dts_per_step, option)
     # The batch and single-grid kernels run the same per-face and per-cell
     # code, but the compiler may fuse float operations differently in the
     # two kernels: FP64 agrees to round-off, mixed to float rounding.
@@ -75,21 +83,21 @@ def test_batch_equals_single_grids(hg, precision, stencil):
         assert err < tol, (i, err)
     # per-grid dt equals the single-grid reduction
     for i, g in enumerate(GRIDS):
-        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision, stencil=stencil)
+        ctx = hg.Context(g["n"], mu=g["mu"], precision=precision, **OPTIONS[option])
         ctx.set_uniform_grid((0, 0, 0), g["length"])
         ctx.set_state(torch.tensor(qs[i], device="cuda:0"))
         assert abs(ctx.max_dt(0.35) - dts_per_step[0][i]) <= 1e-15 * dts_per_step[0][i]
 
 
-@pytest.mark.parametrize("stencil", ["S", "S_prime"])
-def test_batch_step_against_oracle(hg, stencil):
+@pytest.mark.parametrize("option", list(OPTIONS))
+def test_batch_step_against_oracle(hg, option):
     """One two-stage FP64 step of every grid of the batch against the
     oracle's step of that grid (periodic, its own mu and time step),
     element by element: normalised max-norm error <= 1e-12."""
     import oracle
 
     qs = states()
-    b = make_batch(hg, "fp64", qs, stencil)
+    b = make_batch(hg, "fp64", qs, option)
     dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
     b.max_dt(0.35, dt)
     b.sync()
@@ -98,18 +106,18 @@ def test_batch_step_against_oracle(hg, stencil):
     b.sync()
     for i, g in enumerate(GRIDS):
         prob = oracle.uniform_problem(g["n"], (0.0, 0.0, 0.0), g["length"], bc=("periodic",) * 3,
-                                      params=oracle.Params(mu=g["mu"], stencil=stencil))
+                                      params=oracle.Params(mu=g["mu"], **OPTIONS[option]))
         assert abs(oracle.max_dt(prob, qs[i], 0.35) - dts[i]) <= 1e-14 * dts[i]
         ref = oracle.step(prob, qs[i], dts[i], n_stages=2)
         e = nerr(b.get_state(i).cpu().numpy(), ref, mom_scale=True)
         assert e.max() < 1e-12, (i, e)
 
 
-
-def test_graph_replay_equals_eager(hg):
+@pytest.mark.parametrize("option", list(OPTIONS))
+def test_graph_replay_equals_eager(hg, option):
     qs = states()
-    eager = make_batch(hg, "mixed", qs)
-    graph = make_batch(hg, "mixed", qs)
+    eager = make_batch(hg, "mixed", qs, option)
+    graph = make_batch(hg, "mixed", qs, option)
     graph.capture(0.35, 2, 2)
     dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
     for rep in range(3):
@@ -129,11 +137,12 @@ def test_graph_replay_equals_eager(hg):
             assert np.array_equal(a, e), (rep, i, np.abs(a - e).max())
 
 
+@pytest.mark.parametrize("option", list(OPTIONS))
 @pytest.mark.parametrize("wg", [8, 64, 1024])
-def test_persistent_workgroups_do_not_change_results(hg, wg):
+def test_persistent_workgroups_do_not_change_results(hg, wg, option):
     qs = states()
-    ref = make_batch(hg, "fp64", qs)
-    alt = make_batch(hg, "fp64", qs)
+    ref = make_batch(hg, "fp64", qs, option)
+    alt = make_batch(hg, "fp64", qs, option)
     for phase in range(5):
         alt.set_launch(phase, wg)
     dt = torch.empty(len(GRIDS), dtype=torch.float64, device="cuda:0")
